@@ -1,0 +1,180 @@
+/*
+ * dynbond.h -- C-ABI of libdynbond, the MI355X (gfx950) implementation of the
+ * data-parallel hot path of dynamic-bonding molecular dynamics
+ * (C. Svaneborg, "LAMMPS framework for dynamic bonding and an application
+ * modeling DNA", Comput. Phys. Commun. 2012).
+ *
+ * The library owns one simulation box per handle: beads with positions and
+ * velocities, a bond graph with per-direction bond types, per-bead angle and
+ * dihedral tables, a force field (WCA pairs, harmonic bonds, harmonic angles,
+ * cosine dihedrals, Langevin thermostat) and an ordered set of dynamic-bonding
+ * rules.  Every step runs on the GPU: a counting-sort cell list, a fused
+ * force + integrate kernel, and every `every` steps the bond create / break /
+ * kill / convert sweep followed by the angle/dihedral update.
+ *
+ * Conventions shared by all calls
+ *  - Bead ids are 0..N-1 and are the global ids used as random-number keys.
+ *    The library reorders beads internally and never exposes that order.
+ *  - Host pointers unless a call says otherwise (`on_device` = 1: the pointer
+ *    is device memory on the handle's device).  Inputs are copied in; outputs
+ *    are written into caller-allocated buffers of the documented size.
+ *  - Arrays of 3-vectors are row-major N x 3 doubles.
+ *  - Bead-type wildcard: DB_ANY (0).  Bond-type sets are 32-bit masks with bit
+ *    t set for bond type t (types 1..31); DB_ALL_BONDTYPES matches any type.
+ *  - Rule order is call order: when several rules apply to one bead pair the
+ *    last one wins (section 2; appendix steps 2-3).
+ *  - Every call returns DB_OK (0) or a negative DB_E* code; db_last_error()
+ *    gives a message.  Device-side errors (table overflow, non-finite state)
+ *    are latched on the device and reported by the next db_step /
+ *    db_sweep_now; after one the state is undefined and must be reloaded.
+ *  - A handle is not thread-safe and issues all work on its own stream.
+ */
+#ifndef DYNBOND_H
+#define DYNBOND_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DB_OK 0
+#define DB_EINVAL (-1)      /* bad argument or rule */
+#define DB_ECAPACITY (-2)   /* a per-bead table overflowed */
+#define DB_ENONFINITE (-3)  /* non-finite or escaping position */
+#define DB_EDEVICE (-4)     /* HIP runtime error */
+#define DB_ESTATE (-5)      /* call out of order */
+
+#define DB_ANY 0
+#define DB_ALL_BONDTYPES 0xFFFFFFFFu
+
+#define DB_FP64 0           /* all force arithmetic in double */
+#define DB_MIXED 1          /* pair and bonded force arithmetic in float; positions,
+                               differences, accumulation, integration in double */
+
+/* per-bead capacities of the bond, angle and dihedral tables */
+#define DB_MAX_BONDS_PER_BEAD 4
+#define DB_MAX_ANGLES_PER_BEAD 12
+#define DB_MAX_DIHEDRALS_PER_BEAD 16
+
+typedef struct db_ctx db_ctx;
+
+typedef struct {
+    /* last sweep, then cumulative (appendix step 9 statistics) */
+    int64_t bonds_created, bonds_broken, bonds_killed, bonds_converted;
+    int64_t angles_created, angles_removed, dihedrals_created, dihedrals_removed;
+    int64_t cum_bonds_created, cum_bonds_broken, cum_bonds_killed, cum_bonds_converted;
+    int64_t cum_angles_created, cum_angles_removed, cum_dihedrals_created, cum_dihedrals_removed;
+    int64_t sweeps;          /* sweeps performed */
+    int64_t steps;           /* current step counter */
+    int64_t rebuilds;        /* cell-list rebuilds */
+    int64_t rollbacks;       /* blocks re-run because beads moved further than the skin */
+} db_stats;
+
+/* ---- lifecycle ---------------------------------------------------------------- */
+
+/* Create a handle for n_beads beads in a periodic cube of edge box_L.  seed keys
+ * every random number (Langevin noise and bond acceptance).  precision: DB_FP64
+ * or DB_MIXED.  hip_stream: a hipStream_t (NULL = the null stream).  Allocates no
+ * device memory yet. */
+int db_create(db_ctx** out, int32_t n_beads, double box_L, uint64_t seed, int precision, void* hip_stream);
+/* Device bytes the handle needs; db_bind_workspace may hand it a caller-owned
+ * buffer (>= that size, 256-byte aligned) before db_set_state; otherwise the
+ * library allocates on first use. */
+int db_workspace_bytes(const db_ctx* ctx, size_t* bytes);
+int db_bind_workspace(db_ctx* ctx, void* dev_ptr, size_t bytes);
+int db_destroy(db_ctx* ctx);
+const char* db_last_error(const db_ctx* ctx);
+
+/* ---- system / topology (section 2: directional bonds; appendix: init) --------- */
+
+/* x: positions in [0, box_L); v: velocities (the leapfrog half-step velocity that
+ * enters the next force evaluation; NULL = zero); type: bead types 1..31. */
+int db_set_state(db_ctx* ctx, const double* x, const double* v, const int32_t* type, int on_device);
+/* reactive group of the bonding rules (section 2, `beadgroup`): flag per bead */
+int db_set_reactive(db_ctx* ctx, const uint8_t* flag);
+/* nb bonds: ij[2k], ij[2k+1] bead ids; t_ij = type stored by the first bead,
+ * t_ji = type stored by the second (equal for symmetric bonds).  Replaces the
+ * bond graph and clears angles and dihedrals. */
+int db_set_bonds(db_ctx* ctx, int64_t nb, const int32_t* ij, const int32_t* t_ij, const int32_t* t_ji);
+/* explicit angle (a,b,c centre b) and dihedral (a,b,c,d) lists with types */
+int db_set_angles(db_ctx* ctx, int64_t na, const int32_t* abc, const int32_t* type);
+int db_set_dihedrals(db_ctx* ctx, int64_t nd, const int32_t* abcd, const int32_t* type);
+/* replace the angle and dihedral lists by every path of the current bond graph
+ * that matches the pattern rules (section 2 matching, applied with every bond
+ * taken as new) */
+int db_generate_angles_dihedrals(db_ctx* ctx);
+
+/* ---- force field and thermostat (section 3 potentials) ------------------------- */
+
+/* WCA U = 4 eps[(s/r)^12 - (s/r)^6] + eps for r < rc.  exclude_depth 1 removes
+ * bonded pairs, 2 also pairs two bonds apart. */
+int db_pair_wca(db_ctx* ctx, double eps, double sigma, double rc, int exclude_depth);
+/* U = K (r - r0)^2; a bead feels the potential of the type it stores */
+int db_bond_harmonic(db_ctx* ctx, int32_t type, double K, double r0);
+/* U = K (theta - theta0)^2 */
+int db_angle_harmonic(db_ctx* ctx, int32_t type, double K, double theta0);
+/* U = K [1 - cos(phi - phi0)], phi the signed dihedral with cis = 0 */
+int db_dihedral_cosine(db_ctx* ctx, int32_t type, double K, double phi0);
+/* Langevin force -gamma v + sqrt(24 gamma T/dt)(u - 1/2) per component, u uniform;
+ * gamma = 0 gives NVE.  dt is the time step. */
+int db_langevin(db_ctx* ctx, double T, double gamma, double dt);
+/* T(step) = T0 + (T1 - T0) min(step, n_steps) / n_steps */
+int db_temperature_ramp(db_ctx* ctx, double T0, double T1, int64_t n_steps);
+
+/* ---- dynamic-bonding rules (Fig. 1 syntax, section 2 semantics) ---------------- */
+
+/* sweep every `every` steps (0 = never); paircheck13/14 admit beads two / three
+ * bonds apart as creation partners */
+int db_sweep_every(db_ctx* ctx, int32_t every, int paircheck13, int paircheck14);
+/* createbond: symmetric bond of type bt between bead types bead1, bead2 when
+ * r < r_max, with probability p */
+int db_bond_create(db_ctx* ctx, int32_t bt, int32_t bead1, int32_t bead2, double r_max, double p);
+/* createdirbond: the bead of type bead1 stores bt1, the bead of type bead2 stores bt2 */
+int db_bond_create_dir(db_ctx* ctx, int32_t bt1, int32_t bt2, int32_t bead1, int32_t bead2, double r_max, double p);
+/* breakbond: a symmetric bond of type bt longer than r_min breaks with probability p */
+int db_bond_break(db_ctx* ctx, int32_t bt, double r_min, double p);
+/* killbond: every symmetric bond of type bt longer than r_min is removed */
+int db_bond_kill(db_ctx* ctx, int32_t bt, double r_min);
+/* convertbond: a symmetric bond of type bt_from longer than r_min becomes bt_to
+ * with probability p (r_min = 0: any length, as in Fig. 1) */
+int db_bond_convert(db_ctx* ctx, int32_t bt_from, int32_t bt_to, double r_min, double p);
+/* maxbond: a bead of type bead_type (DB_ANY: any) holds at most max bonds it stores as bt */
+int db_max_bonds(db_ctx* ctx, int32_t bt, int32_t bead_type, int32_t max);
+/* createangle: bead types bead[0..2] (DB_ANY wildcard), bond-type sets
+ * bondmask[0] for the type the centre stores towards the first bead and
+ * bondmask[1] towards the third; tested on ABC then CBA */
+int db_angle_pattern(db_ctx* ctx, int32_t atype, const int32_t bead[3], const uint32_t bondmask[2]);
+/* createdihedral: bead[0..3]; bondmask[0] for t(B->A), bondmask[1] for t(C->B) or
+ * t(B->C), bondmask[2] for t(C->D); tested on ABCD then DCBA */
+int db_dihedral_pattern(db_ctx* ctx, int32_t dtype, const int32_t bead[4], const uint32_t bondmask[3]);
+
+/* ---- run and observe ----------------------------------------------------------- */
+
+/* advance n steps (sweep at every step k with k % every == 0, before the force) */
+int db_step(db_ctx* ctx, int64_t n);
+/* the sweep of the current step, now (it is then not repeated by db_step) */
+int db_sweep_now(db_ctx* ctx);
+/* conservative forces at the current positions, N x 3 */
+int db_forces(db_ctx* ctx, double* f, int on_device);
+/* out = {kinetic (full-step velocities), U_pair, U_bond, U_angle, U_dihedral, virial} */
+int db_energy(db_ctx* ctx, double out[6]);
+int db_get_state(db_ctx* ctx, double* x, double* v, int on_device);
+int db_topology_counts(db_ctx* ctx, int64_t* nb, int64_t* na, int64_t* nd);
+/* canonical, sorted lists: bonds i<j; angles a<c; dihedrals a<d (path reversed if needed) */
+int db_get_bonds(db_ctx* ctx, int32_t* ij, int32_t* t_ij, int32_t* t_ji);
+int db_get_angles(db_ctx* ctx, int32_t* abc, int32_t* type);
+int db_get_dihedrals(db_ctx* ctx, int32_t* abcd, int32_t* type);
+int db_get_stats(db_ctx* ctx, db_stats* out);
+/* current step counter; db_set_step also allows the sweep of that step again */
+int db_set_step(db_ctx* ctx, int64_t step);
+/* enable (1) / disable (0) HIP-event timing of every launch of the fused step
+ * kernel on the handle's stream */
+int db_profile(db_ctx* ctx, int enable);
+/* mean GPU time per launch (microseconds) of the fused step kernel over the
+ * launches timed since the last call, and their number; resets the tally */
+int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1128 @@
+// Host side of libdynbond: the C-ABI entry points, argument validation, the
+// device memory arena, host <-> device transfer of the system, and the step
+// scheduler.
+//
+// Scheduling.  Time is advanced in blocks.  A block starts with a fresh cell
+// list (and, every `permute_every` blocks, a reordering of all per-bead state
+// into cell order), runs the sweep if the block's first step is a sweep step,
+// and then runs up to `rebuild_interval` fused step kernels without rebuilding.
+// Each step kernel records the largest speed; after the block the host bounds
+// the largest displacement by the sum of dt * max speed.  If that bound exceeds
+// the skin (cell edge minus pair cutoff) some pair could have been missed, so
+// the block's positions and velocities are restored and the block is re-run
+// with a fresh cell list at every step.  The interval adapts to the speeds seen.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "db_device.h"
+
+using namespace db;
+
+namespace {
+
+const int kMaxBlock = 64;
+const double kSkinDefault = 0.3;
+
+struct Pinned {
+    int err;
+    int pad;
+    float vmax2[kMaxBlock];
+    unsigned long long stats[8];
+    double energy[6];
+    int total[4];
+};
+
+struct HostSys {
+    std::vector<double> x, v;
+    std::vector<int32_t> type;
+    std::vector<uint8_t> reactive;
+    std::vector<int32_t> bonds;   // 4 per bond: i, j, t_ij, t_ji
+    std::vector<int32_t> ang;     // 4 per angle: type, a, b, c (a < c)
+    std::vector<int32_t> dih;     // 5 per dihedral: type, a, b, c, d (a < d)
+};
+
+}  // namespace
+
+struct db_host_ext {
+    HostSys h;
+    bool host_valid = true;   // host copies reflect the current state
+    bool dev_valid = false;   // device holds the current state
+    int dev_error = 0;        // latched device error code
+    Pinned* pin = nullptr;
+    int* tmp_n1 = nullptr;    // n + 1 ints
+};
+
+static db_host_ext& ext(db_ctx* c) { return *c->hx; }
+
+static int fail(db_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+static int fail(db_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail((c), DB_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------------------------
+// arena layout
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int ncell_cap(int n) { return 2 * n + 64; }
+
+static int blocksum_ints(int count) {
+    int tot = 2;
+    int t = count;
+    while (t > 1) {
+        t = (t + 1023) / 1024;
+        tot += t + 1;
+    }
+    return tot + 64;
+}
+
+struct Layout {
+    size_t off[64];
+    int k = 0;
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t o = total;
+        off[k++] = o;
+        total = align256(total + (bytes ? bytes : 1));
+        return o;
+    }
+};
+
+static size_t layout(db_ctx* c, bool assign) {
+    const size_t n = (size_t)std::max(c->n, 1);
+    const size_t nc = (size_t)ncell_cap(c->n);
+    Layout L;
+    auto put = [&](auto*& p, size_t bytes) {
+        size_t o = L.add(bytes);
+        if (assign) p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(c->arena + o);
+    };
+    for (int b = 0; b < 2; ++b) {
+        Bank& B = c->bank[b];
+        put(B.x, 32 * n);
+        put(B.v, 24 * n);
+        put(B.nb, n);
+        put(B.bp, 4 * DB_MAXB * n);
+        put(B.bt, DB_MAXB * n);
+        put(B.na, n);
+        put(B.ang, 16 * DB_MAXA * n);
+        put(B.nd, n);
+        put(B.dih, 16 * DB_MAXD * n);
+        put(B.dt, DB_MAXD * n);
+    }
+    put(c->xnext, 32 * n);
+    put(c->xsave, 32 * n);
+    put(c->vsave, 24 * n);
+    SweepBuf& S = c->sw;
+    put(S.nomC, 4 * n);
+    put(S.ruleC, n);
+    put(S.btC, n);
+    put(S.nomK, 4 * n);
+    put(S.ruleK, n);
+    put(S.rmcnt, n);
+    put(S.rmlist, 4 * DB_MAXB * n);
+    put(S.conv, n);
+    put(S.newp, 4 * n);
+    put(S.stats, 8 * 8);
+    put(c->cells.cnt, 4 * nc);
+    put(c->cells.start, 4 * (nc + 1));
+    put(c->cells.list, 4 * n);
+    put(c->cells.cellid, 4 * n);
+    put(c->cells.blocksum, 4 * (size_t)blocksum_ints((int)std::max(n, nc) + 1));
+    put(c->slot_of_gid, 4 * n);
+    put(c->err_d, 64);
+    put(c->vmax2, 4 * kMaxBlock);
+    put(c->red, 8 * 6 * ((n + DB_BLOCK - 1) / DB_BLOCK + 1));
+    put(c->dp, sizeof(Params));
+    int* t1 = nullptr;
+    put(t1, 4 * (n + 1));
+    if (assign) ext(c).tmp_n1 = t1;
+    return L.total;
+}
+
+static int ensure_memory(db_ctx* c) {
+    if (c->allocated) return DB_OK;
+    size_t need = layout(c, false);
+    if (!c->arena) {
+        void* p = nullptr;
+        HIPCHK(c, hipMalloc(&p, need));
+        c->arena = (char*)p;
+        c->arena_bytes = need;
+        c->arena_owned = true;
+    }
+    layout(c, true);
+    if (!ext(c).pin) {
+        void* p = nullptr;
+        HIPCHK(c, hipHostMalloc(&p, sizeof(Pinned), hipHostMallocDefault));
+        ext(c).pin = (Pinned*)p;
+        memset(p, 0, sizeof(Pinned));
+    }
+    // zero the counters that kernels assume start at zero
+    launch_fill_int(c->cells.cnt, 0, (size_t)ncell_cap(c->n), c->stream);
+    launch_fill_int(c->err_d, 0, 16, c->stream);
+    c->allocated = true;
+    HIPCHK(c, hipGetLastError());
+    return DB_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// parameters and the cell grid
+
+static void compute_grid(db_ctx* c) {
+    Params& P = c->hp;
+    double rc = P.have_pair ? std::sqrt(P.rc2) : 0.0;
+    double rcr = std::sqrt(std::max(P.rmax2_create, 0.0));
+    double amin = std::max(rc + c->skin, rcr);
+    if (!(amin > 0)) amin = c->L;
+    int nc = (int)std::floor(c->L / (amin * (1.0 + 1e-9)));
+    if (nc < 1) nc = 1;
+    while ((long long)nc * nc * nc > ncell_cap(c->n) && nc > 1) --nc;
+    P.nc = nc;
+    P.ncell = nc * nc * nc;
+    P.cell_scale = nc / c->L;
+    if (nc >= 3) {
+        P.noff = 3;
+        P.off[0] = -1; P.off[1] = 0; P.off[2] = 1;
+    } else if (nc == 2) {
+        P.noff = 2;
+        P.off[0] = 0; P.off[1] = 1; P.off[2] = 0;
+    } else {
+        P.noff = 1;
+        P.off[0] = 0; P.off[1] = 0; P.off[2] = 0;
+    }
+}
+
+static double skin_of(const db_ctx* c) {
+    if (c->hp.nc < 3) return INFINITY;   // every bead is visited
+    double rc = c->hp.have_pair ? std::sqrt(c->hp.rc2) : 0.0;
+    return c->L / c->hp.nc - rc;
+}
+
+static int upload_params(db_ctx* c) {
+    if (!c->params_dirty) return DB_OK;
+    compute_grid(c);
+    c->hp.n = c->n;
+    HIPCHK(c, hipMemcpyAsync(c->dp, &c->hp, sizeof(Params), hipMemcpyHostToDevice, c->stream));
+    c->params_dirty = false;
+    return DB_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// host <-> device transfer of the whole system (slot = bead id after an upload)
+
+static int upload_system(db_ctx* c) {
+    db_host_ext& X = ext(c);
+    HostSys& h = X.h;
+    const int n = c->n;
+    int rc = ensure_memory(c);
+    if (rc) return rc;
+    std::vector<double4> x4(n);
+    std::vector<double> v(3 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        x4[i].x = h.x[3 * i];
+        x4[i].y = h.x[3 * i + 1];
+        x4[i].z = h.x[3 * i + 2];
+        x4[i].w = pack_meta(i, h.type[i], h.reactive[i]);
+        v[i] = h.v[3 * i];
+        v[n + i] = h.v[3 * i + 1];
+        v[2 * (size_t)n + i] = h.v[3 * i + 2];
+    }
+    std::vector<uint8_t> nb(n, 0), na(n, 0), nd(n, 0);
+    std::vector<int> bp((size_t)DB_MAXB * n, -1);
+    std::vector<int8_t> bt((size_t)DB_MAXB * n, 0);
+    std::vector<int4> ang((size_t)DB_MAXA * n);
+    std::vector<int4> dih((size_t)DB_MAXD * n);
+    std::vector<uint8_t> dt((size_t)DB_MAXD * n, 0);
+    const size_t nbonds = h.bonds.size() / 4;
+    for (size_t k = 0; k < nbonds; ++k) {
+        int i = h.bonds[4 * k], j = h.bonds[4 * k + 1];
+        if (nb[i] >= DB_MAXB || nb[j] >= DB_MAXB)
+            return fail(c, DB_ECAPACITY, "bead %d or %d has more than %d bonds", i, j, DB_MAXB);
+        bp[(size_t)nb[i] * n + i] = j;
+        bt[(size_t)nb[i] * n + i] = (int8_t)h.bonds[4 * k + 2];
+        ++nb[i];
+        bp[(size_t)nb[j] * n + j] = i;
+        bt[(size_t)nb[j] * n + j] = (int8_t)h.bonds[4 * k + 3];
+        ++nb[j];
+    }
+    const size_t nang = h.ang.size() / 4;
+    for (size_t k = 0; k < nang; ++k) {
+        int t = h.ang[4 * k], a = h.ang[4 * k + 1], b = h.ang[4 * k + 2], cc = h.ang[4 * k + 3];
+        int mem[3] = {a, b, cc};
+        for (int m = 0; m < 3; ++m) {
+            int s = mem[m];
+            if (na[s] >= DB_MAXA) return fail(c, DB_ECAPACITY, "bead %d is in more than %d angles", s, DB_MAXA);
+            ang[(size_t)na[s] * n + s] = make_int4(a, b, cc, t);
+            ++na[s];
+        }
+    }
+    const size_t ndih = h.dih.size() / 5;
+    for (size_t k = 0; k < ndih; ++k) {
+        int t = h.dih[5 * k];
+        int mem[4] = {h.dih[5 * k + 1], h.dih[5 * k + 2], h.dih[5 * k + 3], h.dih[5 * k + 4]};
+        for (int m = 0; m < 4; ++m) {
+            int s = mem[m];
+            if (nd[s] >= DB_MAXD) return fail(c, DB_ECAPACITY, "bead %d is in more than %d dihedrals", s, DB_MAXD);
+            dih[(size_t)nd[s] * n + s] = make_int4(mem[0], mem[1], mem[2], mem[3]);
+            dt[(size_t)nd[s] * n + s] = (uint8_t)t;
+            ++nd[s];
+        }
+    }
+    c->cur = 0;
+    Bank& B = c->bank[0];
+    hipStream_t s = c->stream;
+    if (n == 0) {
+        X.dev_valid = true;
+        X.dev_error = 0;
+        return DB_OK;
+    }
+    HIPCHK(c, hipMemcpyAsync(B.x, x4.data(), 32 * (size_t)n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.v, v.data(), 24 * (size_t)n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.nb, nb.data(), n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.bp, bp.data(), 4 * (size_t)DB_MAXB * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.bt, bt.data(), (size_t)DB_MAXB * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.na, na.data(), n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.ang, ang.data(), 16 * (size_t)DB_MAXA * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.nd, nd.data(), n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.dih, dih.data(), 16 * (size_t)DB_MAXD * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(B.dt, dt.data(), (size_t)DB_MAXD * n, hipMemcpyHostToDevice, s));
+    std::vector<int> ident(n);
+    std::iota(ident.begin(), ident.end(), 0);
+    HIPCHK(c, hipMemcpyAsync(c->slot_of_gid, ident.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    X.dev_valid = true;
+    X.dev_error = 0;
+    launch_fill_int(c->err_d, 0, 16, s);
+    return DB_OK;
+}
+
+namespace db {
+void launch_owned_offsets(db_ctx* c, int kind, int* buf);
+void launch_write_owned(db_ctx* c, int kind, const int* off, int32_t* tup, int32_t* typ);
+}  // namespace db
+
+__global__ void k_gather_state(int n, Bank B, double* __restrict__ xo, double* __restrict__ vo) {
+    int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (s >= n) return;
+    double4 x = B.x[s];
+    int g = meta_gid(x);
+    if (xo) {
+        xo[3 * (size_t)g] = x.x;
+        xo[3 * (size_t)g + 1] = x.y;
+        xo[3 * (size_t)g + 2] = x.z;
+    }
+    if (vo) {
+        vo[3 * (size_t)g] = B.v[s];
+        vo[3 * (size_t)g + 1] = B.v[n + s];
+        vo[3 * (size_t)g + 2] = B.v[2 * (size_t)n + s];
+    }
+}
+
+// scratch for gathers: the per-bead storage of the inactive bank (free between reorders)
+static char* scratch(db_ctx* c, size_t bytes) {
+    Bank& O = c->bank[1 - c->cur];
+    size_t avail = (size_t)((char*)O.nd - (char*)O.ang);
+    (void)avail;
+    (void)bytes;
+    return (char*)O.ang;
+}
+static size_t scratch_bytes(db_ctx* c) {
+    Bank& O = c->bank[1 - c->cur];
+    return (size_t)((char*)O.nd - (char*)O.ang);
+}
+
+static int read_owned(db_ctx* c, int kind, std::vector<int32_t>& tup, std::vector<int32_t>& typ, int64_t* count) {
+    const int n = c->n;
+    const int width = kind == 0 ? 2 : (kind == 1 ? 3 : 4);
+    const int twidth = kind == 0 ? 2 : 1;
+    if (n == 0) {
+        *count = 0;
+        tup.clear();
+        typ.clear();
+        return DB_OK;
+    }
+    int* off = ext(c).tmp_n1;
+    launch_owned_offsets(c, kind, off);
+    HIPCHK(c, hipMemcpyAsync(&ext(c).pin->total[0], off + n, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t m = ext(c).pin->total[0];
+    *count = m;
+    size_t need = (size_t)m * 4 * (width + twidth);
+    if (need > scratch_bytes(c)) return fail(c, DB_ECAPACITY, "topology list larger than the gather scratch");
+    int32_t* dtup = (int32_t*)scratch(c, need);
+    int32_t* dtyp = dtup + (size_t)m * width;
+    launch_write_owned(c, kind, off, dtup, dtyp);
+    tup.resize((size_t)m * width);
+    typ.resize((size_t)m * twidth);
+    if (m) {
+        HIPCHK(c, hipMemcpyAsync(tup.data(), dtup, 4 * (size_t)m * width, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(typ.data(), dtyp, 4 * (size_t)m * twidth, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    return DB_OK;
+}
+
+// device -> host copies in bead-id order, canonical and sorted topology
+static int download_system(db_ctx* c) {
+    db_host_ext& X = ext(c);
+    if (X.host_valid || !X.dev_valid) return DB_OK;
+    const int n = c->n;
+    HostSys& h = X.h;
+    if (n > 0) {
+        double* d = (double*)scratch(c, 48 * (size_t)n);
+        hipLaunchKernelGGL(k_gather_state, dim3((n + DB_BLOCK - 1) / DB_BLOCK), dim3(DB_BLOCK), 0, c->stream, n,
+                           c->bank[c->cur], d, d + 3 * (size_t)n);
+        HIPCHK(c, hipMemcpyAsync(h.x.data(), d, 24 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(h.v.data(), d + 3 * (size_t)n, 24 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    std::vector<int32_t> tup, typ;
+    int64_t m;
+    int rc = read_owned(c, 0, tup, typ, &m);
+    if (rc) return rc;
+    h.bonds.resize(4 * (size_t)m);
+    for (int64_t k = 0; k < m; ++k) {
+        h.bonds[4 * k] = tup[2 * k];
+        h.bonds[4 * k + 1] = tup[2 * k + 1];
+        h.bonds[4 * k + 2] = typ[2 * k];
+        h.bonds[4 * k + 3] = typ[2 * k + 1];
+    }
+    rc = read_owned(c, 1, tup, typ, &m);
+    if (rc) return rc;
+    h.ang.resize(4 * (size_t)m);
+    for (int64_t k = 0; k < m; ++k) {
+        h.ang[4 * k] = typ[k];
+        for (int q = 0; q < 3; ++q) h.ang[4 * k + 1 + q] = tup[3 * k + q];
+    }
+    rc = read_owned(c, 2, tup, typ, &m);
+    if (rc) return rc;
+    h.dih.resize(5 * (size_t)m);
+    for (int64_t k = 0; k < m; ++k) {
+        h.dih[5 * k] = typ[k];
+        for (int q = 0; q < 4; ++q) h.dih[5 * k + 1 + q] = tup[4 * k + q];
+    }
+    X.host_valid = true;
+    return DB_OK;
+}
+
+// make the device state current (upload once after host-side edits)
+static int ready(db_ctx* c) {
+    db_host_ext& X = ext(c);
+    if (!c->have_state) return fail(c, DB_ESTATE, "db_set_state has not been called");
+    if (X.dev_error) return fail(c, X.dev_error, "a previous device error left the state undefined: %s", c->err.c_str());
+    int rc = ensure_memory(c);
+    if (rc) return rc;
+    rc = upload_params(c);
+    if (rc) return rc;
+    if (!X.dev_valid) {
+        rc = upload_system(c);
+        if (rc) return rc;
+    }
+    return DB_OK;
+}
+
+// host-side edits start from a current host copy
+static int editable(db_ctx* c) {
+    db_host_ext& X = ext(c);
+    if (X.dev_valid && !X.host_valid && !X.dev_error) {
+        int rc = download_system(c);
+        if (rc) return rc;
+    }
+    X.dev_valid = false;
+    return DB_OK;
+}
+
+static int check_device_error(db_ctx* c) {
+    db_host_ext& X = ext(c);
+    int e = X.pin->err;
+    if (!e) return DB_OK;
+    int code = (e & (ERR_BOND_CAP | ERR_ANGLE_CAP | ERR_DIH_CAP)) ? DB_ECAPACITY : DB_ENONFINITE;
+    X.dev_error = code;
+    return fail(c, code, "device reported %s%s%s%s",
+                (e & ERR_BOND_CAP) ? "bond-table overflow " : "", (e & ERR_ANGLE_CAP) ? "angle-table overflow " : "",
+                (e & ERR_DIH_CAP) ? "dihedral-table overflow " : "",
+                (e & ERR_NONFINITE) ? "non-finite or escaping position" : "");
+}
+
+static void rebuild(db_ctx* c, bool permute) {
+    launch_build_cells(c);
+    if (permute) launch_permute(c);
+    c->rebuilds++;
+}
+
+// rows of src: tuple then types (typ_first = 0) or types then tuple (typ_first = 1);
+// written sorted by tuple, then type
+template <int W, int TW>
+static void sorted_copy(const std::vector<int32_t>& src, int32_t* tup, int32_t* typ, int typ_first) {
+    // src rows: [typ_first ? type, tuple : tuple, types]
+    const size_t rows = src.size() / (W + TW);
+    std::vector<size_t> idx(rows);
+    std::iota(idx.begin(), idx.end(), 0);
+    auto key = [&](size_t r, int q) { return src[r * (W + TW) + (typ_first ? TW : 0) + q]; };
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        for (int q = 0; q < W; ++q)
+            if (key(a, q) != key(b, q)) return key(a, q) < key(b, q);
+        for (int q = 0; q < TW; ++q) {
+            int ta = src[a * (W + TW) + (typ_first ? q : W + q)], tb = src[b * (W + TW) + (typ_first ? q : W + q)];
+            if (ta != tb) return ta < tb;
+        }
+        return false;
+    });
+    for (size_t k = 0; k < rows; ++k) {
+        size_t r = idx[k];
+        for (int q = 0; q < W; ++q) tup[k * W + q] = key(r, q);
+        for (int q = 0; q < TW; ++q) typ[k * TW + q] = src[r * (W + TW) + (typ_first ? q : W + q)];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, void* stream) {
+    if (!out) return DB_EINVAL;
+    *out = nullptr;
+    if (n < 0 || !(L > 0) || !std::isfinite(L)) return DB_EINVAL;
+    if (precision != DB_FP64 && precision != DB_MIXED) return DB_EINVAL;
+    db_ctx* c = new db_ctx();
+    c->hx = new db_host_ext();
+    c->n = n;
+    c->L = L;
+    c->seed = seed;
+    c->precision = precision;
+    c->stream = (hipStream_t)stream;
+    memset(&c->hp, 0, sizeof(Params));
+    Params& P = c->hp;
+    P.n = n;
+    P.L = L;
+    P.hL = 0.5 * L;
+    P.seed_lo = (uint32_t)seed;
+    P.seed_hi = (uint32_t)(seed >> 32);
+    P.T0 = P.T1 = 1.0;
+    P.dt = 0.005;
+    P.excl_depth = 1;
+    c->params_dirty = true;
+    c->skin = kSkinDefault;
+    c->swept_step = -1;
+    c->rebuild_interval = 8;
+    c->permute_every = 1;
+    c->vmax_est = 0;
+    HostSys& h = c->hx->h;
+    h.x.assign(3 * (size_t)n, 0.0);
+    h.v.assign(3 * (size_t)n, 0.0);
+    h.type.assign(n, 1);
+    h.reactive.assign(n, 1);
+    *out = c;
+    return DB_OK;
+}
+
+int db_workspace_bytes(const db_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return DB_EINVAL;
+    *bytes = layout(const_cast<db_ctx*>(c), false);
+    return DB_OK;
+}
+
+int db_bind_workspace(db_ctx* c, void* p, size_t bytes) {
+    if (!c) return DB_EINVAL;
+    if (c->allocated) return fail(c, DB_ESTATE, "workspace already allocated");
+    size_t need = layout(c, false);
+    if (!p || bytes < need || ((uintptr_t)p & 255))
+        return fail(c, DB_EINVAL, "workspace needs %zu bytes, 256-byte aligned", need);
+    c->arena = (char*)p;
+    c->arena_bytes = bytes;
+    c->arena_owned = false;
+    return DB_OK;
+}
+
+int db_destroy(db_ctx* c) {
+    if (!c) return DB_EINVAL;
+    db_host_ext& X = ext(c);
+    if (c->allocated) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->arena_owned && c->arena) (void)hipFree(c->arena);
+    if (X.pin) (void)hipHostFree(X.pin);
+    delete c->hx;
+    delete c;
+    return DB_OK;
+}
+
+const char* db_last_error(const db_ctx* c) { return c ? c->err.c_str() : "null handle"; }
+
+int db_set_state(db_ctx* c, const double* x, const double* v, const int32_t* type, int on_device) {
+    if (!c || !x || !type) return DB_EINVAL;
+    int rc = editable(c);
+    if (rc) return rc;
+    HostSys& h = ext(c).h;
+    const size_t n = (size_t)c->n;
+    std::vector<double> xs(3 * n), vs(3 * n, 0.0);
+    std::vector<int32_t> ts(n);
+    if (on_device) {
+        if (n) {
+            HIPCHK(c, hipMemcpy(xs.data(), x, 24 * n, hipMemcpyDeviceToHost));
+            if (v) HIPCHK(c, hipMemcpy(vs.data(), v, 24 * n, hipMemcpyDeviceToHost));
+            HIPCHK(c, hipMemcpy(ts.data(), type, 4 * n, hipMemcpyDeviceToHost));
+        }
+    } else {
+        std::copy(x, x + 3 * n, xs.begin());
+        if (v) std::copy(v, v + 3 * n, vs.begin());
+        std::copy(type, type + n, ts.begin());
+    }
+    for (size_t i = 0; i < 3 * n; ++i) {
+        if (!std::isfinite(xs[i]) || xs[i] < 0 || xs[i] >= c->L)
+            return fail(c, DB_EINVAL, "position %zu = %g outside [0, L)", i / 3, xs[i]);
+        if (!std::isfinite(vs[i])) return fail(c, DB_EINVAL, "velocity of bead %zu not finite", i / 3);
+    }
+    for (size_t i = 0; i < n; ++i)
+        if (ts[i] < 1 || ts[i] > 255) return fail(c, DB_EINVAL, "bead %zu has type %d outside 1..255", i, ts[i]);
+    h.x.swap(xs);
+    h.v.swap(vs);
+    h.type.swap(ts);
+    c->have_state = true;
+    ext(c).dev_error = 0;
+    return DB_OK;
+}
+
+int db_set_reactive(db_ctx* c, const uint8_t* flag) {
+    if (!c || !flag) return DB_EINVAL;
+    int rc = editable(c);
+    if (rc) return rc;
+    HostSys& h = ext(c).h;
+    for (int i = 0; i < c->n; ++i) h.reactive[i] = flag[i] ? 1 : 0;
+    return DB_OK;
+}
+
+int db_set_bonds(db_ctx* c, int64_t nb, const int32_t* ij, const int32_t* tij, const int32_t* tji) {
+    if (!c || nb < 0 || (nb > 0 && (!ij || !tij || !tji))) return DB_EINVAL;
+    int rc = editable(c);
+    if (rc) return rc;
+    std::vector<int> deg(c->n, 0);
+    std::vector<int32_t> b(4 * (size_t)nb);
+    for (int64_t k = 0; k < nb; ++k) {
+        int i = ij[2 * k], j = ij[2 * k + 1];
+        if (i < 0 || j < 0 || i >= c->n || j >= c->n || i == j)
+            return fail(c, DB_EINVAL, "bond %lld joins invalid beads %d, %d", (long long)k, i, j);
+        if (tij[k] < 1 || tij[k] >= DB_MAXT || tji[k] < 1 || tji[k] >= DB_MAXT)
+            return fail(c, DB_EINVAL, "bond %lld has a type outside 1..%d", (long long)k, DB_MAXT - 1);
+        if (++deg[i] > DB_MAXB || ++deg[j] > DB_MAXB)
+            return fail(c, DB_ECAPACITY, "a bead has more than %d bonds", DB_MAXB);
+        int a = i, bb = j, ta = tij[k], tb = tji[k];
+        if (a > bb) {
+            std::swap(a, bb);
+            std::swap(ta, tb);
+        }
+        b[4 * k] = a;
+        b[4 * k + 1] = bb;
+        b[4 * k + 2] = ta;
+        b[4 * k + 3] = tb;
+    }
+    HostSys& h = ext(c).h;
+    h.bonds.swap(b);
+    h.ang.clear();
+    h.dih.clear();
+    return DB_OK;
+}
+
+int db_set_angles(db_ctx* c, int64_t na, const int32_t* abc, const int32_t* type) {
+    if (!c || na < 0 || (na > 0 && (!abc || !type))) return DB_EINVAL;
+    int rc = editable(c);
+    if (rc) return rc;
+    std::vector<int32_t> a(4 * (size_t)na);
+    for (int64_t k = 0; k < na; ++k) {
+        int x = abc[3 * k], y = abc[3 * k + 1], z = abc[3 * k + 2];
+        if (x < 0 || y < 0 || z < 0 || x >= c->n || y >= c->n || z >= c->n || x == y || y == z || x == z)
+            return fail(c, DB_EINVAL, "angle %lld has invalid beads", (long long)k);
+        if (type[k] < 1 || type[k] >= DB_MAXT) return fail(c, DB_EINVAL, "angle %lld has an invalid type", (long long)k);
+        if (x > z) std::swap(x, z);
+        a[4 * k] = type[k];
+        a[4 * k + 1] = x;
+        a[4 * k + 2] = y;
+        a[4 * k + 3] = z;
+    }
+    ext(c).h.ang.swap(a);
+    return DB_OK;
+}
+
+int db_set_dihedrals(db_ctx* c, int64_t nd, const int32_t* abcd, const int32_t* type) {
+    if (!c || nd < 0 || (nd > 0 && (!abcd || !type))) return DB_EINVAL;
+    int rc = editable(c);
+    if (rc) return rc;
+    std::vector<int32_t> d(5 * (size_t)nd);
+    for (int64_t k = 0; k < nd; ++k) {
+        int m[4] = {abcd[4 * k], abcd[4 * k + 1], abcd[4 * k + 2], abcd[4 * k + 3]};
+        for (int q = 0; q < 4; ++q)
+            if (m[q] < 0 || m[q] >= c->n) return fail(c, DB_EINVAL, "dihedral %lld has invalid beads", (long long)k);
+        if (type[k] < 1 || type[k] >= DB_MAXT)
+            return fail(c, DB_EINVAL, "dihedral %lld has an invalid type", (long long)k);
+        if (m[0] > m[3]) {
+            std::swap(m[0], m[3]);
+            std::swap(m[1], m[2]);
+        }
+        d[5 * k] = type[k];
+        for (int q = 0; q < 4; ++q) d[5 * k + 1 + q] = m[q];
+    }
+    ext(c).h.dih.swap(d);
+    return DB_OK;
+}
+
+int db_generate_angles_dihedrals(db_ctx* c) {
+    if (!c) return DB_EINVAL;
+    int rc = ready(c);
+    if (rc) return rc;
+    launch_generate_all(c);
+    HIPCHK(c, hipMemcpyAsync(&ext(c).pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    ext(c).host_valid = false;
+    return check_device_error(c);
+}
+
+// ---- force field ----
+int db_pair_wca(db_ctx* c, double eps, double sigma, double rc, int depth) {
+    if (!c || !(rc > 0) || !(sigma > 0) || eps < 0 || depth < 0 || depth > 2) return DB_EINVAL;
+    if (2.0 * rc > c->L) return fail(c, DB_EINVAL, "box edge must exceed twice the pair cutoff");
+    Params& P = c->hp;
+    P.have_pair = 1;
+    P.eps = eps;
+    P.sig2 = sigma * sigma;
+    P.rc2 = rc * rc;
+    P.excl_depth = depth;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_bond_harmonic(db_ctx* c, int32_t t, double K, double r0) {
+    if (!c || t < 1 || t >= DB_MAXT || !std::isfinite(K) || !std::isfinite(r0)) return DB_EINVAL;
+    c->hp.bK[t] = K;
+    c->hp.bR0[t] = r0;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_angle_harmonic(db_ctx* c, int32_t t, double K, double th0) {
+    if (!c || t < 1 || t >= DB_MAXT || !std::isfinite(K) || !std::isfinite(th0)) return DB_EINVAL;
+    c->hp.aK[t] = K;
+    c->hp.aT0[t] = th0;
+    c->hp.aPiMinusT0[t] = 3.14159265358979323846 - th0;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_dihedral_cosine(db_ctx* c, int32_t t, double K, double p0) {
+    if (!c || t < 1 || t >= DB_MAXT || !std::isfinite(K) || !std::isfinite(p0)) return DB_EINVAL;
+    c->hp.dK[t] = K;
+    c->hp.dC0[t] = std::cos(p0);
+    c->hp.dS0[t] = std::sin(p0);
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_langevin(db_ctx* c, double T, double gamma, double dt) {
+    if (!c || !(dt > 0) || gamma < 0 || T < 0) return DB_EINVAL;
+    c->hp.T0 = c->hp.T1 = T;
+    c->hp.gamma = gamma;
+    c->hp.dt = dt;
+    c->hp.ramp = 0;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_temperature_ramp(db_ctx* c, double T0, double T1, int64_t n) {
+    if (!c || n < 0 || T0 < 0 || T1 < 0) return DB_EINVAL;
+    c->hp.T0 = T0;
+    c->hp.T1 = T1;
+    c->hp.ramp = n;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+// ---- rules ----
+static void note_create_types(Params& P, int b1, int b2) {
+    if (b1 == 0 || b2 == 0) P.create_types = 0xFFFFFFFFu;
+    else P.create_types |= (1u << (b1 & 31)) | (1u << (b2 & 31));
+}
+
+static int add_rule(db_ctx* c, Rule r) {
+    Params& P = c->hp;
+    if (P.nrule >= DB_MAXRULES) return fail(c, DB_ECAPACITY, "at most %d bond rules", DB_MAXRULES);
+    P.rule[P.nrule++] = r;
+    if (r.kind == RK_CREATE || r.kind == RK_CREATEDIR) {
+        double rmax = std::sqrt(r.r2);
+        if (2.0 * rmax > c->L) {
+            --P.nrule;
+            return fail(c, DB_EINVAL, "box edge must exceed twice the reaction distance");
+        }
+        P.rmax2_create = std::max(P.rmax2_create, r.r2);
+        note_create_types(P, r.b1, r.b2);
+    }
+    if (r.kind == RK_BREAK || r.kind == RK_CONVERT) P.has_break_class = 1;
+    if (r.kind == RK_KILL) P.has_kill = 1;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+static bool bad_bt(int t) { return t < 1 || t >= DB_MAXT; }
+static bool bad_bead(int b) { return b < 0 || b > 255; }
+static bool bad_p(double p) { return !(p >= 0.0 && p <= 1.0); }
+
+int db_sweep_every(db_ctx* c, int32_t every, int pc13, int pc14) {
+    if (!c || every < 0) return DB_EINVAL;
+    c->hp.every = every;
+    c->hp.pc13 = pc13 ? 1 : 0;
+    c->hp.pc14 = pc14 ? 1 : 0;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_bond_create(db_ctx* c, int32_t bt, int32_t b1, int32_t b2, double rmax, double p) {
+    if (!c || bad_bt(bt) || bad_bead(b1) || bad_bead(b2) || !(rmax > 0) || bad_p(p)) return DB_EINVAL;
+    return add_rule(c, Rule{RK_CREATE, bt, bt, b1, b2, rmax * rmax, p});
+}
+
+int db_bond_create_dir(db_ctx* c, int32_t bt1, int32_t bt2, int32_t b1, int32_t b2, double rmax, double p) {
+    if (!c || bad_bt(bt1) || bad_bt(bt2) || bad_bead(b1) || bad_bead(b2) || !(rmax > 0) || bad_p(p)) return DB_EINVAL;
+    return add_rule(c, Rule{RK_CREATEDIR, bt1, bt2, b1, b2, rmax * rmax, p});
+}
+
+int db_bond_break(db_ctx* c, int32_t bt, double rmin, double p) {
+    if (!c || bad_bt(bt) || !(rmin >= 0) || bad_p(p)) return DB_EINVAL;
+    return add_rule(c, Rule{RK_BREAK, bt, bt, 0, 0, rmin * rmin, p});
+}
+
+int db_bond_kill(db_ctx* c, int32_t bt, double rmin) {
+    if (!c || bad_bt(bt) || !(rmin >= 0)) return DB_EINVAL;
+    return add_rule(c, Rule{RK_KILL, bt, bt, 0, 0, rmin * rmin, 1.0});
+}
+
+int db_bond_convert(db_ctx* c, int32_t bf, int32_t bto, double rmin, double p) {
+    if (!c || bad_bt(bf) || bad_bt(bto) || !(rmin >= 0) || bad_p(p)) return DB_EINVAL;
+    return add_rule(c, Rule{RK_CONVERT, bf, bto, 0, 0, rmin * rmin, p});
+}
+
+int db_max_bonds(db_ctx* c, int32_t bt, int32_t bead, int32_t max) {
+    if (!c || bad_bt(bt) || bad_bead(bead) || max < 0) return DB_EINVAL;
+    Params& P = c->hp;
+    if (P.nmax >= DB_MAXRULES) return fail(c, DB_ECAPACITY, "at most %d maxbond rules", DB_MAXRULES);
+    P.maxr[P.nmax++] = MaxRule{bt, bead, max};
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_angle_pattern(db_ctx* c, int32_t t, const int32_t b[3], const uint32_t m[2]) {
+    if (!c || !b || !m || bad_bt(t)) return DB_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (bad_bead(b[k])) return DB_EINVAL;
+    Params& P = c->hp;
+    if (P.narule >= DB_MAXRULES) return fail(c, DB_ECAPACITY, "at most %d angle rules", DB_MAXRULES);
+    AngRule r;
+    r.type = t;
+    for (int k = 0; k < 3; ++k) r.b[k] = b[k];
+    r.m[0] = m[0];
+    r.m[1] = m[1];
+    P.arule[P.narule++] = r;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_dihedral_pattern(db_ctx* c, int32_t t, const int32_t b[4], const uint32_t m[3]) {
+    if (!c || !b || !m || bad_bt(t)) return DB_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (bad_bead(b[k])) return DB_EINVAL;
+    Params& P = c->hp;
+    if (P.ndrule >= DB_MAXRULES) return fail(c, DB_ECAPACITY, "at most %d dihedral rules", DB_MAXRULES);
+    DihRule r;
+    r.type = t;
+    for (int k = 0; k < 4; ++k) r.b[k] = b[k];
+    for (int k = 0; k < 3; ++k) r.m[k] = m[k];
+    P.drule[P.ndrule++] = r;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+// ---- running ----
+static void record_sweep_stats(db_ctx* c) {
+    Pinned* pin = ext(c).pin;
+    for (int q = 0; q < 8; ++q) {
+        c->stat_last[q] = (int64_t)pin->stats[q];
+        c->stat_cum[q] += (int64_t)pin->stats[q];
+    }
+    c->sweeps++;
+}
+
+static int launch_timed_step(db_ctx* c, int64_t step, int slot) {
+    if (c->profile) {
+        if ((size_t)c->ev_used + 2 > c->ev_pool.size()) {
+            for (int k = 0; k < 2 * kMaxBlock; ++k) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                c->ev_pool.push_back(e);
+            }
+        }
+        HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
+        launch_step(c, step, slot);
+        HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    } else {
+        launch_step(c, step, slot);
+    }
+    return DB_OK;
+}
+
+static int harvest_events(db_ctx* c) {
+    for (int k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+        c->prof_ms += ms;
+        c->prof_launches++;
+    }
+    c->ev_used = 0;
+    return DB_OK;
+}
+
+int db_step(db_ctx* c, int64_t nsteps) {
+    if (!c || nsteps < 0) return DB_EINVAL;
+    int rc = ready(c);
+    if (rc) return rc;
+    db_host_ext& X = ext(c);
+    Pinned* pin = X.pin;
+    const double dt = c->hp.dt;
+    const int every = c->hp.every;
+    const double skin = skin_of(c);
+    hipStream_t s = c->stream;
+    while (nsteps > 0) {
+        const int64_t k0 = c->step;
+        const bool sweep_due = every > 0 && k0 % every == 0 && c->swept_step != k0;
+        int64_t len = std::min<int64_t>(nsteps, std::min(c->rebuild_interval, kMaxBlock));
+        if (every > 0) len = std::min<int64_t>(len, every - (k0 % every));
+        const bool permute = (c->rebuild_count++ % c->permute_every) == 0;
+        rebuild(c, permute);
+        if (sweep_due) {
+            launch_sweep(c, k0);
+            HIPCHK(c, hipMemcpyAsync(pin->stats, c->sw.stats, 64, hipMemcpyDeviceToHost, s));
+            c->swept_step = k0;
+        }
+        const bool guard = std::isfinite(skin) && len > 1;
+        Bank& B = c->bank[c->cur];
+        if (guard) {
+            HIPCHK(c, hipMemcpyAsync(c->xsave, B.x, 32 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(c->vsave, B.v, 24 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
+        }
+        launch_fill_int((int*)c->vmax2, 0, (size_t)len, s);
+        for (int64_t q = 0; q < len; ++q) launch_timed_step(c, k0 + q, (int)q);
+        HIPCHK(c, hipMemcpyAsync(pin->vmax2, c->vmax2, 4 * (size_t)len, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, hipGetLastError());
+        if (c->profile) {
+            rc = harvest_events(c);
+            if (rc) return rc;
+        }
+        if (sweep_due) record_sweep_stats(c);
+        X.host_valid = false;
+        rc = check_device_error(c);
+        if (rc) return rc;
+        double bound = 0.0, vmax = 0.0;
+        for (int64_t q = 0; q < len; ++q) {
+            double v = std::sqrt((double)pin->vmax2[q]);
+            vmax = std::max(vmax, v);
+            if (q + 1 < len) bound += dt * v;
+        }
+        if (guard && bound > skin) {
+            // some bead may have left the reach of the cell list: redo with a fresh list every step
+            c->rollbacks++;
+            Bank& Bc = c->bank[c->cur];
+            HIPCHK(c, hipMemcpyAsync(Bc.x, c->xsave, 32 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(Bc.v, c->vsave, 24 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
+            for (int64_t q = 0; q < len; ++q) {
+                rebuild(c, false);
+                launch_step(c, k0 + q, 0);
+            }
+            HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            rc = check_device_error(c);
+            if (rc) return rc;
+            c->rebuild_interval = std::max<int>(1, (int)(len / 2));
+        } else if (std::isfinite(skin) && vmax > 0) {
+            int want = (int)std::floor(0.8 * skin / (dt * vmax));
+            c->rebuild_interval = std::max(1, std::min(kMaxBlock, want));
+        } else if (!std::isfinite(skin)) {
+            c->rebuild_interval = kMaxBlock;
+        }
+        c->vmax_est = vmax;
+        c->step += len;
+        nsteps -= len;
+    }
+    return DB_OK;
+}
+
+int db_sweep_now(db_ctx* c) {
+    if (!c) return DB_EINVAL;
+    int rc = ready(c);
+    if (rc) return rc;
+    if (c->swept_step == c->step) return fail(c, DB_ESTATE, "the sweep of step %lld was already done", (long long)c->step);
+    rebuild(c, (c->rebuild_count++ % c->permute_every) == 0);
+    launch_sweep(c, c->step);
+    Pinned* pin = ext(c).pin;
+    HIPCHK(c, hipMemcpyAsync(pin->stats, c->sw.stats, 64, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    record_sweep_stats(c);
+    c->swept_step = c->step;
+    ext(c).host_valid = false;
+    return check_device_error(c);
+}
+
+int db_forces(db_ctx* c, double* f, int on_device) {
+    if (!c || !f) return DB_EINVAL;
+    int rc = ready(c);
+    if (rc) return rc;
+    rebuild(c, false);
+    double* d = on_device ? f : (double*)scratch(c, 24 * (size_t)c->n);
+    launch_forces(c, d);
+    if (!on_device && c->n) HIPCHK(c, hipMemcpyAsync(f, d, 24 * (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    return DB_OK;
+}
+
+int db_energy(db_ctx* c, double out[6]) {
+    if (!c || !out) return DB_EINVAL;
+    int rc = ready(c);
+    if (rc) return rc;
+    rebuild(c, false);
+    double* d = (double*)scratch(c, 64);
+    launch_energy(c, d);
+    HIPCHK(c, hipMemcpyAsync(ext(c).pin->energy, d, 48, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    memcpy(out, ext(c).pin->energy, 48);
+    return DB_OK;
+}
+
+int db_get_state(db_ctx* c, double* x, double* v, int on_device) {
+    if (!c) return DB_EINVAL;
+    db_host_ext& X = ext(c);
+    const size_t n = (size_t)c->n;
+    if (!X.dev_valid || X.host_valid) {
+        if (!c->have_state) return fail(c, DB_ESTATE, "no state");
+        if (on_device) {
+            if (x && n) HIPCHK(c, hipMemcpy(x, X.h.x.data(), 24 * n, hipMemcpyHostToDevice));
+            if (v && n) HIPCHK(c, hipMemcpy(v, X.h.v.data(), 24 * n, hipMemcpyHostToDevice));
+        } else {
+            if (x) std::copy(X.h.x.begin(), X.h.x.end(), x);
+            if (v) std::copy(X.h.v.begin(), X.h.v.end(), v);
+        }
+        return DB_OK;
+    }
+    if (n == 0) return DB_OK;
+    double* d = (double*)scratch(c, 48 * n);
+    hipLaunchKernelGGL(k_gather_state, dim3((unsigned)((n + DB_BLOCK - 1) / DB_BLOCK)), dim3(DB_BLOCK), 0, c->stream,
+                       (int)n, c->bank[c->cur], d, d + 3 * n);
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (x) HIPCHK(c, hipMemcpyAsync(x, d, 24 * n, kind, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(v, d + 3 * n, 24 * n, kind, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    return DB_OK;
+}
+
+int db_topology_counts(db_ctx* c, int64_t* nb, int64_t* na, int64_t* nd) {
+    if (!c) return DB_EINVAL;
+    db_host_ext& X = ext(c);
+    if (X.host_valid) {
+        if (nb) *nb = (int64_t)(X.h.bonds.size() / 4);
+        if (na) *na = (int64_t)(X.h.ang.size() / 4);
+        if (nd) *nd = (int64_t)(X.h.dih.size() / 5);
+        return DB_OK;
+    }
+    int rc = download_system(c);
+    if (rc) return rc;
+    return db_topology_counts(c, nb, na, nd);
+}
+
+int db_get_bonds(db_ctx* c, int32_t* ij, int32_t* tij, int32_t* tji) {
+    if (!c) return DB_EINVAL;
+    int rc = download_system(c);
+    if (rc) return rc;
+    const std::vector<int32_t>& b = ext(c).h.bonds;
+    const size_t m = b.size() / 4;
+    std::vector<int32_t> tt(2 * m);
+    sorted_copy<2, 2>(b, ij, tt.data(), 0);
+    for (size_t k = 0; k < m; ++k) {
+        if (tij) tij[k] = tt[2 * k];
+        if (tji) tji[k] = tt[2 * k + 1];
+    }
+    return DB_OK;
+}
+
+int db_get_angles(db_ctx* c, int32_t* abc, int32_t* type) {
+    if (!c) return DB_EINVAL;
+    int rc = download_system(c);
+    if (rc) return rc;
+    sorted_copy<3, 1>(ext(c).h.ang, abc, type, 1);
+    return DB_OK;
+}
+
+int db_get_dihedrals(db_ctx* c, int32_t* abcd, int32_t* type) {
+    if (!c) return DB_EINVAL;
+    int rc = download_system(c);
+    if (rc) return rc;
+    sorted_copy<4, 1>(ext(c).h.dih, abcd, type, 1);
+    return DB_OK;
+}
+
+int db_get_stats(db_ctx* c, db_stats* o) {
+    if (!c || !o) return DB_EINVAL;
+    int64_t* p = &o->bonds_created;
+    for (int q = 0; q < 8; ++q) {
+        p[q] = c->stat_last[q];
+        p[8 + q] = c->stat_cum[q];
+    }
+    o->sweeps = c->sweeps;
+    o->steps = c->step;
+    o->rebuilds = c->rebuilds;
+    o->rollbacks = c->rollbacks;
+    return DB_OK;
+}
+
+int db_set_step(db_ctx* c, int64_t step) {
+    if (!c || step < 0) return DB_EINVAL;
+    c->step = step;
+    c->swept_step = -1;
+    return DB_OK;
+}
+
+int db_profile(db_ctx* c, int enable) {
+    if (!c) return DB_EINVAL;
+    c->profile = enable != 0;
+    return DB_OK;
+}
+
+int db_step_kernel_time(db_ctx* c, double* mean_us, int64_t* launches) {
+    if (!c) return DB_EINVAL;
+    if (mean_us) *mean_us = c->prof_launches ? 1000.0 * c->prof_ms / (double)c->prof_launches : 0.0;
+    if (launches) *launches = c->prof_launches;
+    c->prof_ms = 0;
+    c->prof_launches = 0;
+    return DB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Device-side helpers of libdynbond: counter-based random numbers, minimum
+// image, bead metadata packing, workgroup-to-XCD mapping.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "db_internal.h"
+
+namespace db {
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies with the published multipliers, key schedule bumped by the Weyl
+// constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * c.x;
+        uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// counter layout: (a, b, step low word, step high bits | stream tag << 28)
+__device__ __forceinline__ uint4 rng_draw(const Params& P, uint32_t a, uint32_t b, int64_t step, uint32_t kind) {
+    uint64_t st = (uint64_t)step;
+    uint4 c = make_uint4(a, b, (uint32_t)st, ((uint32_t)(st >> 32) & 0x0FFFFFFFu) | (kind << 28));
+    return philox4x32_10(c, P.seed_lo, P.seed_hi);
+}
+
+// uniform in [0,1) with 53 random bits, drawn for the unordered pair {ga, gb}
+__device__ __forceinline__ double pair_uniform(const Params& P, int ga, int gb, int64_t step, uint32_t kind) {
+    uint32_t lo = (uint32_t)(ga < gb ? ga : gb), hi = (uint32_t)(ga < gb ? gb : ga);
+    uint4 w = rng_draw(P, lo, hi, step, kind);
+    uint64_t bits = ((((uint64_t)w.x) << 32) | (uint64_t)w.y) >> 11;
+    return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ double min_image(double d, double L, double hL) {
+    if (d > hL) return d - L;
+    if (d < -hL) return d + L;
+    return d;
+}
+
+// x_j - x_i with the minimum-image convention, and its squared length summed
+// as (dx^2 + dy^2) + dz^2 (the order the cutoff decisions are defined in)
+__device__ __forceinline__ double separation(const Params& P, const double4& xi, const double4& xj, double& dx,
+                                             double& dy, double& dz) {
+    dx = min_image(xj.x - xi.x, P.L, P.hL);
+    dy = min_image(xj.y - xi.y, P.L, P.hL);
+    dz = min_image(xj.z - xi.z, P.L, P.hL);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ int meta_gid(const double4& x) {
+    return (int)(uint32_t)((unsigned long long)__double_as_longlong(x.w));
+}
+__device__ __forceinline__ int meta_word(const double4& x) {
+    return (int)(uint32_t)(((unsigned long long)__double_as_longlong(x.w)) >> 32);
+}
+__device__ __forceinline__ int meta_type(int m) { return m & 0xFF; }
+__device__ __forceinline__ int meta_reactive(int m) { return (m >> 8) & 1; }
+
+__host__ __device__ inline double pack_meta(int gid, int type, int reactive) {
+    unsigned long long bits = (unsigned long long)(uint32_t)gid |
+                              ((unsigned long long)(uint32_t)(type | (reactive << 8)) << 32);
+    double d;
+    __builtin_memcpy(&d, &bits, sizeof(d));
+    return d;
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs.  Map them so that each XCD
+// processes one contiguous range of tiles and neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+    int per = nblocks >> 3;
+    int full = per << 3;
+    if (bid >= full) return bid;           // the tail keeps its own index
+    return (bid & 7) * per + (bid >> 3);   // XCD (bid % 8) owns tiles [x*per, (x+1)*per)
+}
+
+__device__ __forceinline__ int cell_coord(double x, double scale, int nc) {
+    int c = (int)(x * scale);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+// position update with the periodic wrap into [0, L)
+__device__ __forceinline__ double wrap1(double x, double L) {
+    if (x >= L) return x - L;
+    if (x < 0.0) {
+        double y = x + L;
+        return y >= L ? 0.0 : y;
+    }
+    return x;
+}
+
+}  // namespace db

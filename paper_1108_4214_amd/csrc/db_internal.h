@@ -1,0 +1,182 @@
+// Internal declarations of libdynbond: device-side parameter block, per-bead
+// storage layout, the handle, and the kernel launchers shared by the .hip units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dynbond.h"
+
+#define DB_MAXB DB_MAX_BONDS_PER_BEAD
+#define DB_MAXA DB_MAX_ANGLES_PER_BEAD
+#define DB_MAXD DB_MAX_DIHEDRALS_PER_BEAD
+#define DB_MAXT 32
+#define DB_MAXRULES 32
+#define DB_BLOCK 256
+
+namespace db {
+
+enum RuleKind { RK_CREATE = 1, RK_CREATEDIR = 2, RK_BREAK = 3, RK_KILL = 4, RK_CONVERT = 5 };
+
+// random-number stream tags (top 4 bits of the last counter word)
+enum RngKind : uint32_t { RNG_LANGEVIN = 0u, RNG_CREATE = 1u, RNG_BREAK = 2u };
+
+// device error word bits
+enum ErrBit : int { ERR_BOND_CAP = 1, ERR_ANGLE_CAP = 2, ERR_DIH_CAP = 4, ERR_NONFINITE = 8, ERR_CELL = 16 };
+
+struct Rule {
+    int kind, bt1, bt2, b1, b2;
+    double r2, p;
+};
+struct MaxRule { int bt, bead, max; };
+struct AngRule { int type; int b[3]; uint32_t m[2]; };
+struct DihRule { int type; int b[4]; uint32_t m[3]; };
+
+// Read-only parameters of one box, resident in device memory.
+struct Params {
+    int n;
+    double L, hL;
+    // cell grid: nc^3 cells of edge L/nc; neighbour offsets per dimension
+    int nc, ncell, noff;
+    int off[3];
+    double cell_scale;   // nc / L
+    // WCA
+    int have_pair, excl_depth;
+    double eps, sig2, rc2;
+    // bonded
+    double bK[DB_MAXT], bR0[DB_MAXT];
+    double aK[DB_MAXT], aT0[DB_MAXT], aPiMinusT0[DB_MAXT];
+    double dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
+    // thermostat / integration
+    double gamma, dt, T0, T1;
+    int64_t ramp;
+    uint32_t seed_lo, seed_hi;
+    // rules, in call order
+    int every, pc13, pc14;
+    int nrule, nmax, narule, ndrule;
+    Rule rule[DB_MAXRULES];
+    MaxRule maxr[DB_MAXRULES];
+    AngRule arule[DB_MAXRULES];
+    DihRule drule[DB_MAXRULES];
+    double rmax2_create;        // largest creation distance squared
+    uint32_t create_types;      // bit t: bead type t occurs in some creation rule
+    int has_break_class;        // any breakbond / convertbond rule
+    int has_kill;
+};
+
+// Per-bead storage in slot (cell-sorted) order.  Tables are column-major:
+// entry k of bead s lives at [k * n + s], so a wavefront reads one row coalesced.
+struct Bank {
+    double4* x;       // x, y, z; w = bits {int gid, int meta}; meta = type | reactive << 8
+    double* v;        // SoA: vx[n], vy[n], vz[n]
+    uint8_t* nb;      // bond count
+    int* bp;          // [MAXB][n] partner slot
+    int8_t* bt;       // [MAXB][n] type this bead stores for the bond
+    uint8_t* na;
+    int4* ang;        // [MAXA][n] members (slots) a, b, c; .w = angle type
+    uint8_t* nd;
+    int4* dih;        // [MAXD][n] members (slots) a, b, c, d
+    uint8_t* dt;      // [MAXD][n] dihedral type
+};
+
+// Scratch of the sweep, per bead in slot order.
+struct SweepBuf {
+    int* nomC;        // creation partner slot or -1
+    int8_t* ruleC;    // rule index
+    int8_t* btC;      // type this bead would store
+    int* nomK;        // breakage partner slot or -1
+    int8_t* ruleK;
+    uint8_t* rmcnt;   // removed (killed / broken / converted) bond entries
+    int* rmlist;      // [MAXB][n] partner slots of removed entries
+    uint8_t* conv;    // bead takes part in an accepted conversion
+    int* newp;        // partner slot of this bead's new (created or converted) bond, or -1
+    unsigned long long* stats;   // [8] counters of the sweep
+};
+
+struct Cells {
+    int* cnt;         // [ncell]
+    int* start;       // [ncell + 1]
+    int* list;        // [n] slots, cell by cell, ascending within a cell
+    int* cellid;      // [n]
+    int* blocksum;    // scan scratch
+};
+
+}  // namespace db
+
+struct db_host_ext;   // host-side copies and staging, defined by the API unit
+
+struct db_ctx {
+    db_host_ext* hx;
+    int n;
+    double L;
+    uint64_t seed;
+    int precision;
+    hipStream_t stream;
+    std::string err;
+
+    db::Params hp;       // host copy
+    db::Params* dp;      // device copy
+    bool params_dirty;
+
+    // device memory arena
+    char* arena;
+    size_t arena_bytes;
+    bool arena_owned;
+    bool allocated;
+
+    db::Bank bank[2];
+    int cur;
+    double4* xnext;      // double buffer of positions for the step kernel
+    double4* xsave;      // state at block start (rollback)
+    double* vsave;
+    db::SweepBuf sw;
+    db::Cells cells;
+    int* slot_of_gid;    // [n]
+    int* err_d;          // device error word
+    float* vmax2;        // [max block length] max |v|^2 after each step (as float bits)
+    double* red;         // reduction scratch
+    int64_t* cnt64;      // small device counters
+    void* pinned;        // pinned host staging
+    int max_block;
+
+    // topology on the host side until uploaded
+    bool have_state, have_topology;
+    int64_t step, swept_step;
+    int64_t rebuilds, rollbacks, sweeps;
+    int64_t stat_last[8], stat_cum[8];
+    int rebuild_interval;     // steps between rebuilds inside a block
+    int permute_every;        // permute the state every k-th rebuild
+    int64_t rebuild_count;
+    double skin;
+    double vmax_est;
+
+    // profiling
+    bool profile;
+    std::vector<hipEvent_t> ev_pool;
+    int ev_used;
+    double prof_ms;
+    int64_t prof_launches;
+};
+
+namespace db {
+
+// kernels_cells.hip
+void launch_fill_int(int* p, int value, size_t count, hipStream_t s);
+void launch_build_cells(db_ctx* c);                  // bin + scan + scatter + in-cell sort
+void launch_permute(db_ctx* c);                      // reorder all per-bead state by the cell list
+void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s);
+
+// kernels_force.hip
+void launch_step(db_ctx* c, int64_t step, int slot_in_block);
+void launch_forces(db_ctx* c, double* f_gid_order);
+void launch_energy(db_ctx* c, double* out6_device);
+
+// kernels_sweep.hip
+void launch_sweep(db_ctx* c, int64_t step);
+void launch_generate_all(db_ctx* c);
+void launch_count_topology(db_ctx* c, int64_t* nb_na_nd_device);
+void launch_gather_topology(db_ctx* c, int kind, int32_t* out_tuples, int32_t* out_types, int64_t count);
+
+}  // namespace db

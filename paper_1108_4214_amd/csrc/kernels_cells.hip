@@ -1,0 +1,221 @@
+// Cell list (counting sort of beads by cell) and spatial reordering of the
+// per-bead state.  The cell edge is at least the longest reaction distance and
+// at least the pair cutoff plus a skin, so a bead's partners within reach lie in
+// its own or the adjacent cells (the neighbour structure needs a communication
+// distance at least as long as the longest reaction distance, appendix).
+#include "db_device.h"
+
+namespace db {
+
+__global__ void k_fill_int(int* __restrict__ p, int value, size_t count) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+void launch_fill_int(int* p, int value, size_t count, hipStream_t s) {
+    if (count == 0) return;
+    unsigned blocks = (unsigned)((count + DB_BLOCK - 1) / DB_BLOCK);
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks), dim3(DB_BLOCK), 0, s, p, value, count);
+}
+
+// ---- binning -----------------------------------------------------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_bin(const Params* __restrict__ Pp, const double4* __restrict__ x,
+                                                   int* __restrict__ cellid, int* __restrict__ cnt) {
+    const Params& P = *Pp;
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= P.n) return;
+    double4 xi = x[i];
+    int cx = cell_coord(xi.x, P.cell_scale, P.nc);
+    int cy = cell_coord(xi.y, P.cell_scale, P.nc);
+    int cz = cell_coord(xi.z, P.cell_scale, P.nc);
+    int c = (cz * P.nc + cy) * P.nc + cx;
+    cellid[i] = c;
+    atomicAdd(&cnt[c], 1);
+}
+
+// ---- exclusive scan (1024 items per workgroup, multi-level) -------------------
+#define SCAN_ITEMS 4
+#define SCAN_TILE (DB_BLOCK * SCAN_ITEMS)
+
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    // Hillis-Steele over the 64 lanes of a wavefront
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// in[0..count) -> out[0..count) exclusive; per-tile totals to blocksum
+__global__ __launch_bounds__(DB_BLOCK) void k_scan_tiles(const int* __restrict__ in, int* __restrict__ out, int count,
+                                                         int* __restrict__ blocksum) {
+    __shared__ int wsum[DB_BLOCK / 64];
+    int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int local = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int idx = base + k;
+        v[k] = idx < count ? in[idx] : 0;
+        local += v[k];
+    }
+    int incl = wave_inclusive_scan(local);
+    int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int w = 0; w < wid; ++w) woff += wsum[w];
+    int run = woff + incl - local;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int idx = base + k;
+        if (idx < count) out[idx] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == DB_BLOCK - 1) blocksum[blockIdx.x] = run;
+}
+
+__global__ __launch_bounds__(DB_BLOCK) void k_scan_add(int* __restrict__ out, int count,
+                                                       const int* __restrict__ offsets) {
+    int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int off = offsets[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int idx = base + k;
+        if (idx < count) out[idx] += off;
+    }
+}
+
+__global__ void k_copy_int(const int* __restrict__ src, int* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+// out[count] = out[count - 1] + (saved last input)
+__global__ void k_scan_total(const int* __restrict__ last_in, int* __restrict__ out, int count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[count] = out[count - 1] + *last_in;
+}
+
+// Exclusive scan of in[0..count) into out[0..count) (in == out allowed: each tile
+// reads its items before any of them is written).  blocksum must hold the tile
+// totals of every level: ceil(count/1024) + ceil(count/1024^2) + ... ints.
+static void scan_into(const int* in, int* out, int count, int* blocksum, hipStream_t s) {
+    int tiles = (count + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles == 0) return;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(DB_BLOCK), 0, s, in, out, count, blocksum);
+    if (tiles > 1) {
+        scan_into(blocksum, blocksum, tiles, blocksum + tiles, s);
+        hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(DB_BLOCK), 0, s, out, count, blocksum);
+    }
+}
+
+// data[0..count) -> exclusive prefix sums in place, and the total in data[count]
+void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s) {
+    (void)total_out;
+    if (count <= 0) return;
+    int* last = blocksum;
+    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(1), 0, s, data + count - 1, last);
+    scan_into(data, data, count, blocksum + 1, s);
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, last, data, count);
+}
+
+// ---- scatter and in-cell ordering --------------------------------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_scatter(int n, const int* __restrict__ cellid,
+                                                       const int* __restrict__ start, int* __restrict__ cnt,
+                                                       int* __restrict__ list) {
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int c = cellid[i];
+    int k = atomicSub(&cnt[c], 1) - 1;   // leaves cnt at zero for the next build
+    list[start[c] + k] = i;
+}
+
+// ascending slot order inside each cell makes the list independent of the
+// arrival order of the atomics above
+__global__ __launch_bounds__(DB_BLOCK) void k_cellsort(int ncell, const int* __restrict__ start,
+                                                        int* __restrict__ list) {
+    int c = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (c >= ncell) return;
+    int s0 = start[c], s1 = start[c + 1];
+    for (int a = s0 + 1; a < s1; ++a) {
+        int v = list[a];
+        int b = a - 1;
+        while (b >= s0 && list[b] > v) {
+            list[b + 1] = list[b];
+            --b;
+        }
+        list[b + 1] = v;
+    }
+}
+
+void launch_build_cells(db_ctx* c) {
+    const int n = c->n;
+    const int ncell = c->hp.ncell;
+    hipStream_t s = c->stream;
+    db::Bank& B = c->bank[c->cur];
+    unsigned nb = (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK);
+    if (n > 0) hipLaunchKernelGGL(k_bin, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid, c->cells.cnt);
+    // start = exclusive scan of cnt; start[ncell] = n
+    scan_into(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, c->cells.start + ncell, n, (size_t)1);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.cellid, c->cells.start,
+                           c->cells.cnt, c->cells.list);
+        unsigned cb = (unsigned)((ncell + DB_BLOCK - 1) / DB_BLOCK);
+        hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(DB_BLOCK), 0, s, ncell, c->cells.start, c->cells.list);
+    }
+}
+
+// ---- permutation of the whole per-bead state into cell order -------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_newslot(int n, const int* __restrict__ list, int* __restrict__ newslot) {
+    int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (s < n) newslot[list[s]] = s;
+}
+
+__global__ __launch_bounds__(DB_BLOCK) void k_permute(int n, Bank src, Bank dst, int* __restrict__ list,
+                                                       const int* __restrict__ newslot, int* __restrict__ slot_of_gid) {
+    int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (s >= n) return;
+    int o = list[s];
+    double4 x = src.x[o];
+    dst.x[s] = x;
+    dst.v[s] = src.v[o];
+    dst.v[n + s] = src.v[n + o];
+    dst.v[2 * n + s] = src.v[2 * n + o];
+    slot_of_gid[meta_gid(x)] = s;
+    int nb = src.nb[o];
+    dst.nb[s] = (uint8_t)nb;
+    for (int k = 0; k < nb; ++k) {
+        dst.bp[k * n + s] = newslot[src.bp[k * n + o]];
+        dst.bt[k * n + s] = src.bt[k * n + o];
+    }
+    int na = src.na[o];
+    dst.na[s] = (uint8_t)na;
+    for (int k = 0; k < na; ++k) {
+        int4 e = src.ang[k * n + o];
+        dst.ang[k * n + s] = make_int4(newslot[e.x], newslot[e.y], newslot[e.z], e.w);
+    }
+    int nd = src.nd[o];
+    dst.nd[s] = (uint8_t)nd;
+    for (int k = 0; k < nd; ++k) {
+        int4 e = src.dih[k * n + o];
+        dst.dih[k * n + s] = make_int4(newslot[e.x], newslot[e.y], newslot[e.z], newslot[e.w]);
+        dst.dt[k * n + s] = src.dt[k * n + o];
+    }
+    list[s] = s;   // the cells now hold contiguous slot ranges
+}
+
+void launch_permute(db_ctx* c) {
+    const int n = c->n;
+    if (n == 0) return;
+    hipStream_t s = c->stream;
+    unsigned nb = (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK);
+    int* newslot = c->cells.cellid;   // the bin ids are no longer needed
+    hipLaunchKernelGGL(k_newslot, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, newslot);
+    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->bank[c->cur], c->bank[1 - c->cur],
+                       c->cells.list, newslot, c->slot_of_gid);
+    c->cur = 1 - c->cur;
+}
+
+}  // namespace db

@@ -1,0 +1,640 @@
+// The dynamic-bonding sweep (section 2 and the appendix "Implementation
+// details", steps 2-9) as per-bead kernels.  Every bead owns its bond, angle and
+// dihedral table (the paper's Newton-off storage), so each kernel writes only
+// the entries of its own bead and reads other beads' tables; no atomics touch
+// the topology.  Both beads of a pair evaluate the same pair-keyed decisions
+// (distance, rule, random number), so their tables stay consistent without any
+// exchange.
+//
+//   nominate_create   closest eligible creation partner per bead (step 2)
+//   nominate_break    most distant eligible bonded partner; killbond marks (step 3, 5)
+//   resolve           mutual breakage nominations accepted with probability p (step 5)
+//   apply             drop angles/dihedrals crossing removed bonds (step 6),
+//                     remove / convert bonds (step 7), accept mutual creation
+//                     nominations with probability p (step 8)
+//   generate          new angles/dihedrals on paths through new bonds (step 9)
+#include "db_device.h"
+
+namespace db {
+
+enum { ST_CREATED = 0, ST_BROKEN, ST_KILLED, ST_CONVERTED, ST_ANG_NEW, ST_ANG_DEL, ST_DIH_NEW, ST_DIH_DEL };
+
+struct Tab {
+    int n;
+    int p[DB_MAXB];
+    int t[DB_MAXB];
+};
+
+__device__ __forceinline__ Tab load_tab(const Bank& B, int n, int s) {
+    Tab T;
+    T.n = B.nb[s];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        T.p[k] = k < T.n ? B.bp[k * n + s] : -1;
+        T.t[k] = k < T.n ? (int)B.bt[k * n + s] : 0;
+    }
+    return T;
+}
+
+__device__ __forceinline__ int tab_type_of(const Tab& T, int v) {
+    for (int k = 0; k < T.n; ++k)
+        if (T.p[k] == v) return T.t[k];
+    return -1;
+}
+__device__ __forceinline__ bool tab_has(const Tab& T, int v) {
+    for (int k = 0; k < T.n; ++k)
+        if (T.p[k] == v) return true;
+    return false;
+}
+__device__ __forceinline__ int tab_count(const Tab& T, int t) {
+    int c = 0;
+    for (int k = 0; k < T.n; ++k) c += (T.t[k] == t);
+    return c;
+}
+__device__ __forceinline__ bool type_ok(int rule_bead, int bead_type) { return rule_bead == 0 || rule_bead == bead_type; }
+__device__ __forceinline__ bool in_mask(uint32_t m, int t) { return t >= 0 && t < 32 && ((m >> t) & 1u); }
+
+// maxbond: a bead of type bead_type holding table T may store one more bond of type t
+__device__ __forceinline__ bool max_ok(const Params& P, int bead_type, const Tab& T, int t) {
+    for (int q = 0; q < P.nmax; ++q) {
+        const MaxRule& m = P.maxr[q];
+        if (m.bt == t && type_ok(m.bead, bead_type) && tab_count(T, t) >= m.max) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void stat_add(unsigned long long* st, int k, unsigned long long v) {
+    if (v) atomicAdd(&st[k], v);
+}
+
+// ---- step 2: creation nomination -------------------------------------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
+                                                              const int* __restrict__ cstart,
+                                                              const int* __restrict__ clist, SweepBuf S) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double4 xi = B.x[i];
+    int mi = meta_word(xi);
+    int ti = meta_type(mi);
+    int gi = meta_gid(xi);
+    int best = -1, best_rule = -1, best_bt = 0, best_g = 0;
+    double best_r2 = 0.0;
+    if (meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0) {
+        Tab Ti = load_tab(B, n, i);
+        const int nc = P.nc;
+        int cx = cell_coord(xi.x, P.cell_scale, nc);
+        int cy = cell_coord(xi.y, P.cell_scale, nc);
+        int cz = cell_coord(xi.z, P.cell_scale, nc);
+        for (int oz = 0; oz < P.noff; ++oz)
+            for (int oy = 0; oy < P.noff; ++oy)
+                for (int ox = 0; ox < P.noff; ++ox) {
+                    int c = (wrap_cell(cz + P.off[oz], nc) * nc + wrap_cell(cy + P.off[oy], nc)) * nc +
+                            wrap_cell(cx + P.off[ox], nc);
+                    int s1 = cstart[c + 1];
+                    for (int p = cstart[c]; p < s1; ++p) {
+                        int j = clist[p];
+                        if (j == i) continue;
+                        double4 xj = B.x[j];
+                        int mj = meta_word(xj);
+                        if (!meta_reactive(mj)) continue;
+                        double dx, dy, dz;
+                        double r2 = separation(P, xi, xj, dx, dy, dz);
+                        if (!(r2 < P.rmax2_create)) continue;
+                        int tj = meta_type(mj);
+                        int gj = meta_gid(xj);
+                        // last creation rule that applies to the pair
+                        int rule = -1, bti = 0;
+                        bool have_tj = false;
+                        Tab Tj;
+                        for (int q = 0; q < P.nrule; ++q) {
+                            const Rule& r = P.rule[q];
+                            if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
+                            bool o1 = type_ok(r.b1, ti) && type_ok(r.b2, tj);
+                            bool o2 = type_ok(r.b1, tj) && type_ok(r.b2, ti);
+                            if (!o1 && !o2) continue;
+                            if (o1 && o2) o1 = gi < gj;   // both orientations: the lower id plays bead1
+                            int si = o1 ? r.bt1 : r.bt2;
+                            int sj = o1 ? r.bt2 : r.bt1;
+                            if (!(r2 < r.r2)) continue;
+                            if (!max_ok(P, ti, Ti, si)) continue;
+                            if (!have_tj) {
+                                Tj = load_tab(B, n, j);
+                                have_tj = true;
+                            }
+                            if (!max_ok(P, tj, Tj, sj)) continue;
+                            rule = q;
+                            bti = si;
+                        }
+                        if (rule < 0) continue;
+                        // graph distance 1, 2 or 3 on the bond graph before the sweep
+                        if (tab_has(Ti, j)) continue;
+                        bool d2 = false;
+                        for (int a = 0; a < Ti.n && !d2; ++a)
+                            if (tab_has(Tj, Ti.p[a])) d2 = true;
+                        if (d2 && !P.pc13) continue;
+                        if (!d2 && !P.pc14) {
+                            bool d3 = false;
+                            for (int a = 0; a < Ti.n && !d3; ++a) {
+                                Tab Tq = load_tab(B, n, Ti.p[a]);
+                                for (int b = 0; b < Tj.n; ++b)
+                                    if (tab_has(Tq, Tj.p[b])) {
+                                        d3 = true;
+                                        break;
+                                    }
+                            }
+                            if (d3) continue;
+                        }
+                        if (best < 0 || r2 < best_r2 || (r2 == best_r2 && gj < best_g)) {
+                            best = j;
+                            best_r2 = r2;
+                            best_g = gj;
+                            best_rule = rule;
+                            best_bt = bti;
+                        }
+                    }
+                }
+    }
+    S.nomC[i] = best;
+    S.ruleC[i] = (int8_t)best_rule;
+    S.btC[i] = (int8_t)best_bt;
+}
+
+// ---- steps 3 and 5: breakage nomination and killbond marks ----------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __restrict__ Pp, Bank B, SweepBuf S) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double4 xi = B.x[i];
+    int mi = meta_word(xi);
+    int gi = meta_gid(xi);
+    int best = -1, best_rule = -1, best_g = 0;
+    double best_r2 = 0.0;
+    int rm = 0;
+    unsigned long long killed_here = 0;
+    if (meta_reactive(mi) && (P.has_kill || P.has_break_class)) {
+        Tab Ti = load_tab(B, n, i);
+        int ti = meta_type(mi);
+        for (int k = 0; k < Ti.n; ++k) {
+            int j = Ti.p[k], t = Ti.t[k];
+            double4 xj = B.x[j];
+            int mj = meta_word(xj);
+            if (!meta_reactive(mj)) continue;
+            Tab Tj = load_tab(B, n, j);
+            if (tab_type_of(Tj, i) != t) continue;   // only symmetric bonds break
+            double dx, dy, dz;
+            double r2 = separation(P, xi, xj, dx, dy, dz);
+            int gj = meta_gid(xj);
+            bool killed = false;
+            int rule = -1;
+            for (int q = 0; q < P.nrule; ++q) {
+                const Rule& r = P.rule[q];
+                if (r.kind == RK_KILL) {
+                    if (r.bt1 == t && r2 > r.r2) killed = true;
+                } else if (r.kind == RK_BREAK) {
+                    if (r.bt1 == t && r2 > r.r2) rule = q;
+                } else if (r.kind == RK_CONVERT) {
+                    if (r.bt1 == t && r2 > r.r2 && max_ok(P, ti, Ti, r.bt2) && max_ok(P, meta_type(mj), Tj, r.bt2))
+                        rule = q;
+                }
+            }
+            if (killed) {
+                S.rmlist[rm * n + i] = j;
+                ++rm;
+                if (gi < gj) ++killed_here;
+            }
+            if (rule < 0) continue;
+            if (best < 0 || r2 > best_r2 || (r2 == best_r2 && gj < best_g)) {
+                best = j;
+                best_r2 = r2;
+                best_g = gj;
+                best_rule = rule;
+            }
+        }
+    }
+    S.nomK[i] = best;
+    S.ruleK[i] = (int8_t)best_rule;
+    S.rmcnt[i] = (uint8_t)rm;
+    stat_add(S.stats, ST_KILLED, killed_here);
+}
+
+// ---- step 5: mutual breakage nominations ----------------------------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_resolve(const Params* __restrict__ Pp, Bank B, SweepBuf S,
+                                                      int64_t step) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int j = S.nomK[i];
+    int conv = 0, newp = -1;
+    if (j >= 0 && S.nomK[j] == i) {
+        int rm = S.rmcnt[i];
+        bool killed = false;
+        for (int k = 0; k < rm; ++k)
+            if (S.rmlist[k * n + i] == j) killed = true;   // killbond wins over the nomination
+        if (!killed) {
+            int gi = meta_gid(B.x[i]), gj = meta_gid(B.x[j]);
+            const Rule& r = P.rule[S.ruleK[i]];
+            if (pair_uniform(P, gi, gj, step, RNG_BREAK) < r.p) {
+                S.rmlist[rm * n + i] = j;
+                S.rmcnt[i] = (uint8_t)(rm + 1);
+                if (r.kind == RK_CONVERT) {
+                    conv = 1;
+                    newp = j;
+                    if (gi < gj) stat_add(S.stats, ST_CONVERTED, 1);
+                } else if (gi < gj) {
+                    stat_add(S.stats, ST_BROKEN, 1);
+                }
+            }
+        }
+    }
+    S.conv[i] = (uint8_t)conv;
+    S.newp[i] = newp;
+}
+
+__device__ __forceinline__ bool bond_removed(const SweepBuf& S, int n, int u, int v) {
+    int rm = S.rmcnt[u];
+    for (int k = 0; k < rm; ++k)
+        if (S.rmlist[k * n + u] == v) return true;
+    return false;
+}
+
+// ---- steps 6-8: purge, remove / convert, create ---------------------------------
+__global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ Pp, Bank B, SweepBuf S, int64_t step,
+                                                    int* __restrict__ err) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long ang_del = 0, dih_del = 0;
+    // step 6: angles and dihedrals crossing a removed bond (judged on the old graph)
+    int na = B.na[i], w = 0;
+    for (int k = 0; k < na; ++k) {
+        int4 e = B.ang[k * n + i];
+        if (bond_removed(S, n, e.x, e.y) || bond_removed(S, n, e.y, e.z)) {
+            if (e.y == i) ++ang_del;
+            continue;
+        }
+        if (w != k) B.ang[w * n + i] = e;
+        ++w;
+    }
+    B.na[i] = (uint8_t)w;
+    int nd = B.nd[i];
+    w = 0;
+    for (int k = 0; k < nd; ++k) {
+        int4 e = B.dih[k * n + i];
+        if (bond_removed(S, n, e.x, e.y) || bond_removed(S, n, e.y, e.z) || bond_removed(S, n, e.z, e.w)) {
+            if (e.y == i) ++dih_del;
+            continue;
+        }
+        if (w != k) {
+            B.dih[w * n + i] = e;
+            B.dt[w * n + i] = B.dt[k * n + i];
+        }
+        ++w;
+    }
+    B.nd[i] = (uint8_t)w;
+    // step 7: own bond entries
+    int rm = S.rmcnt[i];
+    int conv = S.conv[i];
+    int convp = conv ? S.newp[i] : -1;
+    int nb = B.nb[i];
+    w = 0;
+    for (int k = 0; k < nb; ++k) {
+        int j = B.bp[k * n + i];
+        int t = B.bt[k * n + i];
+        if (rm > 0 && bond_removed(S, n, i, j)) {
+            if (j != convp) continue;
+            t = P.rule[S.ruleK[i]].bt2;   // converted: same partner, new type
+        }
+        B.bp[w * n + i] = j;
+        B.bt[w * n + i] = (int8_t)t;
+        ++w;
+    }
+    // step 8: mutual creation nominations, no creation for converting beads
+    int j = S.nomC[i];
+    if (j >= 0 && !conv && S.nomC[j] == i && !S.conv[j]) {
+        int gi = meta_gid(B.x[i]), gj = meta_gid(B.x[j]);
+        const Rule& r = P.rule[S.ruleC[i]];
+        if (pair_uniform(P, gi, gj, step, RNG_CREATE) < r.p) {
+            if (w >= DB_MAXB) {
+                atomicOr(err, ERR_BOND_CAP);
+            } else {
+                B.bp[w * n + i] = j;
+                B.bt[w * n + i] = S.btC[i];
+                ++w;
+            }
+            S.newp[i] = j;
+            if (gi < gj) stat_add(S.stats, ST_CREATED, 1);
+        }
+    }
+    B.nb[i] = (uint8_t)w;
+    stat_add(S.stats, ST_ANG_DEL, ang_del);
+    stat_add(S.stats, ST_DIH_DEL, dih_del);
+}
+
+// ---- step 9: angles / dihedrals on paths holding a new bond -----------------------
+// Pattern match of section 2.  t(u->v) is the type u stores for its bond to v.
+// Angle ABC: bead types match and t(B->A) in S1, t(B->C) in S2; else CBA.
+// Dihedral ABCD: bead types match, t(B->A) in S1, t(C->B) or t(B->C) in S2,
+// t(C->D) in S3; else DCBA.  The first rule in table order that matches wins.
+__device__ int match_angle(const Params& P, int ta, int tb, int tc, int t_ba, int t_bc) {
+    for (int q = 0; q < P.narule; ++q) {
+        const AngRule& r = P.arule[q];
+        if (type_ok(r.b[0], ta) && type_ok(r.b[1], tb) && type_ok(r.b[2], tc) && in_mask(r.m[0], t_ba) &&
+            in_mask(r.m[1], t_bc))
+            return r.type;
+        if (type_ok(r.b[0], tc) && type_ok(r.b[1], tb) && type_ok(r.b[2], ta) && in_mask(r.m[0], t_bc) &&
+            in_mask(r.m[1], t_ba))
+            return r.type;
+    }
+    return 0;
+}
+
+__device__ int match_dihedral(const Params& P, int ta, int tb, int tc, int td, int t_ba, int t_bc, int t_cb,
+                              int t_cd) {
+    for (int q = 0; q < P.ndrule; ++q) {
+        const DihRule& r = P.drule[q];
+        if (type_ok(r.b[0], ta) && type_ok(r.b[1], tb) && type_ok(r.b[2], tc) && type_ok(r.b[3], td) &&
+            in_mask(r.m[0], t_ba) && (in_mask(r.m[1], t_cb) || in_mask(r.m[1], t_bc)) && in_mask(r.m[2], t_cd))
+            return r.type;
+        if (type_ok(r.b[0], td) && type_ok(r.b[1], tc) && type_ok(r.b[2], tb) && type_ok(r.b[3], ta) &&
+            in_mask(r.m[0], t_cd) && (in_mask(r.m[1], t_bc) || in_mask(r.m[1], t_cb)) && in_mask(r.m[2], t_ba))
+            return r.type;
+    }
+    return 0;
+}
+
+struct Gen {
+    const Params& P;
+    const Bank& B;
+    const SweepBuf& S;
+    int n;
+    bool all;
+    __device__ bool is_new(int u, int v) const { return all || S.newp[u] == v; }
+    __device__ int type_of(int s) const { return meta_type(meta_word(B.x[s])); }
+    __device__ int gid_of(int s) const { return meta_gid(B.x[s]); }
+};
+
+template <bool ALL>
+__global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict__ Pp, Bank B, SweepBuf S,
+                                                       int* __restrict__ err) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    if (P.narule == 0 && P.ndrule == 0) return;
+    Tab Ti = load_tab(B, n, i);
+    if (!ALL) {
+        // only beads within two bonds of a new bond can lie on a qualifying path
+        bool dirty = S.newp[i] >= 0;
+        for (int a = 0; a < Ti.n && !dirty; ++a) {
+            int q = Ti.p[a];
+            if (S.newp[q] >= 0) dirty = true;
+            int nq = B.nb[q];
+            for (int m = 0; m < nq && !dirty; ++m)
+                if (S.newp[B.bp[m * n + q]] >= 0) dirty = true;
+        }
+        if (!dirty) return;
+    }
+    Gen g{P, B, S, n, ALL};
+    const int gi = g.gid_of(i), ti = g.type_of(i);
+    int na = B.na[i], nd = B.nd[i];
+    unsigned long long ang_new = 0, dih_new = 0;
+    bool overflow_a = false, overflow_d = false;
+    auto push_angle = [&](int a, int b, int c, int type) {
+        if (g.gid_of(a) > g.gid_of(c)) {
+            int t = a;
+            a = c;
+            c = t;
+        }
+        if (na >= DB_MAXA) {
+            overflow_a = true;
+            return;
+        }
+        B.ang[na * n + i] = make_int4(a, b, c, type);
+        ++na;
+    };
+    auto push_dih = [&](int a, int b, int c, int d, int type) -> bool {
+        bool rev = g.gid_of(a) > g.gid_of(d);
+        if (rev) {
+            int t = a; a = d; d = t;
+            t = b; b = c; c = t;
+        }
+        if (nd >= DB_MAXD) {
+            overflow_d = true;
+            return false;
+        }
+        B.dih[nd * n + i] = make_int4(a, b, c, d);
+        B.dt[nd * n + i] = (uint8_t)type;
+        ++nd;
+        return b == i;
+    };
+    // angles with i in the centre
+    if (P.narule) {
+        for (int k1 = 0; k1 < Ti.n; ++k1)
+            for (int k2 = k1 + 1; k2 < Ti.n; ++k2) {
+                int a = Ti.p[k1], c = Ti.p[k2];
+                if (a == c) continue;
+                if (!(g.is_new(i, a) || g.is_new(i, c))) continue;
+                int t = match_angle(P, g.type_of(a), ti, g.type_of(c), Ti.t[k1], Ti.t[k2]);
+                if (t) {
+                    push_angle(a, i, c, t);
+                    ++ang_new;
+                }
+            }
+        // angles with i at an end: i - b - c
+        for (int k = 0; k < Ti.n; ++k) {
+            int b = Ti.p[k];
+            Tab Tb = load_tab(B, n, b);
+            int t_bi = tab_type_of(Tb, i);
+            int tb = g.type_of(b);
+            for (int m = 0; m < Tb.n; ++m) {
+                int c = Tb.p[m];
+                if (c == i) continue;
+                if (!(g.is_new(i, b) || g.is_new(b, c))) continue;
+                int t = match_angle(P, ti, tb, g.type_of(c), t_bi, Tb.t[m]);
+                if (t) push_angle(i, b, c, t);
+            }
+        }
+    }
+    if (P.ndrule) {
+        // dihedrals with i at an end: i - b - c - d
+        for (int k = 0; k < Ti.n; ++k) {
+            int b = Ti.p[k];
+            Tab Tb = load_tab(B, n, b);
+            int t_bi = tab_type_of(Tb, i);
+            int tb = g.type_of(b);
+            for (int m = 0; m < Tb.n; ++m) {
+                int c = Tb.p[m];
+                if (c == i) continue;
+                Tab Tc = load_tab(B, n, c);
+                int t_cb = tab_type_of(Tc, b);
+                int tc = g.type_of(c);
+                for (int q = 0; q < Tc.n; ++q) {
+                    int d = Tc.p[q];
+                    if (d == b || d == i) continue;
+                    if (!(g.is_new(i, b) || g.is_new(b, c) || g.is_new(c, d))) continue;
+                    int t = match_dihedral(P, ti, tb, tc, g.type_of(d), t_bi, Tb.t[m], t_cb, Tc.t[q]);
+                    if (t) push_dih(i, b, c, d, t);
+                }
+            }
+        }
+        // dihedrals with i second: a - i - c - d
+        for (int k1 = 0; k1 < Ti.n; ++k1) {
+            int a = Ti.p[k1];
+            int ta = g.type_of(a);
+            for (int k2 = 0; k2 < Ti.n; ++k2) {
+                if (k2 == k1) continue;
+                int c = Ti.p[k2];
+                if (c == a) continue;
+                Tab Tc = load_tab(B, n, c);
+                int t_ci = tab_type_of(Tc, i);
+                int tc = g.type_of(c);
+                for (int q = 0; q < Tc.n; ++q) {
+                    int d = Tc.p[q];
+                    if (d == i || d == a) continue;
+                    if (!(g.is_new(a, i) || g.is_new(i, c) || g.is_new(c, d))) continue;
+                    int t = match_dihedral(P, ta, ti, tc, g.type_of(d), Ti.t[k1], Ti.t[k2], t_ci, Tc.t[q]);
+                    if (t && push_dih(a, i, c, d, t)) ++dih_new;
+                }
+            }
+        }
+    }
+    B.na[i] = (uint8_t)na;
+    B.nd[i] = (uint8_t)nd;
+    if (overflow_a) atomicOr(err, ERR_ANGLE_CAP);
+    if (overflow_d) atomicOr(err, ERR_DIH_CAP);
+    if (!ALL) {
+        stat_add(S.stats, ST_ANG_NEW, ang_new);
+        stat_add(S.stats, ST_DIH_NEW, dih_new);
+    }
+    (void)gi;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+__global__ void k_clear_angles(int n, uint8_t* na, uint8_t* nd) {
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i < n) {
+        na[i] = 0;
+        nd[i] = 0;
+    }
+}
+
+static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK); }
+
+void launch_sweep(db_ctx* c, int64_t step) {
+    if (c->n == 0) return;
+    hipStream_t s = c->stream;
+    Bank& B = c->bank[c->cur];
+    unsigned g = grid_for(c->n);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, c->sw.stats, 8);
+    hipLaunchKernelGGL(k_nominate_create, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start, c->cells.list,
+                       c->sw);
+    hipLaunchKernelGGL(k_nominate_break, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
+    hipLaunchKernelGGL(k_resolve, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step);
+    hipLaunchKernelGGL(k_apply, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step, c->err_d);
+    hipLaunchKernelGGL(k_generate<false>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
+}
+
+void launch_generate_all(db_ctx* c) {
+    if (c->n == 0) return;
+    hipStream_t s = c->stream;
+    Bank& B = c->bank[c->cur];
+    unsigned g = grid_for(c->n);
+    hipLaunchKernelGGL(k_clear_angles, dim3(g), dim3(DB_BLOCK), 0, s, c->n, B.na, B.nd);
+    hipLaunchKernelGGL(k_generate<true>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
+}
+
+// ---- canonical output lists: each bond / angle / dihedral is emitted once -------
+// owner: bonds by the bead with the lower id, angles by the centre, dihedrals by
+// the second bead of the canonical (a < d) orientation.  Per-bead counts, an
+// exclusive scan, then every owner writes its entries at its offset.
+__global__ __launch_bounds__(DB_BLOCK) void k_count_owned(int n, int kind, Bank B, int* __restrict__ cnt) {
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    if (kind == 0) {
+        int gi = meta_gid(B.x[i]);
+        int nb = B.nb[i];
+        for (int k = 0; k < nb; ++k) c += gi < meta_gid(B.x[B.bp[k * n + i]]);
+    } else if (kind == 1) {
+        int na = B.na[i];
+        for (int k = 0; k < na; ++k) c += B.ang[k * n + i].y == i;
+    } else {
+        int nd = B.nd[i];
+        for (int k = 0; k < nd; ++k) c += B.dih[k * n + i].y == i;
+    }
+    cnt[i] = c;
+}
+
+__global__ __launch_bounds__(DB_BLOCK) void k_write_owned(int n, int kind, Bank B, const int* __restrict__ off,
+                                                          int32_t* __restrict__ tup, int32_t* __restrict__ typ) {
+    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int o = off[i];
+    int gi = meta_gid(B.x[i]);
+    if (kind == 0) {
+        int nb = B.nb[i];
+        for (int k = 0; k < nb; ++k) {
+            int j = B.bp[k * n + i];
+            int gj = meta_gid(B.x[j]);
+            if (!(gi < gj)) continue;
+            int tji = -1;
+            int nbj = B.nb[j];
+            for (int m = 0; m < nbj; ++m)
+                if (B.bp[m * n + j] == i) tji = B.bt[m * n + j];
+            tup[2 * o] = gi;
+            tup[2 * o + 1] = gj;
+            typ[2 * o] = B.bt[k * n + i];
+            typ[2 * o + 1] = tji;
+            ++o;
+        }
+    } else if (kind == 1) {
+        int na = B.na[i];
+        for (int k = 0; k < na; ++k) {
+            int4 e = B.ang[k * n + i];
+            if (e.y != i) continue;
+            tup[3 * o] = meta_gid(B.x[e.x]);
+            tup[3 * o + 1] = gi;
+            tup[3 * o + 2] = meta_gid(B.x[e.z]);
+            typ[o] = e.w;
+            ++o;
+        }
+    } else {
+        int nd = B.nd[i];
+        for (int k = 0; k < nd; ++k) {
+            int4 e = B.dih[k * n + i];
+            if (e.y != i) continue;
+            tup[4 * o] = meta_gid(B.x[e.x]);
+            tup[4 * o + 1] = gi;
+            tup[4 * o + 2] = meta_gid(B.x[e.z]);
+            tup[4 * o + 3] = meta_gid(B.x[e.w]);
+            typ[o] = B.dt[k * n + i];
+            ++o;
+        }
+    }
+}
+
+// counts of owned entries -> offsets in c->scan_buf (n + 1 ints; [n] = total)
+void launch_owned_offsets(db_ctx* c, int kind, int* buf) {
+    if (c->n == 0) return;
+    unsigned g = grid_for(c->n);
+    hipLaunchKernelGGL(k_count_owned, dim3(g), dim3(DB_BLOCK), 0, c->stream, c->n, kind, c->bank[c->cur], buf);
+    launch_exclusive_scan(buf, c->n, nullptr, c->cells.blocksum, c->stream);
+}
+
+void launch_write_owned(db_ctx* c, int kind, const int* off, int32_t* tup, int32_t* typ) {
+    if (c->n == 0) return;
+    unsigned g = grid_for(c->n);
+    hipLaunchKernelGGL(k_write_owned, dim3(g), dim3(DB_BLOCK), 0, c->stream, c->n, kind, c->bank[c->cur], off, tup,
+                       typ);
+}
+
+}  // namespace db

@@ -1,0 +1,321 @@
+"""Parity of the HIP path with the FP64 oracle on identical seeded inputs:
+forces (relative L2 <= 1e-12 in FP64, <= 1e-5 mixed), energies, the initial
+pattern enumeration and every sweep (bond / angle / dihedral lists bit-exact,
+statistics equal), short trajectories, shadow mode over longer runs, error
+paths and determinism."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import (both, copy_oracle_from_gpu, fig2_dynamic_setup, fig2_rules, perturbed, rel_l2,
+                        same_topology, topo_diff)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1108_4214_amd  # noqa: F401  (fails loudly without the built library)
+
+
+def _duplex_system(n_duplex, n_bp, rho, seed, scale=0.05):
+    s = synth.duplex_box(n_duplex, n_bp, rho, seed, seed + 10)
+    return perturbed(s, scale, seed)
+
+
+# ---- forces and energies ---------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+@pytest.mark.parametrize("n_duplex,n_bp,rho", [(1, 3, 0.01), (37, 7, 0.3), (150, 12, 0.5)])
+def test_forces_match_oracle(precision, tol, n_duplex, n_bp, rho):
+    s = _duplex_system(n_duplex, n_bp, rho, seed=n_duplex)
+    ff = synth.ff_t2()
+    ff.angles = {1: (10.0, 2.6)}   # off the straight angle so every angle term is active
+    g, o = both(s, ff, synth.rules_t2(), precision=precision)
+    assert rel_l2(g.forces(), o.forces()) <= tol
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forces_paper_exclusion_depth_two(precision):
+    s = _duplex_system(20, 6, 0.4, seed=5)
+    ff = synth.ff_t2()
+    ff.exclude_depth = 2
+    g, o = both(s, ff, synth.rules_t2(), precision=precision)
+    assert rel_l2(g.forces(), o.forces()) <= (FP64_TOL if precision == 0 else MIXED_TOL)
+
+
+def test_forces_fig2_model_dihedral_phases():
+    s, ff, rules = fig2_dynamic_setup()
+    ff.dihedrals = {1: (1.0, 0.3), 2: (1.0, -1.1), 3: (1.0, math.pi)}
+    lad = synth.ladder_1bead(9)
+    lad = perturbed(lad, 0.1, 3)
+    g, o = both(lad, ff, rules)
+    assert rel_l2(g.forces(), o.forces()) <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_energy_matches_oracle(precision):
+    s = _duplex_system(37, 7, 0.3, seed=2)
+    ff = synth.ff_t2()
+    g, o = both(s, ff, synth.rules_t2(), precision=precision)
+    eg, eo = g.energy(), o.energy()
+    tol = 1e-11 if precision == 0 else 2e-5
+    for k in range(6):
+        assert abs(eg[k] - eo[k]) <= tol * max(1.0, abs(eo[k])), (k, eg[k], eo[k])
+
+
+# ---- topology: initial enumeration -------------------------------------------------------
+
+def test_generation_t2_duplexes():
+    s = _duplex_system(30, 9, 0.2, seed=4)
+    g, o = both(s, synth.ff_t2(), synth.rules_t2())
+    assert same_topology(g, o), topo_diff(g, o)
+    nb, na, nd = g.counts()
+    assert na == 30 * (2 * 7 + 2 * 9) and nd == 30 * 2 * 8
+
+
+@pytest.mark.parametrize("n", [2, 3, 8])
+def test_generation_fig2_ladder(n):
+    lad = synth.ladder_1bead(n)
+    g, o = both(lad, synth.ForceField(), fig2_rules())
+    assert same_topology(g, o), topo_diff(g, o)
+
+
+def test_explicit_angle_lists_round_trip():
+    s = _duplex_system(3, 5, 0.05, seed=9)
+    o = oracle.Oracle.from_system(s, synth.ff_t2(), synth.rules_t2(), seed=1)
+    s.angles = o.angles()
+    s.dihedrals = o.dihedrals()
+    import paper_1108_4214_amd as pk
+    g = pk.System(s.n, s.L, 1).configure(s, synth.ff_t2(), synth.rules_t2())
+    assert np.array_equal(g.angles(), o.angles()) and np.array_equal(g.dihedrals(), o.dihedrals())
+
+
+# ---- the sweep on single snapshots -------------------------------------------------------
+
+def _sweep_both(system, ff, rules, seed=11, step=0):
+    g, o = both(system, ff, rules, seed=seed)
+    g.set_step(step)
+    o.set_step(step)
+    g.sweep_now()
+    o.sweep_now()
+    return g, o
+
+
+def _stats_equal(g, o):
+    sg = g.stats()
+    so, _, _ = o.stats()
+    return all(sg[k] == so[k] for k in so)
+
+
+@pytest.mark.parametrize("p", [0.1, 0.5, 1.0])
+def test_sweep_isolated_pairs(p):
+    s = synth.isolated_pairs(3000, 1.0, seed=3)
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, p), ("maxbond", 1, 0, 1)])
+    g, o = _sweep_both(s, synth.ForceField(), rules, step=17)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_sweep_dense_gas_with_bonds(seed):
+    s = synth.random_gas(2500, 14.0, seed=seed, n_types=4)
+    s.bonds = np.array([(2 * k, 2 * k + 1, 1, 1) for k in range(300)], dtype=np.int32)
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 0.7), ("create", 1, 3, 4, 1.5, 0.7),
+                                          ("break", 1, 1.2, 0.6), ("maxbond", 1, 0, 1)])
+    g, o = _sweep_both(s, synth.ForceField(), rules, seed=seed, step=40)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+    assert g.stats()["bonds_created"] > 50 and g.stats()["bonds_broken"] > 10
+
+
+def test_sweep_kill_and_purge_on_stretched_duplexes():
+    s = _duplex_system(40, 8, 0.1, seed=6, scale=0.35)
+    rules = synth.rules_t2(p=0.5, every=1, r_kill=1.4)
+    g, o = _sweep_both(s, synth.ff_t2(), rules, step=3)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+    assert g.stats()["bonds_killed"] > 5 and g.stats()["angles_removed"] > 10
+
+
+def test_sweep_conversion():
+    s = _duplex_system(40, 6, 0.1, seed=8, scale=0.3)
+    rules = synth.rules_t2(p=0.9, every=1, convert=True)
+    rules.rules.insert(0, ("angle", 2, (5, 0, 0), (synth.mask(4), synth.mask(5))))
+    g, o = _sweep_both(s, synth.ff_t2(weak=True), rules, step=5)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+    assert g.stats()["bonds_converted"] > 5
+
+
+def test_sweep_fig2_rules_paircheck_and_createdir():
+    s, ff, rules = fig2_dynamic_setup(n_strand=60, L=7.0)
+    g, o = _sweep_both(s, ff, rules, step=2)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+
+
+def test_sweep_shadowing_and_paircheck13():
+    s = synth.random_gas(1500, 11.0, seed=12, n_types=4)
+    s.bonds = np.array([(3 * k, 3 * k + 1, 4, 4) for k in range(200)] +
+                       [(3 * k + 1, 3 * k + 2, 4, 4) for k in range(200)], dtype=np.int32)
+    rules = synth.RuleSet(every=1, paircheck13=1, rules=[("create", 1, 1, 2, 1.5, 1.0), ("create", 2, 1, 2, 1.1, 0.3),
+                                                         ("createdir", 2, 3, 3, 4, 1.3, 0.8)])
+    g, o = _sweep_both(s, synth.ForceField(), rules, step=9)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+
+
+# ---- trajectories ------------------------------------------------------------------------
+
+def test_short_trajectory_fp64():
+    s = synth.single_strands(24, 6, L=11.0, seed_w=3, seed_d=4)
+    rules = synth.rules_t2(p=0.7, every=5, r_kill=1.35)
+    ff = synth.ff_t2()
+    g, o = both(s, ff, rules, seed=9)
+    g.step(20)
+    o.step(20)
+    xg, vg = g.state()
+    xo, vo = o.state()
+    d = xg - xo
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-7
+    assert same_topology(g, o), topo_diff(g, o)
+
+
+def test_shadow_mode_dynamic_run():
+    s = synth.single_strands(24, 6, L=11.0, seed_w=3, seed_d=4)
+    rules = synth.rules_t2(p=0.7, every=2, r_kill=1.35)
+    ff = synth.ff_t2()
+    import paper_1108_4214_amd as pk
+    g = pk.System(s.n, s.L, 9).configure(s, ff, rules)
+    events = 0
+    for blk in range(60):
+        g.step(2)                       # ends just before the next sweep step
+        step = g.stats()["steps"]
+        o = copy_oracle_from_gpu(g, s, ff, rules, seed=9, step=step)
+        o.sweep_now()
+        g.sweep_now()
+        assert same_topology(g, o), (blk, topo_diff(g, o))
+        so, _, _ = o.stats()
+        events += so["bonds_created"] + so["bonds_killed"]
+    assert events > 20
+
+
+def test_shadow_mode_fig2_model():
+    s, ff, rules = fig2_dynamic_setup()
+    rules.every = 3
+    import paper_1108_4214_amd as pk
+    g = pk.System(s.n, s.L, 21).configure(s, ff, rules)
+    events = 0
+    for blk in range(40):
+        g.step(3)
+        step = g.stats()["steps"]
+        o = copy_oracle_from_gpu(g, s, ff, rules, seed=21, step=step)
+        o.sweep_now()
+        g.sweep_now()
+        assert same_topology(g, o), (blk, topo_diff(g, o))
+        so, _, _ = o.stats()
+        events += so["bonds_created"] + so["bonds_killed"] + so["dihedrals_created"]
+    assert events > 20
+
+
+def test_determinism_two_runs_bitwise():
+    s = _duplex_system(60, 10, 0.5, seed=13)
+    import paper_1108_4214_amd as pk
+    out = []
+    for _ in range(2):
+        g = pk.System(s.n, s.L, 5).configure(s, synth.ff_t2(), synth.rules_t2(p=0.5, every=10))
+        g.step(50)
+        x, v = g.state()
+        out.append((x, v, g.bonds(), g.angles(), g.dihedrals()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_nve_drift_mixed_vs_fp64():
+    s = _duplex_system(40, 8, 0.3, seed=14, scale=0.02)
+    ff = synth.ff_t2(gamma=0.0, dt=0.002)
+    import paper_1108_4214_amd as pk
+    drift = []
+    for prec in (0, 1):
+        g = pk.System(s.n, s.L, 5, prec).configure(s, ff, synth.rules_t2(every=0))
+        e0 = g.energy()
+        g.step(500)
+        e1 = g.energy()
+        drift.append(abs(e1[:5].sum() - e0[:5].sum()) / s.n)
+    assert drift[0] < 1e-3 and drift[1] < 1e-3, drift
+
+
+# ---- edge cases and error paths -----------------------------------------------------------
+
+def test_tiny_systems():
+    import paper_1108_4214_amd as pk
+    for n in (1, 2):
+        s = synth.random_gas(n, 5.0, seed=1)
+        g, o = both(s, synth.ForceField(), synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 1.0)]))
+        assert rel_l2(g.forces() + 1e-300, o.forces() + 1e-300) <= 1e-12 or np.allclose(g.forces(), o.forces())
+        g.step(3)
+        o.step(3)
+        assert np.allclose(g.state()[0], o.state()[0], atol=1e-10)
+    g = pk.System(0, 5.0, 1)
+    g.configure(synth.random_gas(0, 5.0), synth.ForceField(), None)
+    g.step(2)
+    assert g.counts() == (0, 0, 0)
+
+
+def test_bond_capacity_overflow_is_reported():
+    import paper_1108_4214_amd as pk
+    # bead 0 already holds four bonds; a creation rule without maxbond would add a fifth
+    pos = [[5, 5, 5], [6, 5, 5], [4, 5, 5], [5, 6, 5], [5, 4, 5], [5, 5, 6.2]]
+    x = np.array(pos, dtype=float)
+    s = synth.System(L=12.0, x=x, v=np.zeros_like(x), type=np.array([1, 5, 5, 5, 5, 2], dtype=np.int32),
+                     reactive=np.ones(6, dtype=np.uint8),
+                     bonds=np.array([(0, k, 4, 4) for k in range(1, 5)], dtype=np.int32))
+    g = pk.System(s.n, s.L, 1).configure(s, synth.ForceField(eps=0.0),
+                                         synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 1.0)]))
+    with pytest.raises(pk.DynBondError) as e:
+        g.sweep_now()
+    assert e.value.code == pk.DB_ECAPACITY
+
+
+def test_invalid_arguments_rejected():
+    import paper_1108_4214_amd as pk
+    g = pk.System(4, 10.0, 1)
+    with pytest.raises(pk.DynBondError):
+        pk.db_set_state(g.ctx, np.full((4, 3), 11.0), None, np.ones(4, np.int32))
+    with pytest.raises(pk.DynBondError):
+        pk.db_bond_create(g.ctx, 1, 1, 2, 1.5, 1.5)
+    with pytest.raises(pk.DynBondError):
+        pk.db_step(g.ctx, 1)   # no state yet
+
+
+# ---- full-size workload (1,000,000 beads): forces and one sweep against the oracle -------
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_full_size_c3_forces(precision, tol, c3_workload):
+    w = c3_workload
+    g, o = both(w.system, w.ff, w.rules, seed=w.seed, precision=precision)
+    assert rel_l2(g.forces(), o.forces()) <= tol
+
+
+def test_full_size_c3_sweep(c3_workload):
+    w = c3_workload
+    s = perturbed(w.system, 0.25, 1)   # stretch some hybridization bonds past the kill distance
+    g, o = _sweep_both(s, w.ff, w.rules, seed=w.seed, step=0)
+    assert same_topology(g, o)
+    assert _stats_equal(g, o)
+
+
+@pytest.fixture(scope="module")
+def c3_workload():
+    return synth.c3()
