@@ -1,0 +1,154 @@
+#!/usr/bin/env python3
+"""Throughput of the dynamic-bonding hot path on one MI355X.
+
+Workload: 12,500 random 40-nt strands paired into 6,250 pre-hybridized duplexes
+of the 2-bead/nucleotide model (1,000,000 beads, density 0.5, box 125.99 sigma),
+WCA pairs, harmonic bonds, straight backbone and rung angles, cis stacking
+dihedrals, Langevin thermostat on a 0.5 -> 1.5 temperature ramp over 1e5 steps,
+bond sweep (create within 1.5 sigma with p = 0.5, kill beyond 2.0 sigma, at most
+one hybridization bond per bead) every 10 steps.  Inputs are synthetic and
+seeded (synth.c3).
+
+One step = one pass of the whole hot path (cell-list upkeep, fused force +
+integrate kernel, and on every 10th step the sweep).  Prints one JSON line.
+``value`` is the mixed-precision path (FP32 force arithmetic, FP64 positions,
+differences, accumulation and integration); the plain FP64 path is measured in
+the same run and reported under ``fp64``.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_bead_step(b, a, d, every):
+    """Bytes the method must move per bead and step: position and velocity read and
+    written in FP64 (96), the bead type (1), one read of every bond (2 ids + 2 types,
+    10 B), angle (3 ids + type, 13 B) and dihedral (4 ids + type, 17 B) counted once,
+    plus the sweep's read of positions, types, counts and bonds amortised over its
+    interval."""
+    per_step = 97.0 + 10.0 * b + 13.0 * a + 17.0 * d
+    sweep = (25.0 + 10.0 * b) / every if every > 0 else 0.0
+    return per_step, per_step + sweep
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+
+    import paper_1108_4214_amd as pk
+
+    s = w.system
+    g = pk.System(s.n, s.L, w.seed, precision).configure(s, w.ff, w.rules)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    pk.db_step_kernel_time(g.ctx)          # reset the tally
+    pk.db_profile(g.ctx, 1)
+    st0 = g.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pk.db_profile(g.ctx, 0)
+    kern_us, launches = pk.db_step_kernel_time(g.ctx)
+    st1 = g.stats()
+    nb, na, nd = g.counts()
+    out = {
+        "seconds": t1 - t0,
+        "bead_steps_per_s": s.n * steps / (t1 - t0),
+        "ms_per_step": 1e3 * (t1 - t0) / steps,
+        "step_kernel_us": kern_us,
+        "step_kernel_launches": launches,
+        "sweeps": st1["sweeps"] - st0["sweeps"],
+        "rebuilds": st1["rebuilds"] - st0["rebuilds"],
+        "rollbacks": st1["rollbacks"] - st0["rollbacks"],
+        "bonds_created": st1["cum_bonds_created"] - st0["cum_bonds_created"],
+        "bonds_killed": st1["cum_bonds_killed"] - st0["cum_bonds_killed"],
+        "topology_per_bead": [nb / s.n, na / s.n, nd / s.n],
+    }
+    g.close()
+    return out
+
+
+def cpu_baseline(w, steps):
+    import oracle
+
+    s = w.system
+    o = oracle.Oracle.from_system(s, w.ff, w.rules, seed=w.seed)
+    t0 = time.perf_counter()
+    o.step(steps)
+    t1 = time.perf_counter()
+    return {"value": s.n * steps / (t1 - t0), "unit": "bead-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"the oracle (single thread) advancing the same 1,000,000-bead workload {steps} steps "
+                      f"from its initial snapshot, {steps // max(1, w.rules.every)} sweeps included, "
+                      f"{t1 - t0:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build: a large box "
+              "would shard by spatial domains, which this build does not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    w = synth.c3()
+    every = w.rules.every
+    mixed = run_gpu(w, 1, args.steps, args.warmup)
+    fp64 = run_gpu(w, 0, args.steps, args.warmup)
+    b, a, d = mixed["topology_per_bead"]
+    kernel_bytes, step_bytes = algorithmic_bytes_per_bead_step(b, a, d, every)
+    n = w.system.n
+    achieved = kernel_bytes * n / (mixed["step_kernel_us"] * 1e-6) / 1e9 if mixed["step_kernel_us"] > 0 else 0.0
+    line = {
+        "metric": "bead-steps/s at 1M beads incl. bond sweep; mixed vs FP64 on same GPU",
+        "value": mixed["bead_steps_per_s"],
+        "unit": "bead-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "12500 x 40-nt strands in 6250 pre-hybridized duplexes, 2-bead model, "
+                               "1000000 beads, rho=0.5, T ramp 0.5->1.5 over 1e5 steps, sweep every 10 steps",
+                   "beads": n, "sweep_every": every, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step<float> (fused pair + bonded + Langevin + velocity Verlet)",
+                     "bytes_per_bead_step": kernel_bytes, "beads_per_launch": n,
+                     "launch_us": mixed["step_kernel_us"], "launches_timed": mixed["step_kernel_launches"]},
+        "path_roofline_frac": step_bytes * mixed["bead_steps_per_s"] / (HBM_PEAK_GBS * 1e9),
+        "fp64": {"value": fp64["bead_steps_per_s"], "ms_per_step": fp64["ms_per_step"],
+                 "step_kernel_us": fp64["step_kernel_us"],
+                 "roofline_frac": kernel_bytes * n / (fp64["step_kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+                 if fp64["step_kernel_us"] > 0 else None},
+        "mixed_detail": mixed,
+        "fp64_detail": fp64,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -19,7 +19,7 @@
  *    is device memory on the handle's device).  Inputs are copied in; outputs
  *    are written into caller-allocated buffers of the documented size.
  *  - Arrays of 3-vectors are row-major N x 3 doubles.
- *  - Bead-type wildcard: DB_ANY (0).  Bond-type sets are 32-bit masks with bit
+ *  - Bead types are 1..31, wildcard DB_ANY (0).  Bond-type sets are 32-bit masks with bit
  *    t set for bond type t (types 1..31); DB_ALL_BONDTYPES matches any type.
  *  - Rule order is call order: when several rules apply to one bead pair the
  *    last one wins (section 2; appendix steps 2-3).

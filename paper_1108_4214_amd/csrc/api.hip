@@ -591,7 +591,7 @@ int db_set_state(db_ctx* c, const double* x, const double* v, const int32_t* typ
         if (!std::isfinite(vs[i])) return fail(c, DB_EINVAL, "velocity of bead %zu not finite", i / 3);
     }
     for (size_t i = 0; i < n; ++i)
-        if (ts[i] < 1 || ts[i] > 255) return fail(c, DB_EINVAL, "bead %zu has type %d outside 1..255", i, ts[i]);
+        if (ts[i] < 1 || ts[i] > 31) return fail(c, DB_EINVAL, "bead %zu has type %d outside 1..31", i, ts[i]);
     h.x.swap(xs);
     h.v.swap(vs);
     h.type.swap(ts);
@@ -779,7 +779,7 @@ static int add_rule(db_ctx* c, Rule r) {
 }
 
 static bool bad_bt(int t) { return t < 1 || t >= DB_MAXT; }
-static bool bad_bead(int b) { return b < 0 || b > 255; }
+static bool bad_bead(int b) { return b < 0 || b > 31; }
 static bool bad_p(double p) { return !(p >= 0.0 && p <= 1.0); }
 
 int db_sweep_every(db_ctx* c, int32_t every, int pc13, int pc14) {
