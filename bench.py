@@ -38,13 +38,16 @@ def algorithmic_bytes_per_bead_step(b, a, d, every):
     return per_step, per_step + sweep
 
 
-def run_gpu(w, precision, steps, warmup):
+def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
     import torch
 
     import paper_1108_4214_amd as pk
 
     s = w.system
-    g = pk.System(s.n, s.L, w.seed, precision).configure(s, w.ff, w.rules)
+    g = pk.System(s.n, s.L, w.seed, precision)
+    if skin is not None:
+        pk.db_tune(g.ctx, skin, permute_every or 1)
+    g.configure(s, w.ff, w.rules)
     g.step(warmup)
     torch.cuda.synchronize()
     pk.db_step_kernel_time(g.ctx)          # reset the tally
@@ -97,6 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skin", type=float, default=None)
+    ap.add_argument("--permute-every", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build: a large box "
@@ -110,8 +115,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     w = synth.c3()
     every = w.rules.every
-    mixed = run_gpu(w, 1, args.steps, args.warmup)
-    fp64 = run_gpu(w, 0, args.steps, args.warmup)
+    mixed = run_gpu(w, 1, args.steps, args.warmup, args.skin, args.permute_every)
+    fp64 = run_gpu(w, 0, args.steps, args.warmup, args.skin, args.permute_every)
     b, a, d = mixed["topology_per_bead"]
     kernel_bytes, step_bytes = algorithmic_bytes_per_bead_step(b, a, d, every)
     n = w.system.n

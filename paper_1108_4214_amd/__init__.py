@@ -31,7 +31,7 @@ EXPORTS = [
     "db_bond_create_dir", "db_bond_break", "db_bond_kill", "db_bond_convert", "db_max_bonds",
     "db_angle_pattern", "db_dihedral_pattern", "db_step", "db_sweep_now", "db_forces", "db_energy",
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
-    "db_get_stats", "db_set_step", "db_profile", "db_step_kernel_time",
+    "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time",
 ]
 
 STAT_FIELDS = [
@@ -97,6 +97,7 @@ _SIG = {
     "db_get_dihedrals": [_P, _P, _P],
     "db_get_stats": [_P, C.POINTER(db_stats)],
     "db_set_step": [_P, _i64],
+    "db_tune": [_P, _d, _i32],
     "db_profile": [_P, _int],
     "db_step_kernel_time": [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
 }
@@ -332,6 +333,10 @@ def db_get_stats(ctx):
 
 def db_set_step(ctx, step):
     _check(ctx, _lib.db_set_step(ctx, int(step)))
+
+
+def db_tune(ctx, skin, permute_every):
+    _check(ctx, _lib.db_tune(ctx, float(skin), int(permute_every)))
 
 
 def db_profile(ctx, enable):

@@ -26,16 +26,29 @@ using namespace db;
 namespace {
 
 const int kMaxBlock = 64;
-const double kSkinDefault = 0.3;
+const double kSkinDefault = 0.6;
 
+// host memory the device writes its end-of-block report into (mapped, pinned)
 struct Pinned {
     int err;
     int pad;
-    float vmax2[kMaxBlock];
+    float vmax2[kMaxBlock];        // largest |v|^2 of each step of the block
     unsigned long long stats[8];
     double energy[6];
     int total[4];
 };
+
+__global__ void k_report(const float* __restrict__ vmax2, int len, const int* __restrict__ err,
+                         const unsigned long long* __restrict__ stats, int with_stats, Pinned* __restrict__ out) {
+    int q = threadIdx.x;
+    if (q < len) {
+        float m = 0.0f;
+        for (int w = 0; w < DB_VMAX_SPREAD; ++w) m = fmaxf(m, vmax2[q * DB_VMAX_SPREAD + w]);
+        out->vmax2[q] = m;
+    }
+    if (q == 0) out->err = *err;
+    if (with_stats && q < 8) out->stats[q] = stats[q];
+}
 
 struct HostSys {
     std::vector<double> x, v;
@@ -54,6 +67,7 @@ struct db_host_ext {
     bool dev_valid = false;   // device holds the current state
     int dev_error = 0;        // latched device error code
     Pinned* pin = nullptr;
+    Pinned* pin_dev = nullptr;   // device view of pin
     int* tmp_n1 = nullptr;    // n + 1 ints
 };
 
@@ -140,14 +154,17 @@ static size_t layout(db_ctx* c, bool assign) {
     put(S.conv, n);
     put(S.newp, 4 * n);
     put(S.stats, 8 * 8);
+    put(c->nlist.nl, 4 * (size_t)DB_NLCAP * n);
+    put(c->nlist.cnt, n);
     put(c->cells.cnt, 4 * nc);
     put(c->cells.start, 4 * (nc + 1));
     put(c->cells.list, 4 * n);
+    put(c->cells.xs, 16 * n);
     put(c->cells.cellid, 4 * n);
     put(c->cells.blocksum, 4 * (size_t)blocksum_ints((int)std::max(n, nc) + 1));
     put(c->slot_of_gid, 4 * n);
     put(c->err_d, 64);
-    put(c->vmax2, 4 * kMaxBlock);
+    put(c->vmax2, 4 * (size_t)kMaxBlock * DB_VMAX_SPREAD);
     put(c->red, 8 * 6 * ((n + DB_BLOCK - 1) / DB_BLOCK + 1));
     put(c->dp, sizeof(Params));
     int* t1 = nullptr;
@@ -169,9 +186,12 @@ static int ensure_memory(db_ctx* c) {
     layout(c, true);
     if (!ext(c).pin) {
         void* p = nullptr;
-        HIPCHK(c, hipHostMalloc(&p, sizeof(Pinned), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc(&p, sizeof(Pinned), hipHostMallocMapped));
         ext(c).pin = (Pinned*)p;
         memset(p, 0, sizeof(Pinned));
+        void* dptr = nullptr;
+        HIPCHK(c, hipHostGetDevicePointer(&dptr, p, 0));
+        ext(c).pin_dev = (Pinned*)dptr;
     }
     // zero the counters that kernels assume start at zero
     launch_fill_int(c->cells.cnt, 0, (size_t)ncell_cap(c->n), c->stream);
@@ -188,7 +208,9 @@ static void compute_grid(db_ctx* c) {
     Params& P = c->hp;
     double rc = P.have_pair ? std::sqrt(P.rc2) : 0.0;
     double rcr = std::sqrt(std::max(P.rmax2_create, 0.0));
-    double amin = std::max(rc + c->skin, rcr);
+    double rnl = P.have_pair ? rc + c->skin : 0.0;
+    P.rnl2 = rnl * rnl;
+    double amin = std::max(rnl, rcr);
     if (!(amin > 0)) amin = c->L;
     int nc = (int)std::floor(c->L / (amin * (1.0 + 1e-9)));
     if (nc < 1) nc = 1;
@@ -208,10 +230,12 @@ static void compute_grid(db_ctx* c) {
     }
 }
 
+// Largest displacement any bead may make between neighbour-list builds: a pair
+// that comes within the cutoff was within cutoff + skin when the list was built
+// as long as neither bead moved more than half the skin.
 static double skin_of(const db_ctx* c) {
-    if (c->hp.nc < 3) return INFINITY;   // every bead is visited
-    double rc = c->hp.have_pair ? std::sqrt(c->hp.rc2) : 0.0;
-    return c->L / c->hp.nc - rc;
+    if (!c->hp.have_pair) return INFINITY;
+    return 0.5 * c->skin;
 }
 
 static int upload_params(db_ctx* c) {
@@ -453,17 +477,18 @@ static int check_device_error(db_ctx* c) {
     db_host_ext& X = ext(c);
     int e = X.pin->err;
     if (!e) return DB_OK;
-    int code = (e & (ERR_BOND_CAP | ERR_ANGLE_CAP | ERR_DIH_CAP)) ? DB_ECAPACITY : DB_ENONFINITE;
+    int code = (e & (ERR_BOND_CAP | ERR_ANGLE_CAP | ERR_DIH_CAP | ERR_NLIST)) ? DB_ECAPACITY : DB_ENONFINITE;
     X.dev_error = code;
-    return fail(c, code, "device reported %s%s%s%s",
+    return fail(c, code, "device reported %s%s%s%s%s",
                 (e & ERR_BOND_CAP) ? "bond-table overflow " : "", (e & ERR_ANGLE_CAP) ? "angle-table overflow " : "",
                 (e & ERR_DIH_CAP) ? "dihedral-table overflow " : "",
+                (e & ERR_NLIST) ? "neighbour-list overflow " : "",
                 (e & ERR_NONFINITE) ? "non-finite or escaping position" : "");
 }
 
-static void rebuild(db_ctx* c, bool permute) {
+static void rebuild(db_ctx* c, bool permute, bool save = false) {
     launch_build_cells(c);
-    if (permute) launch_permute(c);
+    if (permute) launch_permute(c, save);
     c->rebuilds++;
 }
 
@@ -523,7 +548,7 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->skin = kSkinDefault;
     c->swept_step = -1;
     c->rebuild_interval = 8;
-    c->permute_every = 1;
+    c->permute_every = 4;
     c->vmax_est = 0;
     HostSys& h = c->hx->h;
     h.x.assign(3 * (size_t)n, 0.0);
@@ -912,22 +937,22 @@ int db_step(db_ctx* c, int64_t nsteps) {
         int64_t len = std::min<int64_t>(nsteps, std::min(c->rebuild_interval, kMaxBlock));
         if (every > 0) len = std::min<int64_t>(len, every - (k0 % every));
         const bool permute = (c->rebuild_count++ % c->permute_every) == 0;
-        rebuild(c, permute);
+        const bool guard = std::isfinite(skin) && len > 1;
+        rebuild(c, permute, guard);
         if (sweep_due) {
             launch_sweep(c, k0);
-            HIPCHK(c, hipMemcpyAsync(pin->stats, c->sw.stats, 64, hipMemcpyDeviceToHost, s));
             c->swept_step = k0;
         }
-        const bool guard = std::isfinite(skin) && len > 1;
+        launch_build_nlist(c);   // after the sweep: exclusions follow the new bonds
         Bank& B = c->bank[c->cur];
-        if (guard) {
+        if (guard && !permute) {
             HIPCHK(c, hipMemcpyAsync(c->xsave, B.x, 32 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
             HIPCHK(c, hipMemcpyAsync(c->vsave, B.v, 24 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
         }
-        launch_fill_int((int*)c->vmax2, 0, (size_t)len, s);
+        launch_fill_int((int*)c->vmax2, 0, (size_t)len * DB_VMAX_SPREAD, s);
         for (int64_t q = 0; q < len; ++q) launch_timed_step(c, k0 + q, (int)q);
-        HIPCHK(c, hipMemcpyAsync(pin->vmax2, c->vmax2, 4 * (size_t)len, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_report, dim3(1), dim3(kMaxBlock), 0, s, c->vmax2, (int)len, c->err_d, c->sw.stats,
+                           sweep_due ? 1 : 0, X.pin_dev);
         HIPCHK(c, hipStreamSynchronize(s));
         HIPCHK(c, hipGetLastError());
         if (c->profile) {
@@ -952,6 +977,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
             HIPCHK(c, hipMemcpyAsync(Bc.v, c->vsave, 24 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
             for (int64_t q = 0; q < len; ++q) {
                 rebuild(c, false);
+                launch_build_nlist(c);
                 launch_step(c, k0 + q, 0);
             }
             HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -995,12 +1021,14 @@ int db_forces(db_ctx* c, double* f, int on_device) {
     int rc = ready(c);
     if (rc) return rc;
     rebuild(c, false);
+    launch_build_nlist(c);
     double* d = on_device ? f : (double*)scratch(c, 24 * (size_t)c->n);
     launch_forces(c, d);
     if (!on_device && c->n) HIPCHK(c, hipMemcpyAsync(f, d, 24 * (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&ext(c).pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGetLastError());
-    return DB_OK;
+    return check_device_error(c);
 }
 
 int db_energy(db_ctx* c, double out[6]) {
@@ -1107,6 +1135,14 @@ int db_set_step(db_ctx* c, int64_t step) {
     if (!c || step < 0) return DB_EINVAL;
     c->step = step;
     c->swept_step = -1;
+    return DB_OK;
+}
+
+int db_tune(db_ctx* c, double skin, int32_t permute_every) {
+    if (!c || !(skin > 0) || !std::isfinite(skin) || permute_every < 1) return DB_EINVAL;
+    c->skin = skin;
+    c->permute_every = permute_every;
+    c->params_dirty = true;
     return DB_OK;
 }
 

@@ -15,6 +15,8 @@
 #define DB_MAXT 32
 #define DB_MAXRULES 32
 #define DB_BLOCK 256
+#define DB_NLCAP 64          // neighbour-list entries per bead
+#define DB_VMAX_SPREAD 64    // words per step over which the speed maxima are spread
 
 namespace db {
 
@@ -24,7 +26,7 @@ enum RuleKind { RK_CREATE = 1, RK_CREATEDIR = 2, RK_BREAK = 3, RK_KILL = 4, RK_C
 enum RngKind : uint32_t { RNG_LANGEVIN = 0u, RNG_CREATE = 1u, RNG_BREAK = 2u };
 
 // device error word bits
-enum ErrBit : int { ERR_BOND_CAP = 1, ERR_ANGLE_CAP = 2, ERR_DIH_CAP = 4, ERR_NONFINITE = 8, ERR_CELL = 16 };
+enum ErrBit : int { ERR_BOND_CAP = 1, ERR_ANGLE_CAP = 2, ERR_DIH_CAP = 4, ERR_NONFINITE = 8, ERR_NLIST = 16 };
 
 struct Rule {
     int kind, bt1, bt2, b1, b2;
@@ -45,6 +47,7 @@ struct Params {
     // WCA
     int have_pair, excl_depth;
     double eps, sig2, rc2;
+    double rnl2;         // neighbour-list cutoff squared (pair cutoff + skin)
     // bonded
     double bK[DB_MAXT], bR0[DB_MAXT];
     double aK[DB_MAXT], aT0[DB_MAXT], aPiMinusT0[DB_MAXT];
@@ -95,10 +98,17 @@ struct SweepBuf {
     unsigned long long* stats;   // [8] counters of the sweep
 };
 
+// Verlet neighbour list: entry k of bead s at nl[k * n + s] (slots), count in cnt
+struct NList {
+    int* nl;          // [DB_NLCAP][n]
+    uint8_t* cnt;     // [n]
+};
+
 struct Cells {
     int* cnt;         // [ncell]
     int* start;       // [ncell + 1]
     int* list;        // [n] slots, cell by cell, ascending within a cell
+    float4* xs;       // [n] in list order: float x, y, z and the slot (bits) of each entry
     int* cellid;      // [n]
     int* blocksum;    // scan scratch
 };
@@ -133,9 +143,11 @@ struct db_ctx {
     double* vsave;
     db::SweepBuf sw;
     db::Cells cells;
+    db::NList nlist;
+    double nl_skin;      // neighbour-list cutoff minus pair cutoff
     int* slot_of_gid;    // [n]
     int* err_d;          // device error word
-    float* vmax2;        // [max block length] max |v|^2 after each step (as float bits)
+    float* vmax2;        // [max block length][DB_VMAX_SPREAD] max |v|^2 after each step (float bits)
     double* red;         // reduction scratch
     int64_t* cnt64;      // small device counters
     void* pinned;        // pinned host staging
@@ -165,10 +177,12 @@ namespace db {
 // kernels_cells.hip
 void launch_fill_int(int* p, int value, size_t count, hipStream_t s);
 void launch_build_cells(db_ctx* c);                  // bin + scan + scatter + in-cell sort
-void launch_permute(db_ctx* c);                      // reorder all per-bead state by the cell list
+void launch_permute(db_ctx* c, bool save);           // reorder all per-bead state by the cell list
+                                                     // (save: also copy x, v to the rollback buffers)
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s);
 
 // kernels_force.hip
+void launch_build_nlist(db_ctx* c);                  // Verlet list from the current cell list
 void launch_step(db_ctx* c, int64_t step, int slot_in_block);
 void launch_forces(db_ctx* c, double* f_gid_order);
 void launch_energy(db_ctx* c, double* out6_device);

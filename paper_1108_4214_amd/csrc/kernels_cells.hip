@@ -132,9 +132,11 @@ __global__ __launch_bounds__(DB_BLOCK) void k_scatter(int n, const int* __restri
 }
 
 // ascending slot order inside each cell makes the list independent of the
-// arrival order of the atomics above
+// arrival order of the atomics above; the float copy of the positions is then
+// written in list order, so a scan over neighbouring cells reads contiguous runs
 __global__ __launch_bounds__(DB_BLOCK) void k_cellsort(int ncell, const int* __restrict__ start,
-                                                        int* __restrict__ list) {
+                                                        int* __restrict__ list, const double4* __restrict__ x,
+                                                        float4* __restrict__ xs) {
     int c = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (c >= ncell) return;
     int s0 = start[c], s1 = start[c + 1];
@@ -146,6 +148,11 @@ __global__ __launch_bounds__(DB_BLOCK) void k_cellsort(int ncell, const int* __r
             --b;
         }
         list[b + 1] = v;
+    }
+    for (int a = s0; a < s1; ++a) {
+        int j = list[a];
+        double4 xj = x[j];
+        xs[a] = make_float4((float)xj.x, (float)xj.y, (float)xj.z, __int_as_float(j));
     }
 }
 
@@ -163,7 +170,8 @@ void launch_build_cells(db_ctx* c) {
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.cellid, c->cells.start,
                            c->cells.cnt, c->cells.list);
         unsigned cb = (unsigned)((ncell + DB_BLOCK - 1) / DB_BLOCK);
-        hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(DB_BLOCK), 0, s, ncell, c->cells.start, c->cells.list);
+        hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(DB_BLOCK), 0, s, ncell, c->cells.start, c->cells.list, B.x,
+                           c->cells.xs);
     }
 }
 
@@ -174,15 +182,24 @@ __global__ __launch_bounds__(DB_BLOCK) void k_newslot(int n, const int* __restri
 }
 
 __global__ __launch_bounds__(DB_BLOCK) void k_permute(int n, Bank src, Bank dst, int* __restrict__ list,
-                                                       const int* __restrict__ newslot, int* __restrict__ slot_of_gid) {
+                                                       const int* __restrict__ newslot, int* __restrict__ slot_of_gid,
+                                                       double4* __restrict__ xsave, double* __restrict__ vsave,
+                                                       float4* __restrict__ xs) {
     int s = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (s >= n) return;
     int o = list[s];
     double4 x = src.x[o];
+    double vx = src.v[o], vy = src.v[n + o], vz = src.v[2 * n + o];
     dst.x[s] = x;
-    dst.v[s] = src.v[o];
-    dst.v[n + s] = src.v[n + o];
-    dst.v[2 * n + s] = src.v[2 * n + o];
+    dst.v[s] = vx;
+    dst.v[n + s] = vy;
+    dst.v[2 * n + s] = vz;
+    if (xsave) {   // copy kept for re-running the block
+        xsave[s] = x;
+        vsave[s] = vx;
+        vsave[n + s] = vy;
+        vsave[2 * n + s] = vz;
+    }
     slot_of_gid[meta_gid(x)] = s;
     int nb = src.nb[o];
     dst.nb[s] = (uint8_t)nb;
@@ -204,9 +221,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_permute(int n, Bank src, Bank dst,
         dst.dt[k * n + s] = src.dt[k * n + o];
     }
     list[s] = s;   // the cells now hold contiguous slot ranges
+    xs[s].w = __int_as_float(s);
 }
 
-void launch_permute(db_ctx* c) {
+void launch_permute(db_ctx* c, bool save) {
     const int n = c->n;
     if (n == 0) return;
     hipStream_t s = c->stream;
@@ -214,7 +232,8 @@ void launch_permute(db_ctx* c) {
     int* newslot = c->cells.cellid;   // the bin ids are no longer needed
     hipLaunchKernelGGL(k_newslot, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, newslot);
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->bank[c->cur], c->bank[1 - c->cur],
-                       c->cells.list, newslot, c->slot_of_gid);
+                       c->cells.list, newslot, c->slot_of_gid, save ? c->xsave : (double4*)nullptr,
+                       save ? c->vsave : (double*)nullptr, c->cells.xs);
     c->cur = 1 - c->cur;
 }
 

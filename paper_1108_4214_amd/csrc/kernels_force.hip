@@ -10,7 +10,7 @@
 // R is the force arithmetic type: double (DB_FP64) or float (DB_MIXED).  In
 // both, coordinate differences with the minimum image, force accumulation,
 // energies, the thermostat and the integration are double.
-#include "db_device.h"
+#include "cell_scan.h"
 
 namespace db {
 
@@ -28,6 +28,21 @@ template <>
 __device__ __forceinline__ double r_sqrt<double>(double v) { return sqrt(v); }
 template <>
 __device__ __forceinline__ float r_sqrt<float>(float v) { return sqrtf(v); }
+// reciprocal and reciprocal square root: IEEE in double; in float the native
+// single-instruction approximations (about 1 ulp), far inside the float path's
+// error budget
+template <typename R>
+__device__ __forceinline__ R r_rcp(R v);
+template <>
+__device__ __forceinline__ double r_rcp<double>(double v) { return 1.0 / v; }
+template <>
+__device__ __forceinline__ float r_rcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <typename R>
+__device__ __forceinline__ R r_rsqrt(R v);
+template <>
+__device__ __forceinline__ double r_rsqrt<double>(double v) { return 1.0 / sqrt(v); }
+template <>
+__device__ __forceinline__ float r_rsqrt<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <typename R>
 __device__ __forceinline__ R r_atan2(R y, R x);
 template <>
@@ -60,9 +75,10 @@ __device__ __forceinline__ void pair_term(const Params& P, const double4& xi, co
     dz = min_image(xj.z - xi.z, P.L, P.hL);
     R rx = (R)dx, ry = (R)dy, rz = (R)dz;
     R r2 = (rx * rx + ry * ry) + rz * rz;
-    R sr2 = (R)P.sig2 / r2;
+    R ir2 = r_rcp<R>(r2);
+    R sr2 = (R)P.sig2 * ir2;
     R sr6 = sr2 * sr2 * sr2;
-    R fr = (R)24.0 * (R)P.eps * ((R)2.0 * sr6 * sr6 - sr6) / r2;   // -dU/dr / r
+    R fr = (R)24.0 * (R)P.eps * ((R)2.0 * sr6 * sr6 - sr6) * ir2;   // -dU/dr / r
     a.fx -= (double)(fr * rx);
     a.fy -= (double)(fr * ry);
     a.fz -= (double)(fr * rz);
@@ -118,23 +134,106 @@ __device__ void pair_forces(const Params& P, const Bank& B, const int* __restric
     }
 }
 
-// harmonic bond U = K (r - r0)^2 with the type bead i stores
+// Verlet list of bead i: every bead within the list cutoff (pair cutoff plus a
+// skin) that is not excluded, from the 27 cells of the current cell list.  The
+// float prefilter carries a 1e-4 relative margin, so the list is a superset of
+// the pairs within the cutoff in double.
+__global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restrict__ Pp, Bank B,
+                                                          const int* __restrict__ cstart,
+                                                          const float4* __restrict__ xs, NList NL,
+                                                          int* __restrict__ err) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double4 xi = B.x[i];
+    const int nb = B.nb[i];
+    const int p0 = nb > 0 ? B.bp[i] : -1;
+    const int p1 = nb > 1 ? B.bp[n + i] : -1;
+    const int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
+    const int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
+    int cnt = 0;
+    scan_cells(P, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, float) {
+        if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
+        if (P.excl_depth >= 2 && two_bonds_apart(B, n, j, nb, p0, p1, p2, p3)) return;
+        if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
+        ++cnt;
+    });
+    if (cnt > DB_NLCAP) {
+        atomicOr(err, ERR_NLIST);
+        cnt = DB_NLCAP;
+    }
+    NL.cnt[i] = (uint8_t)cnt;
+}
+
+// pair forces from the Verlet list (exclusions were applied when it was built).
+// Entries are taken four at a time: the four indices, then the four positions are
+// requested before any of them is used, so one bead keeps several loads in flight.
+template <typename R>
+__device__ __forceinline__ void pair_one(const Params& P, const double4& xi, const double4& xj, R rc2, Acc<R>& a) {
+    R rx = (R)min_image(xj.x - xi.x, P.L, P.hL);
+    R ry = (R)min_image(xj.y - xi.y, P.L, P.hL);
+    R rz = (R)min_image(xj.z - xi.z, P.L, P.hL);
+    R r2 = (rx * rx + ry * ry) + rz * rz;
+    if (r2 < rc2) {
+        R ir2 = r_rcp<R>(r2);
+        R sr2 = (R)P.sig2 * ir2;
+        R sr6 = sr2 * sr2 * sr2;
+        R fr = (R)24.0 * (R)P.eps * ((R)2.0 * sr6 * sr6 - sr6) * ir2;
+        a.fx -= (double)(fr * rx);
+        a.fy -= (double)(fr * ry);
+        a.fz -= (double)(fr * rz);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void list_pair_forces(const Params& P, const Bank& B, const NList& NL, int i,
+                                                 const double4& xi, Acc<R>& a) {
+    const int n = P.n;
+    const R rc2 = (R)P.rc2;
+    const int m = NL.cnt[i];
+    for (int k0 = 0; k0 < m; k0 += 4) {
+        int j[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) j[q] = (k0 + q < m) ? NL.nl[(k0 + q) * n + i] : i;
+        double4 xj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xj[q] = B.x[j[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (k0 + q < m) pair_one<R>(P, xi, xj[q], rc2, a);
+    }
+}
+
+// harmonic bond U = K (r - r0)^2 with the type bead i stores (all partners requested at once)
 template <typename R, int MODE>
 __device__ __forceinline__ void bond_terms(const Params& P, const Bank& B, int i, const double4& xi, int nb,
                                            Acc<R>& a) {
     const int n = P.n;
-    for (int k = 0; k < nb; ++k) {
-        int j = B.bp[k * n + i];
-        int t = B.bt[k * n + i];
-        double4 xj = B.x[j];
+    int jj[DB_MAXB], tt[DB_MAXB];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        jj[k] = k < nb ? B.bp[k * n + i] : i;
+        tt[k] = k < nb ? (int)B.bt[k * n + i] : 0;
+    }
+    double4 xs[DB_MAXB];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) xs[k] = B.x[jj[k]];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        if (k >= nb) continue;
+        const double4& xj = xs[k];
+        const int t = tt[k];
         double dx = min_image(xj.x - xi.x, P.L, P.hL);
         double dy = min_image(xj.y - xi.y, P.L, P.hL);
         double dz = min_image(xj.z - xi.z, P.L, P.hL);
         R rx = (R)dx, ry = (R)dy, rz = (R)dz;
-        R r = r_sqrt<R>((rx * rx + ry * ry) + rz * rz);
-        if (!(r > (R)0)) continue;
+        R rr2 = (rx * rx + ry * ry) + rz * rz;
+        if (!(rr2 > (R)0)) continue;
+        R ir = r_rsqrt<R>(rr2);
+        R r = rr2 * ir;
         R K = (R)P.bK[t], r0 = (R)P.bR0[t];
-        R g = (R)2.0 * K * (r - r0) / r;   // F_i = g * (x_j - x_i)
+        R g = (R)2.0 * K * (r - r0) * ir;   // F_i = g * (x_j - x_i)
         a.fx += (double)(g * rx);
         a.fy += (double)(g * ry);
         a.fz += (double)(g * rz);
@@ -152,18 +251,19 @@ __device__ __forceinline__ void angle_terms(const Params& P, const Bank& B, int 
     const int n = P.n;
     for (int k = 0; k < na; ++k) {
         int4 e = B.ang[k * n + i];
-        double4 xa = e.x == i ? xi : B.x[e.x];
-        double4 xb = e.y == i ? xi : B.x[e.y];
-        double4 xc = e.z == i ? xi : B.x[e.z];
+        double4 xa = B.x[e.x];
+        double4 xb = B.x[e.y];
+        double4 xc = B.x[e.z];
         R ux = (R)min_image(xa.x - xb.x, P.L, P.hL), uy = (R)min_image(xa.y - xb.y, P.L, P.hL),
           uz = (R)min_image(xa.z - xb.z, P.L, P.hL);
         R wx = (R)min_image(xc.x - xb.x, P.L, P.hL), wy = (R)min_image(xc.y - xb.y, P.L, P.hL),
           wz = (R)min_image(xc.z - xb.z, P.L, P.hL);
-        R ru = r_sqrt<R>((ux * ux + uy * uy) + uz * uz);
-        R rw = r_sqrt<R>((wx * wx + wy * wy) + wz * wz);
-        if (!(ru > (R)0) || !(rw > (R)0)) continue;
-        R cux = ux / ru, cuy = uy / ru, cuz = uz / ru;
-        R cwx = wx / rw, cwy = wy / rw, cwz = wz / rw;
+        R ru2 = (ux * ux + uy * uy) + uz * uz;
+        R rw2 = (wx * wx + wy * wy) + wz * wz;
+        if (!(ru2 > (R)0) || !(rw2 > (R)0)) continue;
+        R iru = r_rsqrt<R>(ru2), irw = r_rsqrt<R>(rw2);
+        R cux = ux * iru, cuy = uy * iru, cuz = uz * iru;
+        R cwx = wx * irw, cwy = wy * irw, cwz = wz * irw;
         R cs = (cux * cwx + cuy * cwy) + cuz * cwz;
         R crx = cuy * cwz - cuz * cwy, cry = cuz * cwx - cux * cwz, crz = cux * cwy - cuy * cwx;
         R sn = r_sqrt<R>((crx * crx + cry * cry) + crz * crz);
@@ -172,11 +272,13 @@ __device__ __forceinline__ void angle_terms(const Params& P, const Bank& B, int 
         R th = r_atan2<R>(sn, cs);
         // dU/dtheta / sin(theta), finite at theta = pi when theta0 = pi
         R del = r_atan2<R>(sn, -cs);   // pi - theta
-        R ratio = del < (R)1e-6 ? (R)1.0 + del * del / (R)6.0 : del / (sn > (R)1e-8 ? sn : (R)1e-8);
+        R isn = r_rcp<R>(sn > (R)1e-8 ? sn : (R)1e-8);
+        R ratio = del < (R)1e-6 ? (R)1.0 + del * del * (R)(1.0 / 6.0) : del * isn;
         R pth = (R)P.aPiMinusT0[t];
-        R A = (R)2.0 * K * (-ratio + (pth != (R)0 ? pth / (sn > (R)1e-8 ? sn : (R)1e-8) : (R)0));
-        R fax = -A * (cs * cux - cwx) / ru, fay = -A * (cs * cuy - cwy) / ru, faz = -A * (cs * cuz - cwz) / ru;
-        R fcx = -A * (cs * cwx - cux) / rw, fcy = -A * (cs * cwy - cuy) / rw, fcz = -A * (cs * cwz - cuz) / rw;
+        R A = (R)2.0 * K * (-ratio + (pth != (R)0 ? pth * isn : (R)0));
+        R Au = -A * iru, Aw = -A * irw;
+        R fax = Au * (cs * cux - cwx), fay = Au * (cs * cuy - cwy), faz = Au * (cs * cuz - cwz);
+        R fcx = Aw * (cs * cwx - cux), fcy = Aw * (cs * cwy - cuy), fcz = Aw * (cs * cwz - cuz);
         if (e.x == i) {
             a.fx += (double)fax; a.fy += (double)fay; a.fz += (double)faz;
         } else if (e.z == i) {
@@ -200,10 +302,10 @@ __device__ __forceinline__ void dihedral_terms(const Params& P, const Bank& B, i
     for (int k = 0; k < nd; ++k) {
         int4 e = B.dih[k * n + i];
         int t = B.dt[k * n + i];
-        double4 xa = e.x == i ? xi : B.x[e.x];
-        double4 xb = e.y == i ? xi : B.x[e.y];
-        double4 xc = e.z == i ? xi : B.x[e.z];
-        double4 xd = e.w == i ? xi : B.x[e.w];
+        double4 xa = B.x[e.x];
+        double4 xb = B.x[e.y];
+        double4 xc = B.x[e.z];
+        double4 xd = B.x[e.w];
         R b1x = (R)min_image(xb.x - xa.x, P.L, P.hL), b1y = (R)min_image(xb.y - xa.y, P.L, P.hL),
           b1z = (R)min_image(xb.z - xa.z, P.L, P.hL);
         R b2x = (R)min_image(xc.x - xb.x, P.L, P.hL), b2y = (R)min_image(xc.y - xb.y, P.L, P.hL),
@@ -217,15 +319,16 @@ __device__ __forceinline__ void dihedral_terms(const Params& P, const Bank& B, i
         R b22 = (b2x * b2x + b2y * b2y) + b2z * b2z;
         if (m2 < (R)1e-24 || n2 < (R)1e-24 || b22 < (R)1e-24) continue;   // collinear: no defined plane
         R nb2 = r_sqrt<R>(b22);
-        R inv = (R)1.0 / r_sqrt<R>(m2 * n2);
+        R inv = r_rsqrt<R>(m2 * n2);
         R cphi = ((mx * nx + my * ny) + mz * nz) * inv;
         R sphi = nb2 * ((b1x * nx + b1y * ny) + b1z * nz) * inv;
         R K = (R)P.dK[t], c0 = (R)P.dC0[t], s0 = (R)P.dS0[t];
         R dU = K * (sphi * c0 - cphi * s0);   // dU/dphi
-        R gax = -nb2 / m2 * mx, gay = -nb2 / m2 * my, gaz = -nb2 / m2 * mz;
-        R gdx = nb2 / n2 * nx, gdy = nb2 / n2 * ny, gdz = nb2 / n2 * nz;
-        R pp = ((b1x * b2x + b1y * b2y) + b1z * b2z) / b22;
-        R qq = ((b3x * b2x + b3y * b2y) + b3z * b2z) / b22;
+        R sa = -nb2 * r_rcp<R>(m2), sd = nb2 * r_rcp<R>(n2), ib22 = r_rcp<R>(b22);
+        R gax = sa * mx, gay = sa * my, gaz = sa * mz;
+        R gdx = sd * nx, gdy = sd * ny, gdz = sd * nz;
+        R pp = ((b1x * b2x + b1y * b2y) + b1z * b2z) * ib22;
+        R qq = ((b3x * b2x + b3y * b2y) + b3z * b2z) * ib22;
         R fx, fy, fz;
         if (e.x == i) {
             fx = -dU * gax; fy = -dU * gay; fz = -dU * gaz;
@@ -269,8 +372,7 @@ __device__ __forceinline__ double temperature(const Params& P, int64_t step) {
 
 template <typename R, int MODE>
 __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B,
-                                                    const int* __restrict__ cstart, const int* __restrict__ clist,
-                                                    double4* __restrict__ xout, int64_t step,
+                                                    NList NL, double4* __restrict__ xout, int64_t step, double pref,
                                                     unsigned int* __restrict__ vmax2_slot,
                                                     double* __restrict__ fout, int* __restrict__ err) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
@@ -285,11 +387,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
     if (active) {
         xi = B.x[i];
         int nb = B.nb[i];
-        int p0 = nb > 0 ? B.bp[i] : -1;
-        int p1 = nb > 1 ? B.bp[n + i] : -1;
-        int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
-        int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
-        if (P.have_pair) pair_forces<R, MODE>(P, B, cstart, clist, i, xi, nb, p0, p1, p2, p3, a);
+        if (P.have_pair) list_pair_forces<R>(P, B, NL, i, xi, a);
         bond_terms<R, MODE>(P, B, i, xi, nb, a);
         angle_terms<R, MODE>(P, B, i, xi, B.na[i], a);
         dihedral_terms<R, MODE>(P, B, i, xi, B.nd[i], a);
@@ -305,7 +403,6 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         vz = B.v[2 * n + i];
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
-            double pref = sqrt(24.0 * P.gamma * temperature(P, step) / P.dt);
             uint4 w = rng_draw(P, (uint32_t)meta_gid(xi), 0u, step, RNG_LANGEVIN);
             const double s32 = 1.0 / 4294967296.0;
             double ux = ((double)w.x + 0.5) * s32, uy = ((double)w.y + 0.5) * s32, uz = ((double)w.z + 0.5) * s32;
@@ -334,9 +431,18 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         }
     }
     if (MODE == MODE_STEP) {
+        // largest speed of the workgroup; one atomic per workgroup, spread over
+        // 64 words so that the workgroups of one step do not serialise on one address
+        __shared__ float wmax[DB_BLOCK / 64];
         double v2 = active ? (vx * vx + vy * vy) + vz * vz : 0.0;
         v2 = wave_max(v2);
-        if ((threadIdx.x & 63) == 0) atomicMax(vmax2_slot, __float_as_uint((float)v2 * 1.0001f));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = (float)v2 * 1.0001f;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = wmax[0];
+            for (int w = 1; w < DB_BLOCK / 64; ++w) m = fmaxf(m, wmax[w]);
+            atomicMax(vmax2_slot + (blockIdx.x & (DB_VMAX_SPREAD - 1)), __float_as_uint(m));
+        }
     }
 }
 
@@ -406,16 +512,34 @@ __global__ void k_energy_final(const double* __restrict__ epart, int nblocks, do
 
 static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK); }
 
+void launch_build_nlist(db_ctx* c) {
+    if (c->n == 0) return;
+    hipLaunchKernelGGL(k_build_nlist, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
+                       c->cells.start, c->cells.xs, c->nlist, c->err_d);
+}
+
+// sqrt(24 gamma T(step) / dt), the amplitude of the uniform Langevin noise
+static double langevin_prefactor(const Params& P, int64_t step) {
+    if (P.gamma == 0.0) return 0.0;
+    double T = P.T0;
+    if (P.ramp > 0) {
+        int64_t k = step < P.ramp ? step : P.ramp;
+        T = P.T0 + (P.T1 - P.T0) * (double)k / (double)P.ramp;
+    }
+    return sqrt(24.0 * P.gamma * T / P.dt);
+}
+
 void launch_step(db_ctx* c, int64_t step, int slot_in_block) {
     if (c->n == 0) return;
+    const double pref = langevin_prefactor(c->hp, step);
     Bank& B = c->bank[c->cur];
-    unsigned* vm = (unsigned*)(c->vmax2 + slot_in_block);
+    unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
     if (c->precision == DB_MIXED)
         hipLaunchKernelGGL((k_step<float, MODE_STEP>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
-                           c->cells.start, c->cells.list, c->xnext, step, vm, (double*)nullptr, c->err_d);
+                           c->nlist, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
     else
         hipLaunchKernelGGL((k_step<double, MODE_STEP>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           B, c->cells.start, c->cells.list, c->xnext, step, vm, (double*)nullptr, c->err_d);
+                           B, c->nlist, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;
@@ -426,10 +550,10 @@ void launch_forces(db_ctx* c, double* f) {
     Bank& B = c->bank[c->cur];
     if (c->precision == DB_MIXED)
         hipLaunchKernelGGL((k_step<float, MODE_FORCES>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           B, c->cells.start, c->cells.list, (double4*)nullptr, (int64_t)0, (unsigned*)nullptr, f, c->err_d);
+                           B, c->nlist, (double4*)nullptr, (int64_t)0, 0.0, (unsigned*)nullptr, f, c->err_d);
     else
         hipLaunchKernelGGL((k_step<double, MODE_FORCES>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream,
-                           c->dp, B, c->cells.start, c->cells.list, (double4*)nullptr, (int64_t)0,
+                           c->dp, B, c->nlist, (double4*)nullptr, (int64_t)0, 0.0,
                            (unsigned*)nullptr, f, c->err_d);
 }
 

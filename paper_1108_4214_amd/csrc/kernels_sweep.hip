@@ -13,7 +13,7 @@
 //                     remove / convert bonds (step 7), accept mutual creation
 //                     nominations with probability p (step 8)
 //   generate          new angles/dihedrals on paths through new bonds (step 9)
-#include "db_device.h"
+#include "cell_scan.h"
 
 namespace db {
 
@@ -68,97 +68,121 @@ __device__ __forceinline__ void stat_add(unsigned long long* st, int k, unsigned
 }
 
 // ---- step 2: creation nomination -------------------------------------------------
+// Visitor of the neighbour scan: every candidate that passes the float prefilter is
+// re-tested with the exact double arithmetic of the method (minimum-image
+// separation summed as (dx^2 + dy^2) + dz^2, strict comparison), then against the
+// rules in call order (the last applicable one wins), maxbond on both beads and
+// the graph distance; the closest survivor (ties: lower id) is nominated.
+struct CreateVisitor {
+    struct Ctx {
+        SweepBuf S;
+    };
+    const Params& P;
+    const Bank& B;
+    Ctx c;
+    int i, ti, gi;
+    double4 xi;
+    Tab Ti;
+    bool can;
+    int best, best_rule, best_bt, best_g;
+    double best_r2;
+    __device__ static float cut2(const Params& P) { return (float)(P.rmax2_create * 1.0001); }
+    // some creation rule admits bead i in one of its two roles (reactive, type, maxbond)
+    __device__ static bool admits(const Params& P, int ti, const Tab& Ti) {
+        for (int q = 0; q < P.nrule; ++q) {
+            const Rule& r = P.rule[q];
+            if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
+            if ((type_ok(r.b1, ti) && max_ok(P, ti, Ti, r.bt1)) || (type_ok(r.b2, ti) && max_ok(P, ti, Ti, r.bt2)))
+                return true;
+        }
+        return false;
+    }
+    __device__ CreateVisitor(const Params& P_, const Bank& B_, int i_, const double4& xi_, const Ctx& c_, bool live)
+        : P(P_), B(B_), c(c_), i(i_), xi(xi_), can(false), best(-1), best_rule(-1), best_bt(0), best_g(0),
+          best_r2(0.0) {
+        if (!live) return;
+        int mi = meta_word(xi);
+        ti = meta_type(mi);
+        gi = meta_gid(xi);
+        can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
+        if (can) {
+            Ti = load_tab(B, P.n, i);
+            can = admits(P, ti, Ti);
+        }
+    }
+    __device__ bool active() const { return can; }
+    __device__ void candidate(int j, float) {
+        const int n = P.n;
+        double4 xj = B.x[j];
+        int mj = meta_word(xj);
+        if (!meta_reactive(mj)) return;
+        double dx, dy, dz;
+        double r2 = separation(P, xi, xj, dx, dy, dz);
+        if (!(r2 < P.rmax2_create)) return;
+        int tj = meta_type(mj);
+        int gj = meta_gid(xj);
+        // last creation rule that applies to the pair
+        int rule = -1, bti = 0;
+        bool have_tj = false;
+        Tab Tj;
+        for (int q = 0; q < P.nrule; ++q) {
+            const Rule& r = P.rule[q];
+            if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
+            bool o1 = type_ok(r.b1, ti) && type_ok(r.b2, tj);
+            bool o2 = type_ok(r.b1, tj) && type_ok(r.b2, ti);
+            if (!o1 && !o2) continue;
+            if (o1 && o2) o1 = gi < gj;   // both orientations: the lower id plays bead1
+            int si = o1 ? r.bt1 : r.bt2;
+            int sj = o1 ? r.bt2 : r.bt1;
+            if (!(r2 < r.r2)) continue;
+            if (!max_ok(P, ti, Ti, si)) continue;
+            if (!have_tj) {
+                Tj = load_tab(B, n, j);
+                have_tj = true;
+            }
+            if (!max_ok(P, tj, Tj, sj)) continue;
+            rule = q;
+            bti = si;
+        }
+        if (rule < 0) return;
+        // graph distance 1, 2 or 3 on the bond graph before the sweep
+        if (tab_has(Ti, j)) return;
+        bool d2 = false;
+        for (int a = 0; a < Ti.n && !d2; ++a)
+            if (tab_has(Tj, Ti.p[a])) d2 = true;
+        if (d2 && !P.pc13) return;
+        if (!d2 && !P.pc14) {
+            for (int a = 0; a < Ti.n; ++a) {
+                Tab Tq = load_tab(B, n, Ti.p[a]);
+                for (int b = 0; b < Tj.n; ++b)
+                    if (tab_has(Tq, Tj.p[b])) return;
+            }
+        }
+        if (best < 0 || r2 < best_r2 || (r2 == best_r2 && gj < best_g)) {
+            best = j;
+            best_r2 = r2;
+            best_g = gj;
+            best_rule = rule;
+            best_bt = bti;
+        }
+    }
+    __device__ void finish() {
+        c.S.nomC[i] = best;
+        c.S.ruleC[i] = (int8_t)best_rule;
+        c.S.btC[i] = (int8_t)best_bt;
+    }
+};
+
 __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
                                                               const int* __restrict__ cstart,
-                                                              const int* __restrict__ clist, SweepBuf S) {
+                                                              const float4* __restrict__ xs, SweepBuf S) {
     const Params& P = *Pp;
-    const int n = P.n;
-    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    double4 xi = B.x[i];
-    int mi = meta_word(xi);
-    int ti = meta_type(mi);
-    int gi = meta_gid(xi);
-    int best = -1, best_rule = -1, best_bt = 0, best_g = 0;
-    double best_r2 = 0.0;
-    if (meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0) {
-        Tab Ti = load_tab(B, n, i);
-        const int nc = P.nc;
-        int cx = cell_coord(xi.x, P.cell_scale, nc);
-        int cy = cell_coord(xi.y, P.cell_scale, nc);
-        int cz = cell_coord(xi.z, P.cell_scale, nc);
-        for (int oz = 0; oz < P.noff; ++oz)
-            for (int oy = 0; oy < P.noff; ++oy)
-                for (int ox = 0; ox < P.noff; ++ox) {
-                    int c = (wrap_cell(cz + P.off[oz], nc) * nc + wrap_cell(cy + P.off[oy], nc)) * nc +
-                            wrap_cell(cx + P.off[ox], nc);
-                    int s1 = cstart[c + 1];
-                    for (int p = cstart[c]; p < s1; ++p) {
-                        int j = clist[p];
-                        if (j == i) continue;
-                        double4 xj = B.x[j];
-                        int mj = meta_word(xj);
-                        if (!meta_reactive(mj)) continue;
-                        double dx, dy, dz;
-                        double r2 = separation(P, xi, xj, dx, dy, dz);
-                        if (!(r2 < P.rmax2_create)) continue;
-                        int tj = meta_type(mj);
-                        int gj = meta_gid(xj);
-                        // last creation rule that applies to the pair
-                        int rule = -1, bti = 0;
-                        bool have_tj = false;
-                        Tab Tj;
-                        for (int q = 0; q < P.nrule; ++q) {
-                            const Rule& r = P.rule[q];
-                            if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
-                            bool o1 = type_ok(r.b1, ti) && type_ok(r.b2, tj);
-                            bool o2 = type_ok(r.b1, tj) && type_ok(r.b2, ti);
-                            if (!o1 && !o2) continue;
-                            if (o1 && o2) o1 = gi < gj;   // both orientations: the lower id plays bead1
-                            int si = o1 ? r.bt1 : r.bt2;
-                            int sj = o1 ? r.bt2 : r.bt1;
-                            if (!(r2 < r.r2)) continue;
-                            if (!max_ok(P, ti, Ti, si)) continue;
-                            if (!have_tj) {
-                                Tj = load_tab(B, n, j);
-                                have_tj = true;
-                            }
-                            if (!max_ok(P, tj, Tj, sj)) continue;
-                            rule = q;
-                            bti = si;
-                        }
-                        if (rule < 0) continue;
-                        // graph distance 1, 2 or 3 on the bond graph before the sweep
-                        if (tab_has(Ti, j)) continue;
-                        bool d2 = false;
-                        for (int a = 0; a < Ti.n && !d2; ++a)
-                            if (tab_has(Tj, Ti.p[a])) d2 = true;
-                        if (d2 && !P.pc13) continue;
-                        if (!d2 && !P.pc14) {
-                            bool d3 = false;
-                            for (int a = 0; a < Ti.n && !d3; ++a) {
-                                Tab Tq = load_tab(B, n, Ti.p[a]);
-                                for (int b = 0; b < Tj.n; ++b)
-                                    if (tab_has(Tq, Tj.p[b])) {
-                                        d3 = true;
-                                        break;
-                                    }
-                            }
-                            if (d3) continue;
-                        }
-                        if (best < 0 || r2 < best_r2 || (r2 == best_r2 && gj < best_g)) {
-                            best = j;
-                            best_r2 = r2;
-                            best_g = gj;
-                            best_rule = rule;
-                            best_bt = bti;
-                        }
-                    }
-                }
-    }
-    S.nomC[i] = best;
-    S.ruleC[i] = (int8_t)best_rule;
-    S.btC[i] = (int8_t)best_bt;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
+    if (i >= P.n) return;
+    const double4 xi = B.x[i];
+    CreateVisitor v(P, B, i, xi, CreateVisitor::Ctx{S}, true);
+    if (v.active()) scan_cells(P, cstart, xs, i, xi, CreateVisitor::cut2(P), [&](int j, float r2f) { v.candidate(j, r2f); });
+    v.finish();
 }
 
 // ---- steps 3 and 5: breakage nomination and killbond marks ----------------------
@@ -535,7 +559,7 @@ void launch_sweep(db_ctx* c, int64_t step) {
     Bank& B = c->bank[c->cur];
     unsigned g = grid_for(c->n);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, c->sw.stats, 8);
-    hipLaunchKernelGGL(k_nominate_create, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start, c->cells.list,
+    hipLaunchKernelGGL(k_nominate_create, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start, c->cells.xs,
                        c->sw);
     hipLaunchKernelGGL(k_nominate_break, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
     hipLaunchKernelGGL(k_resolve, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step);

@@ -319,3 +319,34 @@ def test_full_size_c3_sweep(c3_workload):
 @pytest.fixture(scope="module")
 def c3_workload():
     return synth.c3()
+
+
+def test_dense_cluster_sweep():
+    # a dense clump in a dilute box: crowded cells (about 40 beads each) next to empty ones
+    rng = np.random.default_rng(31)
+    n_clump, n_gas, L = 2600, 400, 16.0
+    x = np.concatenate([rng.uniform(5.0, 8.2, size=(n_clump, 3)), rng.uniform(0, L, size=(n_gas, 3))])
+    s = synth.System(L=L, x=synth.wrap(x, L), v=np.zeros((n_clump + n_gas, 3)),
+                     type=rng.integers(1, 5, size=n_clump + n_gas).astype(np.int32),
+                     reactive=np.ones(n_clump + n_gas, dtype=np.uint8), bonds=np.zeros((0, 4), dtype=np.int32))
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 0.8), ("create", 1, 3, 4, 1.5, 0.8),
+                                          ("maxbond", 1, 0, 1)])
+    g, o = _sweep_both(s, synth.ForceField(eps=0.01), rules, seed=4, step=1)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert g.stats()["bonds_created"] > 100
+
+
+def test_dense_slab_forces():
+    # a slab three cells thick at density 2.2: long cell runs, up to about 55 list
+    # neighbours per bead with the 0.4 skin (the list holds 64)
+    rng = np.random.default_rng(32)
+    L, n = 30.0, 9000
+    x = np.column_stack([rng.uniform(0, L, n), rng.uniform(0, L, n), rng.uniform(10.0, 14.6, n)])
+    s = synth.System(L=L, x=synth.wrap(x, L), v=np.zeros((n, 3)), type=np.ones(n, dtype=np.int32),
+                     reactive=np.ones(n, dtype=np.uint8), bonds=np.zeros((0, 4), dtype=np.int32))
+    import paper_1108_4214_amd as pk
+    g = pk.System(s.n, s.L, 7)
+    pk.db_tune(g.ctx, 0.4, 1)      # list cutoff 1.52: under 64 neighbours at this density
+    g.configure(s, synth.ForceField(eps=0.01), synth.RuleSet(every=0))
+    o = oracle.Oracle.from_system(s, synth.ForceField(eps=0.01), synth.RuleSet(every=0), seed=7)
+    assert rel_l2(g.forces(), o.forces()) <= FP64_TOL
