@@ -156,6 +156,10 @@ static size_t layout(db_ctx* c, bool assign) {
     put(S.stats, 8 * 8);
     put(c->nlist.nl, 4 * (size_t)DB_NLCAP * n);
     put(c->nlist.cnt, n);
+    put(c->halo.nu, n);
+    put(c->halo.u, 4 * (size_t)DB_MAXU * n);
+    put(c->halo.acode, 4 * (size_t)DB_MAXA * n);
+    put(c->halo.dcode, 4 * (size_t)DB_MAXD * n);
     put(c->cells.cnt, 4 * nc);
     put(c->cells.start, 4 * (nc + 1));
     put(c->cells.list, 4 * n);
@@ -539,6 +543,7 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     P.n = n;
     P.L = L;
     P.hL = 0.5 * L;
+    P.invL = 1.0 / L;
     P.seed_lo = (uint32_t)seed;
     P.seed_hi = (uint32_t)(seed >> 32);
     P.T0 = P.T1 = 1.0;

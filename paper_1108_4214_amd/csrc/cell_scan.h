@@ -10,9 +10,9 @@
 namespace db {
 
 __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
-    if (d > hL) return d - L;
-    if (d < -hL) return d + L;
-    return d;
+    const float lo = d - L, hi = d + L;
+    float r = d > hL ? lo : d;
+    return d < -hL ? hi : r;
 }
 
 // f(j, r2f) for every j != i in the 27 cells around xi with float r2 < cut2

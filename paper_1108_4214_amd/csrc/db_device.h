@@ -14,10 +14,11 @@ namespace db {
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * c.x;
-        uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        uint32_t lo1 = 0xCD9E8D57u * c.z;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32->64 product gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -40,10 +41,13 @@ __device__ __forceinline__ double pair_uniform(const Params& P, int ga, int gb, 
     return (double)bits * (1.0 / 9007199254740992.0);
 }
 
+// both shifted values are formed and one is selected, so the compiler emits
+// selects rather than divergent branches; the result is bit-identical to the
+// branching form
 __device__ __forceinline__ double min_image(double d, double L, double hL) {
-    if (d > hL) return d - L;
-    if (d < -hL) return d + L;
-    return d;
+    const double lo = d - L, hi = d + L;
+    double r = d > hL ? lo : d;
+    return d < -hL ? hi : r;
 }
 
 // x_j - x_i with the minimum-image convention, and its squared length summed
@@ -91,12 +95,11 @@ __device__ __forceinline__ int wrap_cell(int c, int nc) { return c < 0 ? c + nc 
 
 // position update with the periodic wrap into [0, L)
 __device__ __forceinline__ double wrap1(double x, double L) {
-    if (x >= L) return x - L;
-    if (x < 0.0) {
-        double y = x + L;
-        return y >= L ? 0.0 : y;
-    }
-    return x;
+    const double lo = x - L;
+    double y = x + L;
+    y = y >= L ? 0.0 : y;
+    double r = x < 0.0 ? y : x;
+    return x >= L ? lo : r;
 }
 
 }  // namespace db

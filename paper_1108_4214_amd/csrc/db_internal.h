@@ -16,6 +16,8 @@
 #define DB_MAXRULES 32
 #define DB_BLOCK 256
 #define DB_NLCAP 64          // neighbour-list entries per bead
+#define DB_MAXU 8            // bonded halo entries per bead (codes hold 3-bit indices)
+#define DB_HALO_OVF 255      // halo marker: more than DB_MAXU distinct bonded partners
 #define DB_VMAX_SPREAD 64    // words per step over which the speed maxima are spread
 
 namespace db {
@@ -39,7 +41,7 @@ struct DihRule { int type; int b[4]; uint32_t m[3]; };
 // Read-only parameters of one box, resident in device memory.
 struct Params {
     int n;
-    double L, hL;
+    double L, hL, invL;
     // cell grid: nc^3 cells of edge L/nc; neighbour offsets per dimension
     int nc, ncell, noff;
     int off[3];
@@ -104,6 +106,17 @@ struct NList {
     uint8_t* cnt;     // [n]
 };
 
+// Bonded halo of each bead (built with the neighbour list): the distinct beads
+// its bonds, angles and dihedrals reach, and those entries re-coded as the
+// bead's role plus halo indices.  nu = DB_HALO_OVF marks a bead whose halo
+// would exceed DB_MAXU; it reads the slot tables instead.
+struct Halo {
+    uint8_t* nu;        // [n]
+    int* u;             // [DB_MAXU][n] slots, bond partners first in table order
+    uint32_t* acode;    // [DB_MAXA][n]
+    uint32_t* dcode;    // [DB_MAXD][n]
+};
+
 struct Cells {
     int* cnt;         // [ncell]
     int* start;       // [ncell + 1]
@@ -144,6 +157,7 @@ struct db_ctx {
     db::SweepBuf sw;
     db::Cells cells;
     db::NList nlist;
+    db::Halo halo;
     double nl_skin;      // neighbour-list cutoff minus pair cutoff
     int* slot_of_gid;    // [n]
     int* err_d;          // device error word

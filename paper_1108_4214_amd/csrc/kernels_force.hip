@@ -22,6 +22,42 @@ struct Acc {
     double e_pair = 0, e_bond = 0, e_ang = 0, e_dih = 0, vir = 0;
 };
 
+// Per-type bonded coefficients in the force arithmetic type, staged in LDS by
+// every workgroup: the type of an entry is known only once the entry is read,
+// and an LDS lookup costs far less than a second dependent global load.
+template <typename R>
+struct Coef {
+    R bK[DB_MAXT], bR0[DB_MAXT];
+    R aK[DB_MAXT], aT0[DB_MAXT], aPm[DB_MAXT];   // aPm = pi - theta0
+    R dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
+};
+
+// fill C from P with the first DB_MAXT threads; the caller synchronises
+template <typename R>
+__device__ __forceinline__ void load_coef(const Params& P, Coef<R>& C) {
+    const int t = threadIdx.x;
+    if (t < DB_MAXT) {
+        C.bK[t] = (R)P.bK[t];
+        C.bR0[t] = (R)P.bR0[t];
+        C.aK[t] = (R)P.aK[t];
+        C.aT0[t] = (R)P.aT0[t];
+        C.aPm[t] = (R)P.aPiMinusT0[t];
+        C.dK[t] = (R)P.dK[t];
+        C.dC0[t] = (R)P.dC0[t];
+        C.dS0[t] = (R)P.dS0[t];
+    }
+}
+
+// Minimum image for separations that are short next to half a box (interacting
+// pairs, members of a bond, angle or dihedral): the nearest multiple of L, which
+// is -L, 0 or L, is removed by one fused multiply-add.  L times that multiple is
+// exact, so the result equals d - L, d or d + L rounded once, as in the
+// comparison form; the two forms can pick different images only for d within a
+// rounding error of L/2, where both images are equally near.
+__device__ __forceinline__ double near_image(double d, const Params& P) {
+    return fma(-rint(d * P.invL), P.L, d);
+}
+
 template <typename R>
 __device__ __forceinline__ R r_sqrt(R v);
 template <>
@@ -70,9 +106,9 @@ __device__ bool two_bonds_apart(const Bank& B, int n, int j, int nb, int p0, int
 template <typename R, int MODE>
 __device__ __forceinline__ void pair_term(const Params& P, const double4& xi, const double4& xj, Acc<R>& a) {
     double dx, dy, dz;
-    dx = min_image(xj.x - xi.x, P.L, P.hL);
-    dy = min_image(xj.y - xi.y, P.L, P.hL);
-    dz = min_image(xj.z - xi.z, P.L, P.hL);
+    dx = near_image(xj.x - xi.x, P);
+    dy = near_image(xj.y - xi.y, P);
+    dz = near_image(xj.z - xi.z, P);
     R rx = (R)dx, ry = (R)dy, rz = (R)dz;
     R r2 = (rx * rx + ry * ry) + rz * rz;
     R ir2 = r_rcp<R>(r2);
@@ -119,9 +155,9 @@ __device__ void pair_forces(const Params& P, const Bank& B, const int* __restric
                     int j = clist[p];
                     if (j == i) continue;
                     double4 xj = B.x[j];
-                    double dx = min_image(xj.x - xi.x, P.L, P.hL);
-                    double dy = min_image(xj.y - xi.y, P.L, P.hL);
-                    double dz = min_image(xj.z - xi.z, P.L, P.hL);
+                    double dx = near_image(xj.x - xi.x, P);
+                    double dy = near_image(xj.y - xi.y, P);
+                    double dz = near_image(xj.z - xi.z, P);
                     R rx = (R)dx, ry = (R)dy, rz = (R)dz;
                     R r2 = (rx * rx + ry * ry) + rz * rz;
                     if (!(r2 < rc2)) continue;
@@ -171,9 +207,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
 // requested before any of them is used, so one bead keeps several loads in flight.
 template <typename R>
 __device__ __forceinline__ void pair_one(const Params& P, const double4& xi, const double4& xj, R rc2, Acc<R>& a) {
-    R rx = (R)min_image(xj.x - xi.x, P.L, P.hL);
-    R ry = (R)min_image(xj.y - xi.y, P.L, P.hL);
-    R rz = (R)min_image(xj.z - xi.z, P.L, P.hL);
+    R rx = (R)near_image(xj.x - xi.x, P);
+    R ry = (R)near_image(xj.y - xi.y, P);
+    R rz = (R)near_image(xj.z - xi.z, P);
     R r2 = (rx * rx + ry * ry) + rz * rz;
     if (r2 < rc2) {
         R ir2 = r_rcp<R>(r2);
@@ -207,14 +243,14 @@ __device__ __forceinline__ void list_pair_forces(const Params& P, const Bank& B,
 
 // harmonic bond U = K (r - r0)^2 with the type bead i stores (all partners requested at once)
 template <typename R, int MODE>
-__device__ __forceinline__ void bond_terms(const Params& P, const Bank& B, int i, const double4& xi, int nb,
+__device__ __forceinline__ void bond_terms(const Params& P, const Coef<R>& C, const Bank& B, int i, const double4& xi, int nb,
                                            Acc<R>& a) {
     const int n = P.n;
     int jj[DB_MAXB], tt[DB_MAXB];
 #pragma unroll
     for (int k = 0; k < DB_MAXB; ++k) {
         jj[k] = k < nb ? B.bp[k * n + i] : i;
-        tt[k] = k < nb ? (int)B.bt[k * n + i] : 0;
+        tt[k] = k < nb ? (int)B.bt[k * n + i] & (DB_MAXT - 1) : 0;
     }
     double4 xs[DB_MAXB];
 #pragma unroll
@@ -224,15 +260,15 @@ __device__ __forceinline__ void bond_terms(const Params& P, const Bank& B, int i
         if (k >= nb) continue;
         const double4& xj = xs[k];
         const int t = tt[k];
-        double dx = min_image(xj.x - xi.x, P.L, P.hL);
-        double dy = min_image(xj.y - xi.y, P.L, P.hL);
-        double dz = min_image(xj.z - xi.z, P.L, P.hL);
+        double dx = near_image(xj.x - xi.x, P);
+        double dy = near_image(xj.y - xi.y, P);
+        double dz = near_image(xj.z - xi.z, P);
         R rx = (R)dx, ry = (R)dy, rz = (R)dz;
         R rr2 = (rx * rx + ry * ry) + rz * rz;
         if (!(rr2 > (R)0)) continue;
         R ir = r_rsqrt<R>(rr2);
         R r = rr2 * ir;
-        R K = (R)P.bK[t], r0 = (R)P.bR0[t];
+        R K = C.bK[t], r0 = C.bR0[t];
         R g = (R)2.0 * K * (r - r0) * ir;   // F_i = g * (x_j - x_i)
         a.fx += (double)(g * rx);
         a.fy += (double)(g * ry);
@@ -244,117 +280,278 @@ __device__ __forceinline__ void bond_terms(const Params& P, const Bank& B, int i
     }
 }
 
-// harmonic angle U = K (theta - theta0)^2; bead i takes the force of its role
+// harmonic angle U = K (theta - theta0)^2 on u = x_a - x_b, w = x_c - x_b; the
+// bead takes the force of its role (0: end a, 1: centre b, 2: end c)
 template <typename R, int MODE>
-__device__ __forceinline__ void angle_terms(const Params& P, const Bank& B, int i, const double4& xi, int na,
+__device__ __forceinline__ void angle_core(const Coef<R>& C, int role, int t, R ux, R uy, R uz, R wx, R wy, R wz,
+                                           Acc<R>& a) {
+    R ru2 = (ux * ux + uy * uy) + uz * uz;
+    R rw2 = (wx * wx + wy * wy) + wz * wz;
+    if (!(ru2 > (R)0) || !(rw2 > (R)0)) return;
+    R iru = r_rsqrt<R>(ru2), irw = r_rsqrt<R>(rw2);
+    R cux = ux * iru, cuy = uy * iru, cuz = uz * iru;
+    R cwx = wx * irw, cwy = wy * irw, cwz = wz * irw;
+    R cs = (cux * cwx + cuy * cwy) + cuz * cwz;
+    R crx = cuy * cwz - cuz * cwy, cry = cuz * cwx - cux * cwz, crz = cux * cwy - cuy * cwx;
+    R sn = r_sqrt<R>((crx * crx + cry * cry) + crz * crz);
+    R K = C.aK[t];
+    // dU/dtheta / sin(theta), finite at theta = pi when theta0 = pi
+    R del = r_atan2<R>(sn, -cs);   // pi - theta
+    R isn = r_rcp<R>(sn > (R)1e-8 ? sn : (R)1e-8);
+    R ratio = del < (R)1e-6 ? (R)1.0 + del * del * (R)(1.0 / 6.0) : del * isn;
+    R pth = C.aPm[t];
+    R A = (R)2.0 * K * (-ratio + (pth != (R)0 ? pth * isn : (R)0));
+    R Au = -A * iru, Aw = -A * irw;
+    R fax = Au * (cs * cux - cwx), fay = Au * (cs * cuy - cwy), faz = Au * (cs * cuz - cwz);
+    R fcx = Aw * (cs * cwx - cux), fcy = Aw * (cs * cwy - cuy), fcz = Aw * (cs * cwz - cuz);
+    if (role == 0) {
+        a.fx += (double)fax; a.fy += (double)fay; a.fz += (double)faz;
+    } else if (role == 2) {
+        a.fx += (double)fcx; a.fy += (double)fcy; a.fz += (double)fcz;
+    } else {
+        a.fx -= (double)(fax + fcx); a.fy -= (double)(fay + fcy); a.fz -= (double)(faz + fcz);
+    }
+    if (MODE == MODE_ENERGY) {
+        R th = r_atan2<R>(sn, cs);
+        R th0 = C.aT0[t];
+        a.e_ang += (double)(K * (th - th0) * (th - th0)) / 3.0;
+        a.vir += (double)((ux * fax + uy * fay + uz * faz) + (wx * fcx + wy * fcy + wz * fcz)) / 3.0;
+    }
+}
+
+// angle entry e = (a, b, c, type) of bead i from the members' positions
+template <typename R, int MODE>
+__device__ __forceinline__ void angle_one(const Params& P, const Coef<R>& C, int i, const int4& e,
+                                          const double4& xa, const double4& xb, const double4& xc, Acc<R>& a) {
+    R ux = (R)near_image(xa.x - xb.x, P), uy = (R)near_image(xa.y - xb.y, P), uz = (R)near_image(xa.z - xb.z, P);
+    R wx = (R)near_image(xc.x - xb.x, P), wy = (R)near_image(xc.y - xb.y, P), wz = (R)near_image(xc.z - xb.z, P);
+    const int role = e.x == i ? 0 : (e.z == i ? 2 : 1);
+    angle_core<R, MODE>(C, role, e.w & (DB_MAXT - 1), ux, uy, uz, wx, wy, wz, a);
+}
+
+template <typename R, int MODE>
+__device__ __forceinline__ void angle_terms(const Params& P, const Coef<R>& C, const Bank& B, int i, int na,
                                             Acc<R>& a) {
     const int n = P.n;
     for (int k = 0; k < na; ++k) {
         int4 e = B.ang[k * n + i];
-        double4 xa = B.x[e.x];
-        double4 xb = B.x[e.y];
-        double4 xc = B.x[e.z];
-        R ux = (R)min_image(xa.x - xb.x, P.L, P.hL), uy = (R)min_image(xa.y - xb.y, P.L, P.hL),
-          uz = (R)min_image(xa.z - xb.z, P.L, P.hL);
-        R wx = (R)min_image(xc.x - xb.x, P.L, P.hL), wy = (R)min_image(xc.y - xb.y, P.L, P.hL),
-          wz = (R)min_image(xc.z - xb.z, P.L, P.hL);
-        R ru2 = (ux * ux + uy * uy) + uz * uz;
-        R rw2 = (wx * wx + wy * wy) + wz * wz;
-        if (!(ru2 > (R)0) || !(rw2 > (R)0)) continue;
-        R iru = r_rsqrt<R>(ru2), irw = r_rsqrt<R>(rw2);
-        R cux = ux * iru, cuy = uy * iru, cuz = uz * iru;
-        R cwx = wx * irw, cwy = wy * irw, cwz = wz * irw;
-        R cs = (cux * cwx + cuy * cwy) + cuz * cwz;
-        R crx = cuy * cwz - cuz * cwy, cry = cuz * cwx - cux * cwz, crz = cux * cwy - cuy * cwx;
-        R sn = r_sqrt<R>((crx * crx + cry * cry) + crz * crz);
-        int t = e.w;
-        R K = (R)P.aK[t];
-        R th = r_atan2<R>(sn, cs);
-        // dU/dtheta / sin(theta), finite at theta = pi when theta0 = pi
-        R del = r_atan2<R>(sn, -cs);   // pi - theta
-        R isn = r_rcp<R>(sn > (R)1e-8 ? sn : (R)1e-8);
-        R ratio = del < (R)1e-6 ? (R)1.0 + del * del * (R)(1.0 / 6.0) : del * isn;
-        R pth = (R)P.aPiMinusT0[t];
-        R A = (R)2.0 * K * (-ratio + (pth != (R)0 ? pth * isn : (R)0));
-        R Au = -A * iru, Aw = -A * irw;
-        R fax = Au * (cs * cux - cwx), fay = Au * (cs * cuy - cwy), faz = Au * (cs * cuz - cwz);
-        R fcx = Aw * (cs * cwx - cux), fcy = Aw * (cs * cwy - cuy), fcz = Aw * (cs * cwz - cuz);
-        if (e.x == i) {
-            a.fx += (double)fax; a.fy += (double)fay; a.fz += (double)faz;
-        } else if (e.z == i) {
-            a.fx += (double)fcx; a.fy += (double)fcy; a.fz += (double)fcz;
-        } else {
-            a.fx -= (double)(fax + fcx); a.fy -= (double)(fay + fcy); a.fz -= (double)(faz + fcz);
-        }
-        if (MODE == MODE_ENERGY) {
-            R th0 = (R)P.aT0[t];
-            a.e_ang += (double)(K * (th - th0) * (th - th0)) / 3.0;
-            a.vir += (double)((ux * fax + uy * fay + uz * faz) + (wx * fcx + wy * fcy + wz * fcz)) / 3.0;
-        }
+        angle_one<R, MODE>(P, C, i, e, B.x[e.x], B.x[e.y], B.x[e.z], a);
     }
 }
 
 // cosine dihedral U = K [1 - cos(phi - phi0)], phi = atan2(|b2| b1.(b2 x b3), (b1 x b2).(b2 x b3))
+// on the bond vectors b1 = x_b - x_a, b2 = x_c - x_b, b3 = x_d - x_c; role 0..3 = a..d
 template <typename R, int MODE>
-__device__ __forceinline__ void dihedral_terms(const Params& P, const Bank& B, int i, const double4& xi, int nd,
+__device__ __forceinline__ void dihedral_core(const Coef<R>& C, int role, int t, R b1x, R b1y, R b1z, R b2x, R b2y,
+                                              R b2z, R b3x, R b3y, R b3z, Acc<R>& a) {
+    R mx = b1y * b2z - b1z * b2y, my = b1z * b2x - b1x * b2z, mz = b1x * b2y - b1y * b2x;
+    R nx = b2y * b3z - b2z * b3y, ny = b2z * b3x - b2x * b3z, nz = b2x * b3y - b2y * b3x;
+    R m2 = (mx * mx + my * my) + mz * mz;
+    R n2 = (nx * nx + ny * ny) + nz * nz;
+    R b22 = (b2x * b2x + b2y * b2y) + b2z * b2z;
+    if (m2 < (R)1e-24 || n2 < (R)1e-24 || b22 < (R)1e-24) return;   // collinear: no defined plane
+    R nb2 = r_sqrt<R>(b22);
+    R inv = r_rsqrt<R>(m2 * n2);
+    R cphi = ((mx * nx + my * ny) + mz * nz) * inv;
+    R sphi = nb2 * ((b1x * nx + b1y * ny) + b1z * nz) * inv;
+    R K = C.dK[t], c0 = C.dC0[t], s0 = C.dS0[t];
+    R dU = K * (sphi * c0 - cphi * s0);   // dU/dphi
+    R sa = -nb2 * r_rcp<R>(m2), sd = nb2 * r_rcp<R>(n2), ib22 = r_rcp<R>(b22);
+    R gax = sa * mx, gay = sa * my, gaz = sa * mz;
+    R gdx = sd * nx, gdy = sd * ny, gdz = sd * nz;
+    R pp = ((b1x * b2x + b1y * b2y) + b1z * b2z) * ib22;
+    R qq = ((b3x * b2x + b3y * b2y) + b3z * b2z) * ib22;
+    R fx, fy, fz;
+    if (role == 0) {
+        fx = -dU * gax; fy = -dU * gay; fz = -dU * gaz;
+    } else if (role == 3) {
+        fx = -dU * gdx; fy = -dU * gdy; fz = -dU * gdz;
+    } else if (role == 1) {
+        fx = -dU * (qq * gdx - (pp + (R)1) * gax);
+        fy = -dU * (qq * gdy - (pp + (R)1) * gay);
+        fz = -dU * (qq * gdz - (pp + (R)1) * gaz);
+    } else {
+        fx = -dU * (pp * gax - (qq + (R)1) * gdx);
+        fy = -dU * (pp * gay - (qq + (R)1) * gdy);
+        fz = -dU * (pp * gaz - (qq + (R)1) * gdz);
+    }
+    a.fx += (double)fx; a.fy += (double)fy; a.fz += (double)fz;
+    if (MODE == MODE_ENERGY) {
+        a.e_dih += (double)(K * ((R)1 - (cphi * c0 + sphi * s0))) / 4.0;
+        // virial about bead b: (x_a - x_b).F_a + (x_c - x_b).F_c + (x_d - x_b).F_d
+        R fa_x = -dU * gax, fa_y = -dU * gay, fa_z = -dU * gaz;
+        R fd_x = -dU * gdx, fd_y = -dU * gdy, fd_z = -dU * gdz;
+        R fc_x = -dU * (pp * gax - (qq + (R)1) * gdx), fc_y = -dU * (pp * gay - (qq + (R)1) * gdy),
+          fc_z = -dU * (pp * gaz - (qq + (R)1) * gdz);
+        R w = -(b1x * fa_x + b1y * fa_y + b1z * fa_z) + (b2x * fc_x + b2y * fc_y + b2z * fc_z) +
+              ((b2x + b3x) * fd_x + (b2y + b3y) * fd_y + (b2z + b3z) * fd_z);
+        a.vir += (double)w / 4.0;
+    }
+}
+
+template <typename R, int MODE>
+__device__ __forceinline__ void dihedral_one(const Params& P, const Coef<R>& C, int i, const int4& e, int t,
+                                             const double4& xa, const double4& xb, const double4& xc,
+                                             const double4& xd, Acc<R>& a) {
+    R b1x = (R)near_image(xb.x - xa.x, P), b1y = (R)near_image(xb.y - xa.y, P), b1z = (R)near_image(xb.z - xa.z, P);
+    R b2x = (R)near_image(xc.x - xb.x, P), b2y = (R)near_image(xc.y - xb.y, P), b2z = (R)near_image(xc.z - xb.z, P);
+    R b3x = (R)near_image(xd.x - xc.x, P), b3y = (R)near_image(xd.y - xc.y, P), b3z = (R)near_image(xd.z - xc.z, P);
+    const int role = e.x == i ? 0 : (e.w == i ? 3 : (e.y == i ? 1 : 2));
+    dihedral_core<R, MODE>(C, role, t, b1x, b1y, b1z, b2x, b2y, b2z, b3x, b3y, b3z, a);
+}
+
+template <typename R, int MODE>
+__device__ __forceinline__ void dihedral_terms(const Params& P, const Coef<R>& C, const Bank& B, int i, int nd,
                                                Acc<R>& a) {
     const int n = P.n;
     for (int k = 0; k < nd; ++k) {
         int4 e = B.dih[k * n + i];
-        int t = B.dt[k * n + i];
-        double4 xa = B.x[e.x];
-        double4 xb = B.x[e.y];
-        double4 xc = B.x[e.z];
-        double4 xd = B.x[e.w];
-        R b1x = (R)min_image(xb.x - xa.x, P.L, P.hL), b1y = (R)min_image(xb.y - xa.y, P.L, P.hL),
-          b1z = (R)min_image(xb.z - xa.z, P.L, P.hL);
-        R b2x = (R)min_image(xc.x - xb.x, P.L, P.hL), b2y = (R)min_image(xc.y - xb.y, P.L, P.hL),
-          b2z = (R)min_image(xc.z - xb.z, P.L, P.hL);
-        R b3x = (R)min_image(xd.x - xc.x, P.L, P.hL), b3y = (R)min_image(xd.y - xc.y, P.L, P.hL),
-          b3z = (R)min_image(xd.z - xc.z, P.L, P.hL);
-        R mx = b1y * b2z - b1z * b2y, my = b1z * b2x - b1x * b2z, mz = b1x * b2y - b1y * b2x;
-        R nx = b2y * b3z - b2z * b3y, ny = b2z * b3x - b2x * b3z, nz = b2x * b3y - b2y * b3x;
-        R m2 = (mx * mx + my * my) + mz * mz;
-        R n2 = (nx * nx + ny * ny) + nz * nz;
-        R b22 = (b2x * b2x + b2y * b2y) + b2z * b2z;
-        if (m2 < (R)1e-24 || n2 < (R)1e-24 || b22 < (R)1e-24) continue;   // collinear: no defined plane
-        R nb2 = r_sqrt<R>(b22);
-        R inv = r_rsqrt<R>(m2 * n2);
-        R cphi = ((mx * nx + my * ny) + mz * nz) * inv;
-        R sphi = nb2 * ((b1x * nx + b1y * ny) + b1z * nz) * inv;
-        R K = (R)P.dK[t], c0 = (R)P.dC0[t], s0 = (R)P.dS0[t];
-        R dU = K * (sphi * c0 - cphi * s0);   // dU/dphi
-        R sa = -nb2 * r_rcp<R>(m2), sd = nb2 * r_rcp<R>(n2), ib22 = r_rcp<R>(b22);
-        R gax = sa * mx, gay = sa * my, gaz = sa * mz;
-        R gdx = sd * nx, gdy = sd * ny, gdz = sd * nz;
-        R pp = ((b1x * b2x + b1y * b2y) + b1z * b2z) * ib22;
-        R qq = ((b3x * b2x + b3y * b2y) + b3z * b2z) * ib22;
-        R fx, fy, fz;
-        if (e.x == i) {
-            fx = -dU * gax; fy = -dU * gay; fz = -dU * gaz;
-        } else if (e.w == i) {
-            fx = -dU * gdx; fy = -dU * gdy; fz = -dU * gdz;
-        } else if (e.y == i) {
-            fx = -dU * (qq * gdx - (pp + (R)1) * gax);
-            fy = -dU * (qq * gdy - (pp + (R)1) * gay);
-            fz = -dU * (qq * gdz - (pp + (R)1) * gaz);
-        } else {
-            fx = -dU * (pp * gax - (qq + (R)1) * gdx);
-            fy = -dU * (pp * gay - (qq + (R)1) * gdy);
-            fz = -dU * (pp * gaz - (qq + (R)1) * gdz);
+        int t = B.dt[k * n + i] & (DB_MAXT - 1);
+        dihedral_one<R, MODE>(P, C, i, e, t, B.x[e.x], B.x[e.y], B.x[e.z], B.x[e.w], a);
+    }
+}
+
+// ---- bonded terms through the bead's halo ----------------------------------
+// The halo of bead i lists, once per topology and slot order, the distinct beads
+// its bonded terms reach (its bond partners first, in table order, then the
+// other members of its angles and dihedrals), and re-expresses every angle and
+// dihedral entry as the bead's role plus halo indices of the other members.
+// The step kernel then reads each of those positions once, as a separation from
+// bead i, instead of once per entry that names it.
+//   acode: role (2 bits) | other member 1 << 2 | other member 2 << 5 | type << 8
+//   dcode: role (2 bits) | others 1..3 << 2, 5, 8 (3 bits each) | type << 11
+__global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp, Bank B, Halo H) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int u[DB_MAXU];
+    const int nb = B.nb[i];
+#pragma unroll
+    for (int q = 0; q < DB_MAXU; ++q) u[q] = (q < DB_MAXB && q < nb) ? B.bp[q * n + i] : -1;
+    int nu = nb;
+    bool ovf = false;
+    // halo index of slot m, appended when new
+    auto code_of = [&](int m) -> int {
+        int idx = -1;
+#pragma unroll
+        for (int q = 0; q < DB_MAXU; ++q)
+            if (idx < 0 && q < nu && u[q] == m) idx = q;
+        if (idx >= 0) return idx;
+        if (nu >= DB_MAXU) {
+            ovf = true;
+            return 0;
         }
-        a.fx += (double)fx; a.fy += (double)fy; a.fz += (double)fz;
-        if (MODE == MODE_ENERGY) {
-            a.e_dih += (double)(K * ((R)1 - (cphi * c0 + sphi * s0))) / 4.0;
-            // virial about bead b: (x_a - x_b).F_a + (x_c - x_b).F_c + (x_d - x_b).F_d
-            R fa_x = -dU * gax, fa_y = -dU * gay, fa_z = -dU * gaz;
-            R fd_x = -dU * gdx, fd_y = -dU * gdy, fd_z = -dU * gdz;
-            R fc_x = -dU * (pp * gax - (qq + (R)1) * gdx), fc_y = -dU * (pp * gay - (qq + (R)1) * gdy),
-              fc_z = -dU * (pp * gaz - (qq + (R)1) * gdz);
-            R w = -(b1x * fa_x + b1y * fa_y + b1z * fa_z) + (b2x * fc_x + b2y * fc_y + b2z * fc_z) +
-                  ((b2x + b3x) * fd_x + (b2y + b3y) * fd_y + (b2z + b3z) * fd_z);
-            a.vir += (double)w / 4.0;
+#pragma unroll
+        for (int q = 0; q < DB_MAXU; ++q)
+            if (q == nu) u[q] = m;
+        return nu++;
+    };
+    const int na = B.na[i];
+    for (int k = 0; k < na; ++k) {
+        const int4 e = B.ang[k * n + i];
+        const int role = e.x == i ? 0 : (e.z == i ? 2 : 1);
+        const int m1 = role == 0 ? e.y : e.x;
+        const int m2 = role == 2 ? e.y : e.z;
+        const int c1 = code_of(m1);
+        const int c2 = code_of(m2);
+        H.acode[k * n + i] = (uint32_t)(role | c1 << 2 | c2 << 5 | (e.w & (DB_MAXT - 1)) << 8);
+    }
+    const int nd = B.nd[i];
+    for (int k = 0; k < nd; ++k) {
+        const int4 e = B.dih[k * n + i];
+        const int t = B.dt[k * n + i] & (DB_MAXT - 1);
+        const int role = e.x == i ? 0 : (e.w == i ? 3 : (e.y == i ? 1 : 2));
+        const int o1 = role == 0 ? e.y : e.x;
+        const int o2 = role <= 1 ? e.z : e.y;
+        const int o3 = role <= 2 ? e.w : e.z;
+        const int c1 = code_of(o1);
+        const int c2 = code_of(o2);
+        const int c3 = code_of(o3);
+        H.dcode[k * n + i] = (uint32_t)(role | c1 << 2 | c2 << 5 | c3 << 8 | t << 11);
+    }
+#pragma unroll
+    for (int q = 0; q < DB_MAXU; ++q)
+        if (q < nu) H.u[q * n + i] = u[q];
+    H.nu[i] = ovf ? (uint8_t)DB_HALO_OVF : (uint8_t)nu;
+}
+
+// all bonded forces on bead i from its halo (nu <= DB_MAXU entries).  The
+// separations are parked in LDS, one column per thread, so that angle and
+// dihedral entries can index them at run time without holding 24 registers.
+template <typename R>
+__device__ __forceinline__ void halo_bonded(const Params& P, const Coef<R>& C, const Bank& B, const Halo& H, int i,
+                                            const double4& xi, int nu, Acc<R>& a) {
+    const int n = P.n;
+    const int tid = threadIdx.x;
+    __shared__ R hs[3][DB_MAXU][DB_BLOCK];
+    R hx[DB_MAXU], hy[DB_MAXU], hz[DB_MAXU];
+    // separations x_k - x_i, four at a time
+#pragma unroll
+    for (int k0 = 0; k0 < DB_MAXU; k0 += 4) {
+        int s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] = k0 + q < nu ? H.u[(k0 + q) * n + i] : i;
+        double4 xk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xk[q] = B.x[s[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            hx[k0 + q] = (R)near_image(xk[q].x - xi.x, P);
+            hy[k0 + q] = (R)near_image(xk[q].y - xi.y, P);
+            hz[k0 + q] = (R)near_image(xk[q].z - xi.z, P);
+            hs[0][k0 + q][tid] = hx[k0 + q];
+            hs[1][k0 + q][tid] = hy[k0 + q];
+            hs[2][k0 + q][tid] = hz[k0 + q];
         }
+    }
+    // bonds: the first nb halo entries are the partners in table order
+    const int nb = B.nb[i];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        if (k >= nb) continue;
+        const int t = B.bt[k * n + i] & (DB_MAXT - 1);
+        const R rx = hx[k], ry = hy[k], rz = hz[k];
+        R rr2 = (rx * rx + ry * ry) + rz * rz;
+        if (!(rr2 > (R)0)) continue;
+        R ir = r_rsqrt<R>(rr2);
+        R r = rr2 * ir;
+        R g = (R)2.0 * C.bK[t] * (r - C.bR0[t]) * ir;   // F_i = g * (x_j - x_i)
+        a.fx += (double)(g * rx);
+        a.fy += (double)(g * ry);
+        a.fz += (double)(g * rz);
+    }
+    const int na = B.na[i];
+    for (int k = 0; k < na; ++k) {
+        const uint32_t code = H.acode[k * n + i];
+        const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, t = (code >> 8) & (DB_MAXT - 1);
+        const R s1x = hs[0][k1][tid], s1y = hs[1][k1][tid], s1z = hs[2][k1][tid];
+        const R s2x = hs[0][k2][tid], s2y = hs[1][k2][tid], s2z = hs[2][k2][tid];
+        // member positions relative to bead i (which sits at the origin)
+        const R z = (R)0;
+        const R pax = role == 0 ? z : s1x, pay = role == 0 ? z : s1y, paz = role == 0 ? z : s1z;
+        const R pbx = role == 0 ? s1x : (role == 1 ? z : s2x), pby = role == 0 ? s1y : (role == 1 ? z : s2y),
+                pbz = role == 0 ? s1z : (role == 1 ? z : s2z);
+        const R pcx = role == 2 ? z : s2x, pcy = role == 2 ? z : s2y, pcz = role == 2 ? z : s2z;
+        angle_core<R, MODE_STEP>(C, role, t, pax - pbx, pay - pby, paz - pbz, pcx - pbx, pcy - pby, pcz - pbz, a);
+    }
+    const int nd = B.nd[i];
+    for (int k = 0; k < nd; ++k) {
+        const uint32_t code = H.dcode[k * n + i];
+        const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, k3 = (code >> 8) & 7;
+        const int t = (code >> 11) & (DB_MAXT - 1);
+        const R s1x = hs[0][k1][tid], s1y = hs[1][k1][tid], s1z = hs[2][k1][tid];
+        const R s2x = hs[0][k2][tid], s2y = hs[1][k2][tid], s2z = hs[2][k2][tid];
+        const R s3x = hs[0][k3][tid], s3y = hs[1][k3][tid], s3z = hs[2][k3][tid];
+        const R z = (R)0;
+        const R pax = role == 0 ? z : s1x, pay = role == 0 ? z : s1y, paz = role == 0 ? z : s1z;
+        const R pbx = role == 0 ? s1x : (role == 1 ? z : s2x), pby = role == 0 ? s1y : (role == 1 ? z : s2y),
+                pbz = role == 0 ? s1z : (role == 1 ? z : s2z);
+        const R pcx = role <= 1 ? s2x : (role == 2 ? z : s3x), pcy = role <= 1 ? s2y : (role == 2 ? z : s3y),
+                pcz = role <= 1 ? s2z : (role == 2 ? z : s3z);
+        const R pdx = role == 3 ? z : s3x, pdy = role == 3 ? z : s3y, pdz = role == 3 ? z : s3z;
+        dihedral_core<R, MODE_STEP>(C, role, t, pbx - pax, pby - pay, pbz - paz, pcx - pbx, pcy - pby, pcz - pbz,
+                                    pdx - pcx, pdy - pcy, pdz - pcz, a);
     }
 }
 
@@ -371,13 +568,16 @@ __device__ __forceinline__ double temperature(const Params& P, int64_t step) {
 }
 
 template <typename R, int MODE>
-__global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B,
-                                                    NList NL, double4* __restrict__ xout, int64_t step, double pref,
+__global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
+                                                    double4* __restrict__ xout, int64_t step, double pref,
                                                     unsigned int* __restrict__ vmax2_slot,
                                                     double* __restrict__ fout, int* __restrict__ err) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
     const Params& P = *Pp;
     const int n = P.n;
+    __shared__ Coef<R> C;
+    load_coef<R>(P, C);
+    __syncthreads();
     int tile = xcd_tile(blockIdx.x, gridDim.x);
     int i = tile * DB_BLOCK + threadIdx.x;
     bool active = i < n;
@@ -386,11 +586,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
     double vx = 0, vy = 0, vz = 0;
     if (active) {
         xi = B.x[i];
-        int nb = B.nb[i];
+        const int nu = H.nu[i];
+        if (nu <= DB_MAXU) {
+            halo_bonded<R>(P, C, B, H, i, xi, nu, a);
+        } else {
+            // more distinct bonded partners than the halo holds: read them per entry
+            bond_terms<R, MODE_STEP>(P, C, B, i, xi, B.nb[i], a);
+            angle_terms<R, MODE_STEP>(P, C, B, i, B.na[i], a);
+            dihedral_terms<R, MODE_STEP>(P, C, B, i, B.nd[i], a);
+        }
         if (P.have_pair) list_pair_forces<R>(P, B, NL, i, xi, a);
-        bond_terms<R, MODE>(P, B, i, xi, nb, a);
-        angle_terms<R, MODE>(P, B, i, xi, B.na[i], a);
-        dihedral_terms<R, MODE>(P, B, i, xi, B.nd[i], a);
         if (MODE == MODE_FORCES) {
             int g = meta_gid(xi);
             fout[3 * (size_t)g] = a.fx;
@@ -453,6 +658,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ 
                                                       int64_t step, double* __restrict__ epart) {
     const Params& P = *Pp;
     const int n = P.n;
+    __shared__ Coef<R> C;
+    load_coef<R>(P, C);
+    __syncthreads();
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     double vals[6] = {0, 0, 0, 0, 0, 0};
     if (i < n) {
@@ -464,9 +672,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ 
         int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
         int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
         if (P.have_pair) pair_forces<R, MODE_ENERGY>(P, B, cstart, clist, i, xi, nb, p0, p1, p2, p3, a);
-        bond_terms<R, MODE_ENERGY>(P, B, i, xi, nb, a);
-        angle_terms<R, MODE_ENERGY>(P, B, i, xi, B.na[i], a);
-        dihedral_terms<R, MODE_ENERGY>(P, B, i, xi, B.nd[i], a);
+        bond_terms<R, MODE_ENERGY>(P, C, B, i, xi, nb, a);
+        angle_terms<R, MODE_ENERGY>(P, C, B, i, B.na[i], a);
+        dihedral_terms<R, MODE_ENERGY>(P, C, B, i, B.nd[i], a);
         double vx = B.v[i], vy = B.v[n + i], vz = B.v[2 * n + i];
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
@@ -514,6 +722,7 @@ static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOC
 
 void launch_build_nlist(db_ctx* c) {
     if (c->n == 0) return;
+    hipLaunchKernelGGL(k_halo, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur], c->halo);
     hipLaunchKernelGGL(k_build_nlist, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
                        c->cells.start, c->cells.xs, c->nlist, c->err_d);
 }
@@ -536,10 +745,10 @@ void launch_step(db_ctx* c, int64_t step, int slot_in_block) {
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
     if (c->precision == DB_MIXED)
         hipLaunchKernelGGL((k_step<float, MODE_STEP>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
-                           c->nlist, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
+                           c->nlist, c->halo, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
     else
         hipLaunchKernelGGL((k_step<double, MODE_STEP>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           B, c->nlist, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
+                           B, c->nlist, c->halo, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;
@@ -550,10 +759,10 @@ void launch_forces(db_ctx* c, double* f) {
     Bank& B = c->bank[c->cur];
     if (c->precision == DB_MIXED)
         hipLaunchKernelGGL((k_step<float, MODE_FORCES>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           B, c->nlist, (double4*)nullptr, (int64_t)0, 0.0, (unsigned*)nullptr, f, c->err_d);
+                           B, c->nlist, c->halo, (double4*)nullptr, (int64_t)0, 0.0, (unsigned*)nullptr, f, c->err_d);
     else
         hipLaunchKernelGGL((k_step<double, MODE_FORCES>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream,
-                           c->dp, B, c->nlist, (double4*)nullptr, (int64_t)0, 0.0,
+                           c->dp, B, c->nlist, c->halo, (double4*)nullptr, (int64_t)0, 0.0,
                            (unsigned*)nullptr, f, c->err_d);
 }
 

@@ -493,6 +493,61 @@ def isolated_pairs(m, r, L_per_pair=4.0, seed=0, types=(A, T)) -> System:
                   reactive=np.ones(n, dtype=np.uint8), bonds=np.zeros((0, 4), dtype=np.int32))
 
 
+def branched_clusters(m, spacing=6.0, seed=0, T=1.0) -> System:
+    """m star-shaped clusters on a cubic lattice: a hub bonded to three arms, each
+    arm bonded to two leaves (bond length about 1), with explicit angles (arm-hub-arm,
+    hub-arm-leaf, leaf-arm-leaf; type 1) and dihedrals (leaf-arm-hub-arm; type 1).
+    Hubs and arms each meet nine distinct beads through their bonded terms, leaves
+    five.  Bonds are type 1 on both sides."""
+    rng = np.random.default_rng(seed)
+    k = int(math.ceil(m ** (1.0 / 3.0)))
+    L = k * spacing
+    xs, bonds, angles, dihedrals = [], [], [], []
+    arm_dirs = np.array([[1.0, 0.0, 0.0], [-0.5, 0.866, 0.0], [-0.5, -0.866, 0.0]])
+    for q in range(m):
+        c = np.array([q % k, (q // k) % k, q // (k * k)], dtype=np.float64) * spacing + 0.5 * spacing
+        R = _rotation(rng)
+        base = len(xs)
+        hub = base
+        xs.append(c)
+        arms, leaves = [], []
+        for a in range(3):
+            d = R @ arm_dirs[a]
+            pa = c + d
+            arms.append(len(xs))
+            xs.append(pa)
+        for a in range(3):
+            d = R @ arm_dirs[a]
+            side = R @ np.array([0.0, 0.0, 1.0])
+            two = []
+            for sgn in (1.0, -1.0):
+                u = d + 0.9 * sgn * side
+                u /= np.linalg.norm(u)
+                two.append(len(xs))
+                xs.append(xs[arms[a]] + u)
+            leaves.append(two)
+        for a in range(3):
+            bonds.append((hub, arms[a], 1, 1))
+            for lf in leaves[a]:
+                bonds.append((arms[a], lf, 1, 1))
+        for a in range(3):
+            for b in range(a + 1, 3):
+                angles.append((1, arms[a], hub, arms[b]))
+            for lf in leaves[a]:
+                angles.append((1, hub, arms[a], lf))
+            angles.append((1, leaves[a][0], arms[a], leaves[a][1]))
+        for a in range(3):
+            for b in range(3):
+                if a != b:
+                    for lf in leaves[a]:
+                        dihedrals.append((1, lf, arms[a], hub, arms[b]))
+    x = wrap(np.array(xs) + rng.normal(0, 0.03, size=(len(xs), 3)), L)
+    n = len(xs)
+    return System(L=float(L), x=x, v=maxwell_boltzmann(rng, n, T), type=np.full(n, 1, dtype=np.int32),
+                  reactive=np.zeros(n, dtype=np.uint8), bonds=np.array(bonds, dtype=np.int32),
+                  angles=np.array(angles, dtype=np.int32), dihedrals=np.array(dihedrals, dtype=np.int32))
+
+
 # ----------------------------------------------------------------------------------
 # the paper's 1-bead model (Fig. 2), as a topology fixture
 # ----------------------------------------------------------------------------------

@@ -61,6 +61,17 @@ def test_forces_fig2_model_dihedral_phases():
     assert rel_l2(g.forces(), o.forces()) <= FP64_TOL
 
 
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_forces_wide_bonded_neighbourhood(precision, tol):
+    """Hubs and arms reach nine distinct beads through their bonded terms, more
+    than the per-bead halo holds, so they take the per-entry path while the leaves
+    take the halo path; both must match the oracle."""
+    s = synth.branched_clusters(27, seed=4)
+    ff = synth.ForceField(bonds={1: (30.0, 1.0)}, angles={1: (5.0, 1.9)}, dihedrals={1: (2.0, 0.4)})
+    g, o = both(s, ff, synth.RuleSet(), precision=precision, generate=False)
+    assert rel_l2(g.forces(), o.forces()) <= tol
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_energy_matches_oracle(precision):
     s = _duplex_system(37, 7, 0.3, seed=2)
