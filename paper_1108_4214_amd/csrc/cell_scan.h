@@ -15,7 +15,32 @@ __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
     return d < -hL ? hi : r;
 }
 
-// f(j, r2f) for every j != i in the 27 cells around xi with float r2 < cut2
+// f(j, r2f) for every j != i in the cells around xi with float r2 < cut2.
+// With three or more cells per edge, the periodic image of a neighbour cell is
+// fixed by whether its index wrapped, so the bead's own coordinates are shifted
+// once per run and the candidates need no minimum-image test (the true nearest
+// image is that one for every candidate within one cell edge).  Smaller grids
+// visit every cell once and take the per-candidate minimum image.  The visitor
+// has a single call site per grid case, which keeps it inlined once.
+template <class F>
+__device__ __forceinline__ void scan_run(const float4* __restrict__ xs, int s0, int s1, int i, float qx, float qy,
+                                         float qz, float cut2, F&& f) {
+    for (int p = s0; p < s1; p += 4) {
+        float4 e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = xs[min(p + q, s1 - 1)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            // one branch per candidate: range, self and distance folded into one predicate
+            const int j = __float_as_int(e[q].w);
+            const float dx = e[q].x - qx, dy = e[q].y - qy, dz = e[q].z - qz;
+            const float r2 = (dx * dx + dy * dy) + dz * dz;
+            const bool hit = (p + q < s1) & (j != i) & (r2 < cut2);
+            if (hit) f(j, r2);
+        }
+    }
+}
+
 template <class F>
 __device__ __forceinline__ void scan_cells(const Params& P, const int* __restrict__ cstart,
                                            const float4* __restrict__ xs, int i, const double4& xi, float cut2,
@@ -26,37 +51,50 @@ __device__ __forceinline__ void scan_cells(const Params& P, const int* __restric
     const int cz = cell_coord(xi.z, P.cell_scale, nc);
     const float Lf = (float)P.L, hLf = (float)P.hL;
     const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
-    const bool rowmerge = (P.noff == 3) && cx >= 1 && cx <= nc - 2;
+    if (P.noff == 3) {
+        // nine x-rows of three cells; a row that wraps in x splits into two runs
+        // (the wrapped cell seen through its image, and the two contiguous ones),
+        // so each row is visited as two runs, the second empty unless it wraps
+        auto shift = [&](int c) { return c < 0 ? -Lf : (c >= nc ? Lf : 0.0f); };
+        for (int r = 0; r < 18; ++r) {
+            const int zr = cz + r / 6 - 1, yr = cy + (r >> 1) % 3 - 1, part = r & 1;
+            const float qz = pz - shift(zr), qy = py - shift(yr);
+            const int row = (wrap_cell(zr, nc) * nc + wrap_cell(yr, nc)) * nc;
+            int a0, a1;          // cell range [a0, a1) of the row, contiguous in the list
+            float qx = px;
+            if (cx >= 1 && cx <= nc - 2) {
+                a0 = part ? 0 : cx - 1;
+                a1 = part ? 0 : cx + 2;
+            } else if (cx == 0) {
+                a0 = part ? 0 : nc - 1;
+                a1 = part ? 2 : nc;
+                if (!part) qx = px + Lf;
+            } else {
+                a0 = part ? 0 : nc - 2;
+                a1 = part ? 1 : nc;
+                if (part) qx = px - Lf;
+            }
+            const int s0 = a1 > a0 ? cstart[row + a0] : 0;
+            const int s1 = a1 > a0 ? cstart[row + a1] : 0;
+            scan_run(xs, s0, s1, i, qx, qy, qz, cut2, f);
+        }
+        return;
+    }
     for (int oz = 0; oz < P.noff; ++oz) {
         const int zz = wrap_cell(cz + P.off[oz], nc);
         for (int oy = 0; oy < P.noff; ++oy) {
             const int row = (zz * nc + wrap_cell(cy + P.off[oy], nc)) * nc;
-            const int nseg = rowmerge ? 1 : P.noff;
-            for (int ox = 0; ox < nseg; ++ox) {
-                int s0, s1;
-                if (rowmerge) {
-                    s0 = cstart[row + cx - 1];
-                    s1 = cstart[row + cx + 2];
-                } else {
-                    const int c = row + wrap_cell(cx + P.off[ox], nc);
-                    s0 = cstart[c];
-                    s1 = cstart[c + 1];
-                }
-                for (int p = s0; p < s1; p += 4) {
-                    float4 e[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) e[q] = xs[min(p + q, s1 - 1)];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        // one branch per candidate: range, self and distance folded into one predicate
-                        const int j = __float_as_int(e[q].w);
-                        const float dx = fmin_image(e[q].x - px, Lf, hLf);
-                        const float dy = fmin_image(e[q].y - py, Lf, hLf);
-                        const float dz = fmin_image(e[q].z - pz, Lf, hLf);
-                        const float r2 = (dx * dx + dy * dy) + dz * dz;
-                        const bool hit = (p + q < s1) & (j != i) & (r2 < cut2);
-                        if (hit) f(j, r2);
-                    }
+            for (int ox = 0; ox < P.noff; ++ox) {
+                const int c = row + wrap_cell(cx + P.off[ox], nc);
+                const int s0 = cstart[c], s1 = cstart[c + 1];
+                for (int p = s0; p < s1; ++p) {
+                    const float4 e = xs[p];
+                    const int j = __float_as_int(e.w);
+                    const float dx = fmin_image(e.x - px, Lf, hLf);
+                    const float dy = fmin_image(e.y - py, Lf, hLf);
+                    const float dz = fmin_image(e.z - pz, Lf, hLf);
+                    const float r2 = (dx * dx + dy * dy) + dz * dz;
+                    if ((j != i) & (r2 < cut2)) f(j, r2);
                 }
             }
         }

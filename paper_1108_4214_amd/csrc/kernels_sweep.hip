@@ -19,36 +19,45 @@ namespace db {
 
 enum { ST_CREATED = 0, ST_BROKEN, ST_KILLED, ST_CONVERTED, ST_ANG_NEW, ST_ANG_DEL, ST_DIH_NEW, ST_DIH_DEL };
 
+// A bead's bond table held in registers.  Entries are read through selects, so
+// loops over a run-time count never index a private array (which would spill it
+// to scratch memory).
 struct Tab {
+    static_assert(DB_MAXB == 4, "Tab holds four entries");
     int n;
-    int p[DB_MAXB];
-    int t[DB_MAXB];
+    int p0, p1, p2, p3;
+    int t0, t1, t2, t3;
+    __device__ int p(int k) const { return k == 0 ? p0 : (k == 1 ? p1 : (k == 2 ? p2 : p3)); }
+    __device__ int t(int k) const { return k == 0 ? t0 : (k == 1 ? t1 : (k == 2 ? t2 : t3)); }
 };
 
 __device__ __forceinline__ Tab load_tab(const Bank& B, int n, int s) {
     Tab T;
     T.n = B.nb[s];
-#pragma unroll
-    for (int k = 0; k < DB_MAXB; ++k) {
-        T.p[k] = k < T.n ? B.bp[k * n + s] : -1;
-        T.t[k] = k < T.n ? (int)B.bt[k * n + s] : 0;
-    }
+    T.p0 = T.n > 0 ? B.bp[s] : -1;
+    T.p1 = T.n > 1 ? B.bp[n + s] : -1;
+    T.p2 = T.n > 2 ? B.bp[2 * n + s] : -1;
+    T.p3 = T.n > 3 ? B.bp[3 * n + s] : -1;
+    T.t0 = T.n > 0 ? (int)B.bt[s] : 0;
+    T.t1 = T.n > 1 ? (int)B.bt[n + s] : 0;
+    T.t2 = T.n > 2 ? (int)B.bt[2 * n + s] : 0;
+    T.t3 = T.n > 3 ? (int)B.bt[3 * n + s] : 0;
     return T;
 }
 
 __device__ __forceinline__ int tab_type_of(const Tab& T, int v) {
     for (int k = 0; k < T.n; ++k)
-        if (T.p[k] == v) return T.t[k];
+        if (T.p(k) == v) return T.t(k);
     return -1;
 }
 __device__ __forceinline__ bool tab_has(const Tab& T, int v) {
     for (int k = 0; k < T.n; ++k)
-        if (T.p[k] == v) return true;
+        if (T.p(k) == v) return true;
     return false;
 }
 __device__ __forceinline__ int tab_count(const Tab& T, int t) {
     int c = 0;
-    for (int k = 0; k < T.n; ++k) c += (T.t[k] == t);
+    for (int k = 0; k < T.n; ++k) c += (T.t(k) == t);
     return c;
 }
 __device__ __forceinline__ bool type_ok(int rule_bead, int bead_type) { return rule_bead == 0 || rule_bead == bead_type; }
@@ -68,121 +77,100 @@ __device__ __forceinline__ void stat_add(unsigned long long* st, int k, unsigned
 }
 
 // ---- step 2: creation nomination -------------------------------------------------
-// Visitor of the neighbour scan: every candidate that passes the float prefilter is
+// Every candidate that passes the float prefilter of the neighbour scan is
 // re-tested with the exact double arithmetic of the method (minimum-image
 // separation summed as (dx^2 + dy^2) + dz^2, strict comparison), then against the
 // rules in call order (the last applicable one wins), maxbond on both beads and
 // the graph distance; the closest survivor (ties: lower id) is nominated.
-struct CreateVisitor {
-    struct Ctx {
-        SweepBuf S;
-    };
-    const Params& P;
-    const Bank& B;
-    Ctx c;
-    int i, ti, gi;
-    double4 xi;
-    Tab Ti;
-    bool can;
-    int best, best_rule, best_bt, best_g;
-    double best_r2;
-    __device__ static float cut2(const Params& P) { return (float)(P.rmax2_create * 1.0001); }
-    // some creation rule admits bead i in one of its two roles (reactive, type, maxbond)
-    __device__ static bool admits(const Params& P, int ti, const Tab& Ti) {
-        for (int q = 0; q < P.nrule; ++q) {
-            const Rule& r = P.rule[q];
-            if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
-            if ((type_ok(r.b1, ti) && max_ok(P, ti, Ti, r.bt1)) || (type_ok(r.b2, ti) && max_ok(P, ti, Ti, r.bt2)))
-                return true;
-        }
-        return false;
+
+// some creation rule admits a bead of type ti holding table Ti in one of its two
+// roles (type and maxbond)
+__device__ __forceinline__ bool create_admits(const Params& P, int ti, const Tab& Ti) {
+    for (int q = 0; q < P.nrule; ++q) {
+        const Rule& r = P.rule[q];
+        if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
+        if ((type_ok(r.b1, ti) && max_ok(P, ti, Ti, r.bt1)) || (type_ok(r.b2, ti) && max_ok(P, ti, Ti, r.bt2)))
+            return true;
     }
-    __device__ CreateVisitor(const Params& P_, const Bank& B_, int i_, const double4& xi_, const Ctx& c_, bool live)
-        : P(P_), B(B_), c(c_), i(i_), xi(xi_), can(false), best(-1), best_rule(-1), best_bt(0), best_g(0),
-          best_r2(0.0) {
-        if (!live) return;
-        int mi = meta_word(xi);
-        ti = meta_type(mi);
-        gi = meta_gid(xi);
-        can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
-        if (can) {
-            Ti = load_tab(B, P.n, i);
-            can = admits(P, ti, Ti);
-        }
-    }
-    __device__ bool active() const { return can; }
-    __device__ void candidate(int j, float) {
-        const int n = P.n;
-        double4 xj = B.x[j];
-        int mj = meta_word(xj);
-        if (!meta_reactive(mj)) return;
-        double dx, dy, dz;
-        double r2 = separation(P, xi, xj, dx, dy, dz);
-        if (!(r2 < P.rmax2_create)) return;
-        int tj = meta_type(mj);
-        int gj = meta_gid(xj);
-        // last creation rule that applies to the pair
-        int rule = -1, bti = 0;
-        bool have_tj = false;
-        Tab Tj;
-        for (int q = 0; q < P.nrule; ++q) {
-            const Rule& r = P.rule[q];
-            if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
-            bool o1 = type_ok(r.b1, ti) && type_ok(r.b2, tj);
-            bool o2 = type_ok(r.b1, tj) && type_ok(r.b2, ti);
-            if (!o1 && !o2) continue;
-            if (o1 && o2) o1 = gi < gj;   // both orientations: the lower id plays bead1
-            int si = o1 ? r.bt1 : r.bt2;
-            int sj = o1 ? r.bt2 : r.bt1;
-            if (!(r2 < r.r2)) continue;
-            if (!max_ok(P, ti, Ti, si)) continue;
-            if (!have_tj) {
-                Tj = load_tab(B, n, j);
-                have_tj = true;
-            }
-            if (!max_ok(P, tj, Tj, sj)) continue;
-            rule = q;
-            bti = si;
-        }
-        if (rule < 0) return;
-        // graph distance 1, 2 or 3 on the bond graph before the sweep
-        if (tab_has(Ti, j)) return;
-        bool d2 = false;
-        for (int a = 0; a < Ti.n && !d2; ++a)
-            if (tab_has(Tj, Ti.p[a])) d2 = true;
-        if (d2 && !P.pc13) return;
-        if (!d2 && !P.pc14) {
-            for (int a = 0; a < Ti.n; ++a) {
-                Tab Tq = load_tab(B, n, Ti.p[a]);
-                for (int b = 0; b < Tj.n; ++b)
-                    if (tab_has(Tq, Tj.p[b])) return;
-            }
-        }
-        if (best < 0 || r2 < best_r2 || (r2 == best_r2 && gj < best_g)) {
-            best = j;
-            best_r2 = r2;
-            best_g = gj;
-            best_rule = rule;
-            best_bt = bti;
-        }
-    }
-    __device__ void finish() {
-        c.S.nomC[i] = best;
-        c.S.ruleC[i] = (int8_t)best_rule;
-        c.S.btC[i] = (int8_t)best_bt;
-    }
-};
+    return false;
+}
 
 __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
                                                               const int* __restrict__ cstart,
                                                               const float4* __restrict__ xs, SweepBuf S) {
     const Params& P = *Pp;
+    const int n = P.n;
     const int i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
-    if (i >= P.n) return;
+    if (i >= n) return;
     const double4 xi = B.x[i];
-    CreateVisitor v(P, B, i, xi, CreateVisitor::Ctx{S}, true);
-    if (v.active()) scan_cells(P, cstart, xs, i, xi, CreateVisitor::cut2(P), [&](int j, float r2f) { v.candidate(j, r2f); });
-    v.finish();
+    const int mi = meta_word(xi);
+    const int ti = meta_type(mi);
+    const int gi = meta_gid(xi);
+    int best = -1, best_rule = -1, best_bt = 0, best_g = 0;
+    double best_r2 = 0.0;
+    bool can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
+    const Tab Ti = can ? load_tab(B, n, i) : Tab{0, -1, -1, -1, -1, 0, 0, 0, 0};
+    can = can && create_admits(P, ti, Ti);
+    if (can) {
+        const float cut2 = (float)(P.rmax2_create * 1.0001);
+        scan_cells(P, cstart, xs, i, xi, cut2, [&](int j, float) {
+            const double4 xj = B.x[j];
+            const int mj = meta_word(xj);
+            if (!meta_reactive(mj)) return;
+            double dx, dy, dz;
+            const double r2 = separation(P, xi, xj, dx, dy, dz);
+            if (!(r2 < P.rmax2_create)) return;
+            const int tj = meta_type(mj);
+            const int gj = meta_gid(xj);
+            // last creation rule that applies to the pair
+            int rule = -1, bti = 0;
+            bool have_tj = false;
+            Tab Tj{0, -1, -1, -1, -1, 0, 0, 0, 0};
+            for (int q = 0; q < P.nrule; ++q) {
+                const Rule& r = P.rule[q];
+                if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
+                bool o1 = type_ok(r.b1, ti) && type_ok(r.b2, tj);
+                const bool o2 = type_ok(r.b1, tj) && type_ok(r.b2, ti);
+                if (!o1 && !o2) continue;
+                if (o1 && o2) o1 = gi < gj;   // both orientations: the lower id plays bead1
+                const int si = o1 ? r.bt1 : r.bt2;
+                const int sj = o1 ? r.bt2 : r.bt1;
+                if (!(r2 < r.r2)) continue;
+                if (!max_ok(P, ti, Ti, si)) continue;
+                if (!have_tj) {
+                    Tj = load_tab(B, n, j);
+                    have_tj = true;
+                }
+                if (!max_ok(P, tj, Tj, sj)) continue;
+                rule = q;
+                bti = si;
+            }
+            if (rule < 0) return;
+            // graph distance 1, 2 or 3 on the bond graph before the sweep
+            if (tab_has(Ti, j)) return;
+            bool d2 = false;
+            for (int a = 0; a < Ti.n && !d2; ++a)
+                if (tab_has(Tj, Ti.p(a))) d2 = true;
+            if (d2 && !P.pc13) return;
+            if (!d2 && !P.pc14) {
+                for (int a = 0; a < Ti.n; ++a) {
+                    const Tab Tq = load_tab(B, n, Ti.p(a));
+                    for (int b = 0; b < Tj.n; ++b)
+                        if (tab_has(Tq, Tj.p(b))) return;
+                }
+            }
+            if (best < 0 || r2 < best_r2 || (r2 == best_r2 && gj < best_g)) {
+                best = j;
+                best_r2 = r2;
+                best_g = gj;
+                best_rule = rule;
+                best_bt = bti;
+            }
+        });
+    }
+    S.nomC[i] = best;
+    S.ruleC[i] = (int8_t)best_rule;
+    S.btC[i] = (int8_t)best_bt;
 }
 
 // ---- steps 3 and 5: breakage nomination and killbond marks ----------------------
@@ -202,7 +190,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         Tab Ti = load_tab(B, n, i);
         int ti = meta_type(mi);
         for (int k = 0; k < Ti.n; ++k) {
-            int j = Ti.p[k], t = Ti.t[k];
+            int j = Ti.p(k), t = Ti.t(k);
             double4 xj = B.x[j];
             int mj = meta_word(xj);
             if (!meta_reactive(mj)) continue;
@@ -393,7 +381,7 @@ __device__ int match_dihedral(const Params& P, int ta, int tb, int tc, int td, i
 
 struct Gen {
     const Params& P;
-    const Bank& B;
+    const Bank B;   // by value: a reference to the kernel argument would force a private copy
     const SweepBuf& S;
     int n;
     bool all;
@@ -415,7 +403,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
         // only beads within two bonds of a new bond can lie on a qualifying path
         bool dirty = S.newp[i] >= 0;
         for (int a = 0; a < Ti.n && !dirty; ++a) {
-            int q = Ti.p[a];
+            int q = Ti.p(a);
             if (S.newp[q] >= 0) dirty = true;
             int nq = B.nb[q];
             for (int m = 0; m < nq && !dirty; ++m)
@@ -460,10 +448,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     if (P.narule) {
         for (int k1 = 0; k1 < Ti.n; ++k1)
             for (int k2 = k1 + 1; k2 < Ti.n; ++k2) {
-                int a = Ti.p[k1], c = Ti.p[k2];
+                int a = Ti.p(k1), c = Ti.p(k2);
                 if (a == c) continue;
                 if (!(g.is_new(i, a) || g.is_new(i, c))) continue;
-                int t = match_angle(P, g.type_of(a), ti, g.type_of(c), Ti.t[k1], Ti.t[k2]);
+                int t = match_angle(P, g.type_of(a), ti, g.type_of(c), Ti.t(k1), Ti.t(k2));
                 if (t) {
                     push_angle(a, i, c, t);
                     ++ang_new;
@@ -471,15 +459,15 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
             }
         // angles with i at an end: i - b - c
         for (int k = 0; k < Ti.n; ++k) {
-            int b = Ti.p[k];
+            int b = Ti.p(k);
             Tab Tb = load_tab(B, n, b);
             int t_bi = tab_type_of(Tb, i);
             int tb = g.type_of(b);
             for (int m = 0; m < Tb.n; ++m) {
-                int c = Tb.p[m];
+                int c = Tb.p(m);
                 if (c == i) continue;
                 if (!(g.is_new(i, b) || g.is_new(b, c))) continue;
-                int t = match_angle(P, ti, tb, g.type_of(c), t_bi, Tb.t[m]);
+                int t = match_angle(P, ti, tb, g.type_of(c), t_bi, Tb.t(m));
                 if (t) push_angle(i, b, c, t);
             }
         }
@@ -487,41 +475,41 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     if (P.ndrule) {
         // dihedrals with i at an end: i - b - c - d
         for (int k = 0; k < Ti.n; ++k) {
-            int b = Ti.p[k];
+            int b = Ti.p(k);
             Tab Tb = load_tab(B, n, b);
             int t_bi = tab_type_of(Tb, i);
             int tb = g.type_of(b);
             for (int m = 0; m < Tb.n; ++m) {
-                int c = Tb.p[m];
+                int c = Tb.p(m);
                 if (c == i) continue;
                 Tab Tc = load_tab(B, n, c);
                 int t_cb = tab_type_of(Tc, b);
                 int tc = g.type_of(c);
                 for (int q = 0; q < Tc.n; ++q) {
-                    int d = Tc.p[q];
+                    int d = Tc.p(q);
                     if (d == b || d == i) continue;
                     if (!(g.is_new(i, b) || g.is_new(b, c) || g.is_new(c, d))) continue;
-                    int t = match_dihedral(P, ti, tb, tc, g.type_of(d), t_bi, Tb.t[m], t_cb, Tc.t[q]);
+                    int t = match_dihedral(P, ti, tb, tc, g.type_of(d), t_bi, Tb.t(m), t_cb, Tc.t(q));
                     if (t) push_dih(i, b, c, d, t);
                 }
             }
         }
         // dihedrals with i second: a - i - c - d
         for (int k1 = 0; k1 < Ti.n; ++k1) {
-            int a = Ti.p[k1];
+            int a = Ti.p(k1);
             int ta = g.type_of(a);
             for (int k2 = 0; k2 < Ti.n; ++k2) {
                 if (k2 == k1) continue;
-                int c = Ti.p[k2];
+                int c = Ti.p(k2);
                 if (c == a) continue;
                 Tab Tc = load_tab(B, n, c);
                 int t_ci = tab_type_of(Tc, i);
                 int tc = g.type_of(c);
                 for (int q = 0; q < Tc.n; ++q) {
-                    int d = Tc.p[q];
+                    int d = Tc.p(q);
                     if (d == i || d == a) continue;
                     if (!(g.is_new(a, i) || g.is_new(i, c) || g.is_new(c, d))) continue;
-                    int t = match_dihedral(P, ta, ti, tc, g.type_of(d), Ti.t[k1], Ti.t[k2], t_ci, Tc.t[q]);
+                    int t = match_dihedral(P, ta, ti, tc, g.type_of(d), Ti.t(k1), Ti.t(k2), t_ci, Tc.t(q));
                     if (t && push_dih(a, i, c, d, t)) ++dih_new;
                 }
             }
