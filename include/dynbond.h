@@ -178,6 +178,35 @@ int db_profile(db_ctx* ctx, int enable);
  * launches timed since the last call, and their number; resets the tally */
 int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);
 
+/* tries skin in {0.4, 0.5, 0.6, 0.8} x permute_every in {1, 2, 4, 8}, running
+ * steps_per_trial steps of the trajectory with each (the system advances by
+ * 16 x steps_per_trial steps), and keeps the fastest; best_skin / best_permute
+ * (either may be NULL) receive the choice */
+int db_autotune(db_ctx* ctx, int64_t steps_per_trial, double* best_skin, int32_t* best_permute);
+
+/* ---- batches of independent replicas ------------------------------------------ */
+/* Not in the paper: many small boxes (replicas of a parameter ladder) are
+ * advanced together so that every kernel launch covers all of them.
+ *
+ * db_batch_create builds a new handle holding copies of the n_rep configured
+ * replica handles (state, reactive flags, topology, step counter).  The
+ * replicas must agree on precision, force field, dt, gamma, rules and step
+ * counter; each keeps its own bead count, box edge, seed and temperature
+ * schedule, and evolves exactly as it would alone (bead ids and random numbers
+ * are per replica).  The replica handles are not modified or referenced
+ * afterwards.  Global bead ids of the batch are the replicas' ids offset by the
+ * bead counts of the replicas before them, in the order given; db_get_bonds and
+ * the other getters of the batch handle use global ids; db_batch_get_state
+ * returns one replica's positions and velocities in its own ids.  State and
+ * topology setters on a batch handle fail with DB_ESTATE; force-field, rule,
+ * thermostat (applied to every replica) and tuning calls work as for a single
+ * system.  Free with db_destroy.
+ * Errors: DB_EINVAL for n_rep < 1 or > 65535, a NULL replica, a replica without
+ * state or mismatched physics; device errors as for db_create. */
+int db_batch_create(db_ctx** out, db_ctx* const* replicas, int32_t n_rep, void* hip_stream);
+/* x, v: that replica's N_r x 3 arrays (either may be NULL), host or device */
+int db_batch_get_state(db_ctx* batch, int32_t replica, double* x, double* v, int on_device);
+
 #ifdef __cplusplus
 }
 #endif

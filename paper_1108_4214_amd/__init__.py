@@ -31,7 +31,8 @@ EXPORTS = [
     "db_bond_create_dir", "db_bond_break", "db_bond_kill", "db_bond_convert", "db_max_bonds",
     "db_angle_pattern", "db_dihedral_pattern", "db_step", "db_sweep_now", "db_forces", "db_energy",
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
-    "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time",
+    "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
+    "db_batch_create", "db_batch_get_state",
 ]
 
 STAT_FIELDS = [
@@ -100,6 +101,9 @@ _SIG = {
     "db_tune": [_P, _d, _i32],
     "db_profile": [_P, _int],
     "db_step_kernel_time": [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+    "db_autotune": [_P, _i64, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
+    "db_batch_create": [C.POINTER(C.c_void_p), _P, _i32, _P],
+    "db_batch_get_state": [_P, _i32, _P, _P, _int],
 }
 for _name, _args in _SIG.items():
     _f = getattr(_lib, _name)
@@ -350,6 +354,29 @@ def db_step_kernel_time(ctx):
     return float(us.value), int(n.value)
 
 
+def db_autotune(ctx, steps_per_trial):
+    sk = C.c_double()
+    pe = C.c_int32()
+    _check(ctx, _lib.db_autotune(ctx, int(steps_per_trial), C.byref(sk), C.byref(pe)))
+    return float(sk.value), int(pe.value)
+
+
+def db_batch_create(replica_ctxs, hip_stream=None):
+    arr = (C.c_void_p * len(replica_ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in replica_ctxs])
+    h = C.c_void_p()
+    rc = _lib.db_batch_create(C.byref(h), C.cast(arr, C.c_void_p), len(replica_ctxs),
+                              C.c_void_p(hip_stream) if hip_stream else None)
+    if rc != DB_OK:
+        raise DynBondError(rc, "db_batch_create rejected its replicas")
+    return h
+
+
+def db_batch_get_state(ctx, replica, x, v):
+    dev = _on_device(x) if x is not None else _on_device(v)
+    _check(ctx, _lib.db_batch_get_state(ctx, int(replica), _ptr(x), _ptr(v), dev))
+    return x, v
+
+
 # ---- object wrapper ---------------------------------------------------------------------
 
 class System:
@@ -455,3 +482,19 @@ class System:
 
     def set_step(self, st):
         db_set_step(self.ctx, st)
+
+
+class Batch(System):
+    """Independent replicas (configured ``System`` objects) advanced by shared
+    kernel launches; the replicas are copied, not referenced."""
+
+    def __init__(self, replicas, hip_stream=None):
+        self.sizes = [r.n for r in replicas]
+        self.n = int(sum(self.sizes))
+        self.ctx = db_batch_create([r.ctx for r in replicas], hip_stream)
+
+    def replica_state(self, r):
+        x = np.zeros((self.sizes[r], 3))
+        v = np.zeros((self.sizes[r], 3))
+        db_batch_get_state(self.ctx, r, x, v)
+        return x, v

@@ -12,6 +12,7 @@
 // the block's positions and velocities are restored and the block is re-run
 // with a fresh cell list at every step.  The interval adapts to the speeds seen.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,6 +58,7 @@ struct HostSys {
     std::vector<int32_t> bonds;   // 4 per bond: i, j, t_ij, t_ji
     std::vector<int32_t> ang;     // 4 per angle: type, a, b, c (a < c)
     std::vector<int32_t> dih;     // 5 per dihedral: type, a, b, c, d (a < d)
+    std::vector<uint16_t> rep;    // replica of each bead (batches only)
 };
 
 }  // namespace
@@ -95,7 +97,8 @@ static int fail(db_ctx* c, int code, const char* fmt, ...) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static int ncell_cap(int n) { return 2 * n + 64; }
+// cell budget: at most 2 n + 64 cells per box
+static int ncell_cap(const db_ctx* c) { return 2 * c->n + 64 * std::max(1, c->nrep); }
 
 static int blocksum_ints(int count) {
     int tot = 2;
@@ -121,7 +124,7 @@ struct Layout {
 
 static size_t layout(db_ctx* c, bool assign) {
     const size_t n = (size_t)std::max(c->n, 1);
-    const size_t nc = (size_t)ncell_cap(c->n);
+    const size_t nc = (size_t)ncell_cap(c);
     Layout L;
     auto put = [&](auto*& p, size_t bytes) {
         size_t o = L.add(bytes);
@@ -171,6 +174,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->vmax2, 4 * (size_t)kMaxBlock * DB_VMAX_SPREAD);
     put(c->red, 8 * 6 * ((n + DB_BLOCK - 1) / DB_BLOCK + 1));
     put(c->dp, sizeof(Params));
+    put(c->rep_d, sizeof(Box) * (size_t)std::max(1, c->nrep));
     int* t1 = nullptr;
     put(t1, 4 * (n + 1));
     if (assign) ext(c).tmp_n1 = t1;
@@ -198,7 +202,7 @@ static int ensure_memory(db_ctx* c) {
         ext(c).pin_dev = (Pinned*)dptr;
     }
     // zero the counters that kernels assume start at zero
-    launch_fill_int(c->cells.cnt, 0, (size_t)ncell_cap(c->n), c->stream);
+    launch_fill_int(c->cells.cnt, 0, (size_t)ncell_cap(c), c->stream);
     launch_fill_int(c->err_d, 0, 16, c->stream);
     c->allocated = true;
     HIPCHK(c, hipGetLastError());
@@ -208,30 +212,47 @@ static int ensure_memory(db_ctx* c) {
 // ------------------------------------------------------------------------------------
 // parameters and the cell grid
 
+// cells of edge >= amin, at most ncap of them
+static void box_grid(Box& X, double amin, int ncap) {
+    if (!(amin > 0)) amin = X.L;
+    int nc = (int)std::floor(X.L / (amin * (1.0 + 1e-9)));
+    if (nc < 1) nc = 1;
+    while ((long long)nc * nc * nc > ncap && nc > 1) --nc;
+    X.nc = nc;
+    X.cell_scale = nc / X.L;
+    if (nc >= 3) {
+        X.noff = 3;
+        X.off[0] = -1; X.off[1] = 0; X.off[2] = 1;
+    } else if (nc == 2) {
+        X.noff = 2;
+        X.off[0] = 0; X.off[1] = 1; X.off[2] = 0;
+    } else {
+        X.noff = 1;
+        X.off[0] = 0; X.off[1] = 0; X.off[2] = 0;
+    }
+}
+
 static void compute_grid(db_ctx* c) {
     Params& P = c->hp;
     double rc = P.have_pair ? std::sqrt(P.rc2) : 0.0;
     double rcr = std::sqrt(std::max(P.rmax2_create, 0.0));
     double rnl = P.have_pair ? rc + c->skin : 0.0;
     P.rnl2 = rnl * rnl;
-    double amin = std::max(rnl, rcr);
-    if (!(amin > 0)) amin = c->L;
-    int nc = (int)std::floor(c->L / (amin * (1.0 + 1e-9)));
-    if (nc < 1) nc = 1;
-    while ((long long)nc * nc * nc > ncell_cap(c->n) && nc > 1) --nc;
-    P.nc = nc;
-    P.ncell = nc * nc * nc;
-    P.cell_scale = nc / c->L;
-    if (nc >= 3) {
-        P.noff = 3;
-        P.off[0] = -1; P.off[1] = 0; P.off[2] = 1;
-    } else if (nc == 2) {
-        P.noff = 2;
-        P.off[0] = 0; P.off[1] = 1; P.off[2] = 0;
-    } else {
-        P.noff = 1;
-        P.off[0] = 0; P.off[1] = 0; P.off[2] = 0;
+    const double amin = std::max(rnl, rcr);
+    if (c->nrep == 0) {
+        box_grid(P.box, amin, ncell_cap(c));
+        P.box.cell_off = 0;
+        P.ncell = P.box.nc * P.box.nc * P.box.nc;
+        return;
     }
+    int off = 0;
+    for (int r = 0; r < c->nrep; ++r) {
+        Box& X = c->reps[r];
+        box_grid(X, amin, 2 * c->rep_n[r] + 64);
+        X.cell_off = off;
+        off += X.nc * X.nc * X.nc;
+    }
+    P.ncell = off;
 }
 
 // Largest displacement any bead may make between neighbour-list builds: a pair
@@ -246,6 +267,11 @@ static int upload_params(db_ctx* c) {
     if (!c->params_dirty) return DB_OK;
     compute_grid(c);
     c->hp.n = c->n;
+    c->hp.nrep = c->nrep;
+    c->hp.rep = c->nrep > 0 ? c->rep_d : nullptr;
+    if (c->nrep > 0)
+        HIPCHK(c, hipMemcpyAsync(c->rep_d, c->reps.data(), sizeof(Box) * c->reps.size(), hipMemcpyHostToDevice,
+                                 c->stream));
     HIPCHK(c, hipMemcpyAsync(c->dp, &c->hp, sizeof(Params), hipMemcpyHostToDevice, c->stream));
     c->params_dirty = false;
     return DB_OK;
@@ -266,7 +292,7 @@ static int upload_system(db_ctx* c) {
         x4[i].x = h.x[3 * i];
         x4[i].y = h.x[3 * i + 1];
         x4[i].z = h.x[3 * i + 2];
-        x4[i].w = pack_meta(i, h.type[i], h.reactive[i]);
+        x4[i].w = pack_meta(i, h.type[i], h.reactive[i], h.rep.empty() ? 0 : (int)h.rep[i]);
         v[i] = h.v[3 * i];
         v[n + i] = h.v[3 * i + 1];
         v[2 * (size_t)n + i] = h.v[3 * i + 2];
@@ -541,12 +567,12 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     memset(&c->hp, 0, sizeof(Params));
     Params& P = c->hp;
     P.n = n;
-    P.L = L;
-    P.hL = 0.5 * L;
-    P.invL = 1.0 / L;
-    P.seed_lo = (uint32_t)seed;
-    P.seed_hi = (uint32_t)(seed >> 32);
-    P.T0 = P.T1 = 1.0;
+    P.box.L = L;
+    P.box.hL = 0.5 * L;
+    P.box.invL = 1.0 / L;
+    P.box.seed_lo = (uint32_t)seed;
+    P.box.seed_hi = (uint32_t)(seed >> 32);
+    P.box.T0 = P.box.T1 = 1.0;
     P.dt = 0.005;
     P.excl_depth = 1;
     c->params_dirty = true;
@@ -598,6 +624,7 @@ const char* db_last_error(const db_ctx* c) { return c ? c->err.c_str() : "null h
 
 int db_set_state(db_ctx* c, const double* x, const double* v, const int32_t* type, int on_device) {
     if (!c || !x || !type) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_ESTATE, "a batch takes its state and topology from its replicas");
     int rc = editable(c);
     if (rc) return rc;
     HostSys& h = ext(c).h;
@@ -632,6 +659,7 @@ int db_set_state(db_ctx* c, const double* x, const double* v, const int32_t* typ
 
 int db_set_reactive(db_ctx* c, const uint8_t* flag) {
     if (!c || !flag) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_ESTATE, "a batch takes its state and topology from its replicas");
     int rc = editable(c);
     if (rc) return rc;
     HostSys& h = ext(c).h;
@@ -641,6 +669,7 @@ int db_set_reactive(db_ctx* c, const uint8_t* flag) {
 
 int db_set_bonds(db_ctx* c, int64_t nb, const int32_t* ij, const int32_t* tij, const int32_t* tji) {
     if (!c || nb < 0 || (nb > 0 && (!ij || !tij || !tji))) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_ESTATE, "a batch takes its state and topology from its replicas");
     int rc = editable(c);
     if (rc) return rc;
     std::vector<int> deg(c->n, 0);
@@ -672,6 +701,7 @@ int db_set_bonds(db_ctx* c, int64_t nb, const int32_t* ij, const int32_t* tij, c
 
 int db_set_angles(db_ctx* c, int64_t na, const int32_t* abc, const int32_t* type) {
     if (!c || na < 0 || (na > 0 && (!abc || !type))) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_ESTATE, "a batch takes its state and topology from its replicas");
     int rc = editable(c);
     if (rc) return rc;
     std::vector<int32_t> a(4 * (size_t)na);
@@ -692,6 +722,7 @@ int db_set_angles(db_ctx* c, int64_t na, const int32_t* abc, const int32_t* type
 
 int db_set_dihedrals(db_ctx* c, int64_t nd, const int32_t* abcd, const int32_t* type) {
     if (!c || nd < 0 || (nd > 0 && (!abcd || !type))) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_ESTATE, "a batch takes its state and topology from its replicas");
     int rc = editable(c);
     if (rc) return rc;
     std::vector<int32_t> d(5 * (size_t)nd);
@@ -764,21 +795,30 @@ int db_dihedral_cosine(db_ctx* c, int32_t t, double K, double p0) {
     return DB_OK;
 }
 
+// the temperature schedule of a single system, or of every replica of a batch
+static void set_schedule(db_ctx* c, double T0, double T1, int64_t n) {
+    c->hp.box.T0 = T0;
+    c->hp.box.T1 = T1;
+    c->hp.box.ramp = n;
+    for (Box& X : c->reps) {
+        X.T0 = T0;
+        X.T1 = T1;
+        X.ramp = n;
+    }
+}
+
 int db_langevin(db_ctx* c, double T, double gamma, double dt) {
     if (!c || !(dt > 0) || gamma < 0 || T < 0) return DB_EINVAL;
-    c->hp.T0 = c->hp.T1 = T;
+    set_schedule(c, T, T, 0);
     c->hp.gamma = gamma;
     c->hp.dt = dt;
-    c->hp.ramp = 0;
     c->params_dirty = true;
     return DB_OK;
 }
 
 int db_temperature_ramp(db_ctx* c, double T0, double T1, int64_t n) {
     if (!c || n < 0 || T0 < 0 || T1 < 0) return DB_EINVAL;
-    c->hp.T0 = T0;
-    c->hp.T1 = T1;
-    c->hp.ramp = n;
+    set_schedule(c, T0, T1, n);
     c->params_dirty = true;
     return DB_OK;
 }
@@ -1148,6 +1188,173 @@ int db_tune(db_ctx* c, double skin, int32_t permute_every) {
     c->skin = skin;
     c->permute_every = permute_every;
     c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* best_permute) {
+    if (!c || steps_per_trial < 1) return DB_EINVAL;
+    const double skins[4] = {0.4, 0.5, 0.6, 0.8};
+    const int perms[4] = {1, 2, 4, 8};
+    double best_t = INFINITY, bs = c->skin;
+    int bp = c->permute_every;
+    for (double sk : skins) {
+        for (int pe : perms) {
+            int rc = db_tune(c, sk, pe);
+            if (rc) return rc;
+            rc = db_step(c, 1);   // the new grid is set up outside the timed steps
+            if (rc) return rc;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            auto t0 = std::chrono::steady_clock::now();
+            rc = db_step(c, steps_per_trial);
+            if (rc) return rc;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (t < best_t) {
+                best_t = t;
+                bs = sk;
+                bp = pe;
+            }
+        }
+    }
+    int rc = db_tune(c, bs, bp);
+    if (rc) return rc;
+    if (best_skin) *best_skin = bs;
+    if (best_permute) *best_permute = bp;
+    return DB_OK;
+}
+
+// the force field, thermostat and rules two handles would run with
+static bool same_physics(const Params& a, const Params& b) {
+    auto eq = [](const void* x, const void* y, size_t n) { return memcmp(x, y, n) == 0; };
+    if (a.have_pair != b.have_pair || a.excl_depth != b.excl_depth || a.eps != b.eps || a.sig2 != b.sig2 ||
+        a.rc2 != b.rc2)
+        return false;
+    if (!eq(a.bK, b.bK, sizeof a.bK) || !eq(a.bR0, b.bR0, sizeof a.bR0) || !eq(a.aK, b.aK, sizeof a.aK) ||
+        !eq(a.aT0, b.aT0, sizeof a.aT0) || !eq(a.dK, b.dK, sizeof a.dK) || !eq(a.dC0, b.dC0, sizeof a.dC0) ||
+        !eq(a.dS0, b.dS0, sizeof a.dS0))
+        return false;
+    if (a.gamma != b.gamma || a.dt != b.dt || a.every != b.every || a.pc13 != b.pc13 || a.pc14 != b.pc14)
+        return false;
+    if (a.nrule != b.nrule || a.nmax != b.nmax || a.narule != b.narule || a.ndrule != b.ndrule) return false;
+    for (int q = 0; q < a.nrule; ++q) {
+        const Rule &x = a.rule[q], &y = b.rule[q];
+        if (x.kind != y.kind || x.bt1 != y.bt1 || x.bt2 != y.bt2 || x.b1 != y.b1 || x.b2 != y.b2 || x.r2 != y.r2 ||
+            x.p != y.p)
+            return false;
+    }
+    for (int q = 0; q < a.nmax; ++q)
+        if (a.maxr[q].bt != b.maxr[q].bt || a.maxr[q].bead != b.maxr[q].bead || a.maxr[q].max != b.maxr[q].max)
+            return false;
+    for (int q = 0; q < a.narule; ++q)
+        if (a.arule[q].type != b.arule[q].type || !eq(a.arule[q].b, b.arule[q].b, sizeof a.arule[q].b) ||
+            !eq(a.arule[q].m, b.arule[q].m, sizeof a.arule[q].m))
+            return false;
+    for (int q = 0; q < a.ndrule; ++q)
+        if (a.drule[q].type != b.drule[q].type || !eq(a.drule[q].b, b.drule[q].b, sizeof a.drule[q].b) ||
+            !eq(a.drule[q].m, b.drule[q].m, sizeof a.drule[q].m))
+            return false;
+    return true;
+}
+
+int db_batch_create(db_ctx** out, db_ctx* const* reps, int32_t nrep, void* stream) {
+    if (!out) return DB_EINVAL;
+    *out = nullptr;
+    if (!reps || nrep < 1 || nrep > 65535) return DB_EINVAL;
+    int64_t ntot = 0;
+    double Lmin = INFINITY, Lmax = 0;
+    for (int r = 0; r < nrep; ++r) {
+        db_ctx* q = reps[r];
+        if (!q || !q->have_state || q->nrep > 0) return DB_EINVAL;
+        if (q->precision != reps[0]->precision || q->step != reps[0]->step) return DB_EINVAL;
+        if (!same_physics(q->hp, reps[0]->hp)) return DB_EINVAL;
+        db_host_ext& X = ext(q);
+        if (X.dev_error) return DB_ESTATE;
+        if (X.dev_valid && !X.host_valid) {
+            int rc = download_system(q);
+            if (rc) return rc;
+        }
+        ntot += q->n;
+        Lmin = std::min(Lmin, q->L);
+        Lmax = std::max(Lmax, q->L);
+    }
+    if (ntot > INT32_MAX) return DB_EINVAL;
+    db_ctx* c = nullptr;
+    int rc = db_create(&c, (int32_t)ntot, Lmax, reps[0]->seed, reps[0]->precision, stream);
+    if (rc) return rc;
+    const db_ctx* r0 = reps[0];
+    c->hp = r0->hp;   // force field, thermostat, rules
+    c->hp.n = (int)ntot;
+    c->L = Lmin;      // the argument checks of later calls hold for every box
+    c->nrep = nrep;
+    c->reps.resize(nrep);
+    c->rep_n.resize(nrep);
+    c->step = r0->step;
+    c->swept_step = r0->swept_step;
+    HostSys& h = ext(c).h;
+    h.x.clear();
+    h.v.clear();
+    h.type.clear();
+    h.reactive.clear();
+    h.rep.clear();
+    int off = 0;
+    for (int r = 0; r < nrep; ++r) {
+        const db_ctx* q = reps[r];
+        const HostSys& g = ext(const_cast<db_ctx*>(q)).h;
+        Box X = q->hp.box;
+        X.gid_off = off;
+        c->reps[r] = X;
+        c->rep_n[r] = q->n;
+        h.x.insert(h.x.end(), g.x.begin(), g.x.end());
+        h.v.insert(h.v.end(), g.v.begin(), g.v.end());
+        h.type.insert(h.type.end(), g.type.begin(), g.type.end());
+        h.reactive.insert(h.reactive.end(), g.reactive.begin(), g.reactive.end());
+        h.rep.insert(h.rep.end(), (size_t)q->n, (uint16_t)r);
+        for (size_t k = 0; k < g.bonds.size(); k += 4) {
+            h.bonds.push_back(g.bonds[k] + off);
+            h.bonds.push_back(g.bonds[k + 1] + off);
+            h.bonds.push_back(g.bonds[k + 2]);
+            h.bonds.push_back(g.bonds[k + 3]);
+        }
+        for (size_t k = 0; k < g.ang.size(); k += 4) {
+            h.ang.push_back(g.ang[k]);
+            for (int m = 1; m < 4; ++m) h.ang.push_back(g.ang[k + m] + off);
+        }
+        for (size_t k = 0; k < g.dih.size(); k += 5) {
+            h.dih.push_back(g.dih[k]);
+            for (int m = 1; m < 5; ++m) h.dih.push_back(g.dih[k + m] + off);
+        }
+        off += q->n;
+    }
+    c->have_state = true;
+    c->params_dirty = true;
+    *out = c;
+    return DB_OK;
+}
+
+int db_batch_get_state(db_ctx* c, int32_t r, double* x, double* v, int on_device) {
+    if (!c || c->nrep == 0 || r < 0 || r >= c->nrep) return DB_EINVAL;
+    const size_t n = (size_t)c->n;
+    const size_t off = (size_t)c->reps[r].gid_off, nr = (size_t)c->rep_n[r];
+    db_host_ext& X = ext(c);
+    if (!X.dev_valid || X.host_valid) {
+        if (on_device) {
+            if (x && nr) HIPCHK(c, hipMemcpy(x, X.h.x.data() + 3 * off, 24 * nr, hipMemcpyHostToDevice));
+            if (v && nr) HIPCHK(c, hipMemcpy(v, X.h.v.data() + 3 * off, 24 * nr, hipMemcpyHostToDevice));
+        } else {
+            if (x) std::copy(X.h.x.begin() + 3 * off, X.h.x.begin() + 3 * (off + nr), x);
+            if (v) std::copy(X.h.v.begin() + 3 * off, X.h.v.begin() + 3 * (off + nr), v);
+        }
+        return DB_OK;
+    }
+    if (nr == 0) return DB_OK;
+    double* d = (double*)scratch(c, 48 * n);
+    hipLaunchKernelGGL(k_gather_state, dim3((unsigned)((n + DB_BLOCK - 1) / DB_BLOCK)), dim3(DB_BLOCK), 0, c->stream,
+                       (int)n, c->bank[c->cur], d, d + 3 * n);
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (x) HIPCHK(c, hipMemcpyAsync(x, d + 3 * off, 24 * nr, kind, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(v, d + 3 * n + 3 * off, 24 * nr, kind, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
     return DB_OK;
 }
 

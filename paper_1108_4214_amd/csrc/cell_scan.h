@@ -42,16 +42,17 @@ __device__ __forceinline__ void scan_run(const float4* __restrict__ xs, int s0, 
 }
 
 template <class F>
-__device__ __forceinline__ void scan_cells(const Params& P, const int* __restrict__ cstart,
+__device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__ cstart,
                                            const float4* __restrict__ xs, int i, const double4& xi, float cut2,
                                            F&& f) {
-    const int nc = P.nc;
-    const int cx = cell_coord(xi.x, P.cell_scale, nc);
-    const int cy = cell_coord(xi.y, P.cell_scale, nc);
-    const int cz = cell_coord(xi.z, P.cell_scale, nc);
-    const float Lf = (float)P.L, hLf = (float)P.hL;
+    const int nc = X.nc;
+    const int cx = cell_coord(xi.x, X.cell_scale, nc);
+    const int cy = cell_coord(xi.y, X.cell_scale, nc);
+    const int cz = cell_coord(xi.z, X.cell_scale, nc);
+    const float Lf = (float)X.L, hLf = (float)X.hL;
     const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
-    if (P.noff == 3) {
+    cstart += X.cell_off;
+    if (X.noff == 3) {
         // nine x-rows of three cells; a row that wraps in x splits into two runs
         // (the wrapped cell seen through its image, and the two contiguous ones),
         // so each row is visited as two runs, the second empty unless it wraps
@@ -80,12 +81,12 @@ __device__ __forceinline__ void scan_cells(const Params& P, const int* __restric
         }
         return;
     }
-    for (int oz = 0; oz < P.noff; ++oz) {
-        const int zz = wrap_cell(cz + P.off[oz], nc);
-        for (int oy = 0; oy < P.noff; ++oy) {
-            const int row = (zz * nc + wrap_cell(cy + P.off[oy], nc)) * nc;
-            for (int ox = 0; ox < P.noff; ++ox) {
-                const int c = row + wrap_cell(cx + P.off[ox], nc);
+    for (int oz = 0; oz < X.noff; ++oz) {
+        const int zz = wrap_cell(cz + X.off[oz], nc);
+        for (int oy = 0; oy < X.noff; ++oy) {
+            const int row = (zz * nc + wrap_cell(cy + X.off[oy], nc)) * nc;
+            for (int ox = 0; ox < X.noff; ++ox) {
+                const int c = row + wrap_cell(cx + X.off[ox], nc);
                 const int s0 = cstart[c], s1 = cstart[c + 1];
                 for (int p = s0; p < s1; ++p) {
                     const float4 e = xs[p];

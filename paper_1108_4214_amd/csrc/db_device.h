@@ -27,16 +27,20 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 }
 
 // counter layout: (a, b, step low word, step high bits | stream tag << 28)
-__device__ __forceinline__ uint4 rng_draw(const Params& P, uint32_t a, uint32_t b, int64_t step, uint32_t kind) {
+// a and b are bead ids within the box; the key is the box's seed
+__device__ __forceinline__ uint4 rng_draw(const Box& X, uint32_t a, uint32_t b, int64_t step, uint32_t kind) {
     uint64_t st = (uint64_t)step;
     uint4 c = make_uint4(a, b, (uint32_t)st, ((uint32_t)(st >> 32) & 0x0FFFFFFFu) | (kind << 28));
-    return philox4x32_10(c, P.seed_lo, P.seed_hi);
+    return philox4x32_10(c, X.seed_lo, X.seed_hi);
 }
 
 // uniform in [0,1) with 53 random bits, drawn for the unordered pair {ga, gb}
-__device__ __forceinline__ double pair_uniform(const Params& P, int ga, int gb, int64_t step, uint32_t kind) {
+// of global ids, both in box X
+__device__ __forceinline__ double pair_uniform(const Box& X, int ga, int gb, int64_t step, uint32_t kind) {
+    ga -= X.gid_off;
+    gb -= X.gid_off;
     uint32_t lo = (uint32_t)(ga < gb ? ga : gb), hi = (uint32_t)(ga < gb ? gb : ga);
-    uint4 w = rng_draw(P, lo, hi, step, kind);
+    uint4 w = rng_draw(X, lo, hi, step, kind);
     uint64_t bits = ((((uint64_t)w.x) << 32) | (uint64_t)w.y) >> 11;
     return (double)bits * (1.0 / 9007199254740992.0);
 }
@@ -52,11 +56,11 @@ __device__ __forceinline__ double min_image(double d, double L, double hL) {
 
 // x_j - x_i with the minimum-image convention, and its squared length summed
 // as (dx^2 + dy^2) + dz^2 (the order the cutoff decisions are defined in)
-__device__ __forceinline__ double separation(const Params& P, const double4& xi, const double4& xj, double& dx,
+__device__ __forceinline__ double separation(const Box& X, const double4& xi, const double4& xj, double& dx,
                                              double& dy, double& dz) {
-    dx = min_image(xj.x - xi.x, P.L, P.hL);
-    dy = min_image(xj.y - xi.y, P.L, P.hL);
-    dz = min_image(xj.z - xi.z, P.L, P.hL);
+    dx = min_image(xj.x - xi.x, X.L, X.hL);
+    dy = min_image(xj.y - xi.y, X.L, X.hL);
+    dz = min_image(xj.z - xi.z, X.L, X.hL);
     return (dx * dx + dy * dy) + dz * dz;
 }
 
@@ -68,13 +72,30 @@ __device__ __forceinline__ int meta_word(const double4& x) {
 }
 __device__ __forceinline__ int meta_type(int m) { return m & 0xFF; }
 __device__ __forceinline__ int meta_reactive(int m) { return (m >> 8) & 1; }
+__device__ __forceinline__ int meta_rep(int m) { return (int)((uint32_t)m >> 16); }
 
-__host__ __device__ inline double pack_meta(int gid, int type, int reactive) {
+// low word: global bead id; high word: type | reactive << 8 | replica << 16
+__host__ __device__ inline double pack_meta(int gid, int type, int reactive, int rep = 0) {
     unsigned long long bits = (unsigned long long)(uint32_t)gid |
-                              ((unsigned long long)(uint32_t)(type | (reactive << 8)) << 32);
+                              ((unsigned long long)(uint32_t)(type | (reactive << 8) | (rep << 16)) << 32);
     double d;
     __builtin_memcpy(&d, &bits, sizeof(d));
     return d;
+}
+
+// The box of a bead: the system's own, or in a batch the replica's (BATCH is a
+// template flag of the kernels, so the single-system path reads uniform values).
+template <bool BATCH>
+__device__ __forceinline__ const Box& box_of(const Params& P, int meta) {
+    if (BATCH) return P.rep[meta_rep(meta)];
+    return P.box;
+}
+
+// temperature of box X at a step: T0 + (T1 - T0) min(step, ramp) / ramp
+__device__ __forceinline__ double box_temperature(const Box& X, int64_t step) {
+    if (X.ramp <= 0) return X.T0;
+    int64_t k = step < X.ramp ? step : X.ramp;
+    return X.T0 + (X.T1 - X.T0) * (double)k / (double)X.ramp;
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs.  Map them so that each XCD

@@ -38,14 +38,29 @@ struct MaxRule { int bt, bead, max; };
 struct AngRule { int type; int b[3]; uint32_t m[2]; };
 struct DihRule { int type; int b[4]; uint32_t m[3]; };
 
-// Read-only parameters of one box, resident in device memory.
+// One periodic box: its edge, cell grid and where its cells and bead ids start
+// in the shared arrays, its random-number key and temperature schedule.  A
+// single system has one box (Params::box); a batch of independent replicas has
+// one per replica (Params::rep, indexed by the replica id in each bead's meta).
+struct Box {
+    double L, hL, invL;
+    double cell_scale;   // nc / L
+    int nc, noff;        // nc^3 cells of edge L/nc; neighbour offsets per dimension
+    int off[3];
+    int cell_off;        // first cell of the box in the shared cell arrays
+    int gid_off;         // first global bead id of the box
+    uint32_t seed_lo, seed_hi;
+    double T0, T1;       // temperature T0 + (T1 - T0) min(step, ramp) / ramp
+    int64_t ramp;
+};
+
+// Read-only parameters, resident in device memory.
 struct Params {
     int n;
-    double L, hL, invL;
-    // cell grid: nc^3 cells of edge L/nc; neighbour offsets per dimension
-    int nc, ncell, noff;
-    int off[3];
-    double cell_scale;   // nc / L
+    int ncell;           // cells over all boxes
+    Box box;             // the box of a single system
+    int nrep;            // replicas in a batch (0: single system)
+    const Box* rep;      // [nrep] device table of a batch
     // WCA
     int have_pair, excl_depth;
     double eps, sig2, rc2;
@@ -55,9 +70,7 @@ struct Params {
     double aK[DB_MAXT], aT0[DB_MAXT], aPiMinusT0[DB_MAXT];
     double dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
     // thermostat / integration
-    double gamma, dt, T0, T1;
-    int64_t ramp;
-    uint32_t seed_lo, seed_hi;
+    double gamma, dt;
     // rules, in call order
     int every, pc13, pc14;
     int nrule, nmax, narule, ndrule;
@@ -158,6 +171,11 @@ struct db_ctx {
     db::Cells cells;
     db::NList nlist;
     db::Halo halo;
+    // a batch of independent replicas (nrep > 0): one box per replica
+    int nrep;
+    std::vector<db::Box> reps;   // host copy; cell_off and gid_off fixed at creation
+    std::vector<int> rep_n;      // beads per replica
+    db::Box* rep_d;              // device copy (Params::rep)
     double nl_skin;      // neighbour-list cutoff minus pair cutoff
     int* slot_of_gid;    // [n]
     int* err_d;          // device error word

@@ -19,16 +19,18 @@ void launch_fill_int(int* p, int value, size_t count, hipStream_t s) {
 }
 
 // ---- binning -----------------------------------------------------------------
+template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_bin(const Params* __restrict__ Pp, const double4* __restrict__ x,
                                                    int* __restrict__ cellid, int* __restrict__ cnt) {
     const Params& P = *Pp;
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i >= P.n) return;
     double4 xi = x[i];
-    int cx = cell_coord(xi.x, P.cell_scale, P.nc);
-    int cy = cell_coord(xi.y, P.cell_scale, P.nc);
-    int cz = cell_coord(xi.z, P.cell_scale, P.nc);
-    int c = (cz * P.nc + cy) * P.nc + cx;
+    const Box& X = box_of<BATCH>(P, meta_word(xi));
+    int cx = cell_coord(xi.x, X.cell_scale, X.nc);
+    int cy = cell_coord(xi.y, X.cell_scale, X.nc);
+    int cz = cell_coord(xi.z, X.cell_scale, X.nc);
+    int c = X.cell_off + (cz * X.nc + cy) * X.nc + cx;
     cellid[i] = c;
     atomicAdd(&cnt[c], 1);
 }
@@ -162,7 +164,12 @@ void launch_build_cells(db_ctx* c) {
     hipStream_t s = c->stream;
     db::Bank& B = c->bank[c->cur];
     unsigned nb = (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK);
-    if (n > 0) hipLaunchKernelGGL(k_bin, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid, c->cells.cnt);
+    if (n > 0) {
+        if (c->nrep > 0)
+            hipLaunchKernelGGL(k_bin<true>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid, c->cells.cnt);
+        else
+            hipLaunchKernelGGL(k_bin<false>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid, c->cells.cnt);
+    }
     // start = exclusive scan of cnt; start[ncell] = n
     scan_into(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, c->cells.start + ncell, n, (size_t)1);

@@ -54,8 +54,8 @@ __device__ __forceinline__ void load_coef(const Params& P, Coef<R>& C) {
 // exact, so the result equals d - L, d or d + L rounded once, as in the
 // comparison form; the two forms can pick different images only for d within a
 // rounding error of L/2, where both images are equally near.
-__device__ __forceinline__ double near_image(double d, const Params& P) {
-    return fma(-rint(d * P.invL), P.L, d);
+__device__ __forceinline__ double near_image(double d, const Box& X) {
+    return fma(-rint(d * X.invL), X.L, d);
 }
 
 template <typename R>
@@ -104,11 +104,11 @@ __device__ bool two_bonds_apart(const Bank& B, int n, int j, int nb, int p0, int
 }
 
 template <typename R, int MODE>
-__device__ __forceinline__ void pair_term(const Params& P, const double4& xi, const double4& xj, Acc<R>& a) {
+__device__ __forceinline__ void pair_term(const Params& P, const Box& X, const double4& xi, const double4& xj, Acc<R>& a) {
     double dx, dy, dz;
-    dx = near_image(xj.x - xi.x, P);
-    dy = near_image(xj.y - xi.y, P);
-    dz = near_image(xj.z - xi.z, P);
+    dx = near_image(xj.x - xi.x, X);
+    dy = near_image(xj.y - xi.y, X);
+    dz = near_image(xj.z - xi.z, X);
     R rx = (R)dx, ry = (R)dy, rz = (R)dz;
     R r2 = (rx * rx + ry * ry) + rz * rz;
     R ir2 = r_rcp<R>(r2);
@@ -125,29 +125,30 @@ __device__ __forceinline__ void pair_term(const Params& P, const double4& xi, co
 }
 
 template <typename R, int MODE>
-__device__ void pair_forces(const Params& P, const Bank& B, const int* __restrict__ cstart,
+__device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const int* __restrict__ cstart,
                             const int* __restrict__ clist, int i, const double4& xi, int nb, int p0, int p1, int p2,
                             int p3, Acc<R>& a) {
-    const int nc = P.nc;
-    int cx = cell_coord(xi.x, P.cell_scale, nc);
-    int cy = cell_coord(xi.y, P.cell_scale, nc);
-    int cz = cell_coord(xi.z, P.cell_scale, nc);
+    const int nc = X.nc;
+    int cx = cell_coord(xi.x, X.cell_scale, nc);
+    int cy = cell_coord(xi.y, X.cell_scale, nc);
+    int cz = cell_coord(xi.z, X.cell_scale, nc);
     const R rc2 = (R)P.rc2;
-    const bool rowmerge = (P.noff == 3) && cx >= 1 && cx <= nc - 2;
-    for (int oz = 0; oz < P.noff; ++oz) {
-        int zz = wrap_cell(cz + P.off[oz], nc);
-        for (int oy = 0; oy < P.noff; ++oy) {
-            int yy = wrap_cell(cy + P.off[oy], nc);
+    const bool rowmerge = (X.noff == 3) && cx >= 1 && cx <= nc - 2;
+    cstart += X.cell_off;
+    for (int oz = 0; oz < X.noff; ++oz) {
+        int zz = wrap_cell(cz + X.off[oz], nc);
+        for (int oy = 0; oy < X.noff; ++oy) {
+            int yy = wrap_cell(cy + X.off[oy], nc);
             int row = (zz * nc + yy) * nc;
             // the three cells of one x-row are contiguous in the list unless the row wraps
-            int nseg = rowmerge ? 1 : P.noff;
+            int nseg = rowmerge ? 1 : X.noff;
             for (int ox = 0; ox < nseg; ++ox) {
                 int s0, s1;
                 if (rowmerge) {
                     s0 = cstart[row + cx - 1];
                     s1 = cstart[row + cx + 2];
                 } else {
-                    int c = row + wrap_cell(cx + P.off[ox], nc);
+                    int c = row + wrap_cell(cx + X.off[ox], nc);
                     s0 = cstart[c];
                     s1 = cstart[c + 1];
                 }
@@ -155,15 +156,15 @@ __device__ void pair_forces(const Params& P, const Bank& B, const int* __restric
                     int j = clist[p];
                     if (j == i) continue;
                     double4 xj = B.x[j];
-                    double dx = near_image(xj.x - xi.x, P);
-                    double dy = near_image(xj.y - xi.y, P);
-                    double dz = near_image(xj.z - xi.z, P);
+                    double dx = near_image(xj.x - xi.x, X);
+                    double dy = near_image(xj.y - xi.y, X);
+                    double dz = near_image(xj.z - xi.z, X);
                     R rx = (R)dx, ry = (R)dy, rz = (R)dz;
                     R r2 = (rx * rx + ry * ry) + rz * rz;
                     if (!(r2 < rc2)) continue;
                     if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) continue;
                     if (P.excl_depth >= 2 && two_bonds_apart(B, P.n, j, nb, p0, p1, p2, p3)) continue;
-                    pair_term<R, MODE>(P, xi, xj, a);
+                    pair_term<R, MODE>(P, X, xi, xj, a);
                 }
             }
         }
@@ -174,6 +175,7 @@ __device__ void pair_forces(const Params& P, const Bank& B, const int* __restric
 // skin) that is not excluded, from the 27 cells of the current cell list.  The
 // float prefilter carries a 1e-4 relative margin, so the list is a superset of
 // the pairs within the cutoff in double.
+template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restrict__ Pp, Bank B,
                                                           const int* __restrict__ cstart,
                                                           const float4* __restrict__ xs, NList NL,
@@ -188,8 +190,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     const int p1 = nb > 1 ? B.bp[n + i] : -1;
     const int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
     const int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
+    const Box& X = box_of<BATCH>(P, meta_word(xi));
     int cnt = 0;
-    scan_cells(P, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, float) {
+    scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, float) {
         if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
         if (P.excl_depth >= 2 && two_bonds_apart(B, n, j, nb, p0, p1, p2, p3)) return;
         if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
@@ -206,10 +209,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
 // Entries are taken four at a time: the four indices, then the four positions are
 // requested before any of them is used, so one bead keeps several loads in flight.
 template <typename R>
-__device__ __forceinline__ void pair_one(const Params& P, const double4& xi, const double4& xj, R rc2, Acc<R>& a) {
-    R rx = (R)near_image(xj.x - xi.x, P);
-    R ry = (R)near_image(xj.y - xi.y, P);
-    R rz = (R)near_image(xj.z - xi.z, P);
+__device__ __forceinline__ void pair_one(const Params& P, const Box& X, const double4& xi, const double4& xj, R rc2, Acc<R>& a) {
+    R rx = (R)near_image(xj.x - xi.x, X);
+    R ry = (R)near_image(xj.y - xi.y, X);
+    R rz = (R)near_image(xj.z - xi.z, X);
     R r2 = (rx * rx + ry * ry) + rz * rz;
     if (r2 < rc2) {
         R ir2 = r_rcp<R>(r2);
@@ -223,7 +226,7 @@ __device__ __forceinline__ void pair_one(const Params& P, const double4& xi, con
 }
 
 template <typename R>
-__device__ __forceinline__ void list_pair_forces(const Params& P, const Bank& B, const NList& NL, int i,
+__device__ __forceinline__ void list_pair_forces(const Params& P, const Box& X, const Bank& B, const NList& NL, int i,
                                                  const double4& xi, Acc<R>& a) {
     const int n = P.n;
     const R rc2 = (R)P.rc2;
@@ -237,13 +240,13 @@ __device__ __forceinline__ void list_pair_forces(const Params& P, const Bank& B,
         for (int q = 0; q < 4; ++q) xj[q] = B.x[j[q]];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (k0 + q < m) pair_one<R>(P, xi, xj[q], rc2, a);
+            if (k0 + q < m) pair_one<R>(P, X, xi, xj[q], rc2, a);
     }
 }
 
 // harmonic bond U = K (r - r0)^2 with the type bead i stores (all partners requested at once)
 template <typename R, int MODE>
-__device__ __forceinline__ void bond_terms(const Params& P, const Coef<R>& C, const Bank& B, int i, const double4& xi, int nb,
+__device__ __forceinline__ void bond_terms(const Params& P, const Box& X, const Coef<R>& C, const Bank& B, int i, const double4& xi, int nb,
                                            Acc<R>& a) {
     const int n = P.n;
     int jj[DB_MAXB], tt[DB_MAXB];
@@ -260,9 +263,9 @@ __device__ __forceinline__ void bond_terms(const Params& P, const Coef<R>& C, co
         if (k >= nb) continue;
         const double4& xj = xs[k];
         const int t = tt[k];
-        double dx = near_image(xj.x - xi.x, P);
-        double dy = near_image(xj.y - xi.y, P);
-        double dz = near_image(xj.z - xi.z, P);
+        double dx = near_image(xj.x - xi.x, X);
+        double dy = near_image(xj.y - xi.y, X);
+        double dz = near_image(xj.z - xi.z, X);
         R rx = (R)dx, ry = (R)dy, rz = (R)dz;
         R rr2 = (rx * rx + ry * ry) + rz * rz;
         if (!(rr2 > (R)0)) continue;
@@ -321,21 +324,21 @@ __device__ __forceinline__ void angle_core(const Coef<R>& C, int role, int t, R 
 
 // angle entry e = (a, b, c, type) of bead i from the members' positions
 template <typename R, int MODE>
-__device__ __forceinline__ void angle_one(const Params& P, const Coef<R>& C, int i, const int4& e,
+__device__ __forceinline__ void angle_one(const Params& P, const Box& X, const Coef<R>& C, int i, const int4& e,
                                           const double4& xa, const double4& xb, const double4& xc, Acc<R>& a) {
-    R ux = (R)near_image(xa.x - xb.x, P), uy = (R)near_image(xa.y - xb.y, P), uz = (R)near_image(xa.z - xb.z, P);
-    R wx = (R)near_image(xc.x - xb.x, P), wy = (R)near_image(xc.y - xb.y, P), wz = (R)near_image(xc.z - xb.z, P);
+    R ux = (R)near_image(xa.x - xb.x, X), uy = (R)near_image(xa.y - xb.y, X), uz = (R)near_image(xa.z - xb.z, X);
+    R wx = (R)near_image(xc.x - xb.x, X), wy = (R)near_image(xc.y - xb.y, X), wz = (R)near_image(xc.z - xb.z, X);
     const int role = e.x == i ? 0 : (e.z == i ? 2 : 1);
     angle_core<R, MODE>(C, role, e.w & (DB_MAXT - 1), ux, uy, uz, wx, wy, wz, a);
 }
 
 template <typename R, int MODE>
-__device__ __forceinline__ void angle_terms(const Params& P, const Coef<R>& C, const Bank& B, int i, int na,
+__device__ __forceinline__ void angle_terms(const Params& P, const Box& X, const Coef<R>& C, const Bank& B, int i, int na,
                                             Acc<R>& a) {
     const int n = P.n;
     for (int k = 0; k < na; ++k) {
         int4 e = B.ang[k * n + i];
-        angle_one<R, MODE>(P, C, i, e, B.x[e.x], B.x[e.y], B.x[e.z], a);
+        angle_one<R, MODE>(P, X, C, i, e, B.x[e.x], B.x[e.y], B.x[e.z], a);
     }
 }
 
@@ -390,24 +393,24 @@ __device__ __forceinline__ void dihedral_core(const Coef<R>& C, int role, int t,
 }
 
 template <typename R, int MODE>
-__device__ __forceinline__ void dihedral_one(const Params& P, const Coef<R>& C, int i, const int4& e, int t,
+__device__ __forceinline__ void dihedral_one(const Params& P, const Box& X, const Coef<R>& C, int i, const int4& e, int t,
                                              const double4& xa, const double4& xb, const double4& xc,
                                              const double4& xd, Acc<R>& a) {
-    R b1x = (R)near_image(xb.x - xa.x, P), b1y = (R)near_image(xb.y - xa.y, P), b1z = (R)near_image(xb.z - xa.z, P);
-    R b2x = (R)near_image(xc.x - xb.x, P), b2y = (R)near_image(xc.y - xb.y, P), b2z = (R)near_image(xc.z - xb.z, P);
-    R b3x = (R)near_image(xd.x - xc.x, P), b3y = (R)near_image(xd.y - xc.y, P), b3z = (R)near_image(xd.z - xc.z, P);
+    R b1x = (R)near_image(xb.x - xa.x, X), b1y = (R)near_image(xb.y - xa.y, X), b1z = (R)near_image(xb.z - xa.z, X);
+    R b2x = (R)near_image(xc.x - xb.x, X), b2y = (R)near_image(xc.y - xb.y, X), b2z = (R)near_image(xc.z - xb.z, X);
+    R b3x = (R)near_image(xd.x - xc.x, X), b3y = (R)near_image(xd.y - xc.y, X), b3z = (R)near_image(xd.z - xc.z, X);
     const int role = e.x == i ? 0 : (e.w == i ? 3 : (e.y == i ? 1 : 2));
     dihedral_core<R, MODE>(C, role, t, b1x, b1y, b1z, b2x, b2y, b2z, b3x, b3y, b3z, a);
 }
 
 template <typename R, int MODE>
-__device__ __forceinline__ void dihedral_terms(const Params& P, const Coef<R>& C, const Bank& B, int i, int nd,
+__device__ __forceinline__ void dihedral_terms(const Params& P, const Box& X, const Coef<R>& C, const Bank& B, int i, int nd,
                                                Acc<R>& a) {
     const int n = P.n;
     for (int k = 0; k < nd; ++k) {
         int4 e = B.dih[k * n + i];
         int t = B.dt[k * n + i] & (DB_MAXT - 1);
-        dihedral_one<R, MODE>(P, C, i, e, t, B.x[e.x], B.x[e.y], B.x[e.z], B.x[e.w], a);
+        dihedral_one<R, MODE>(P, X, C, i, e, t, B.x[e.x], B.x[e.y], B.x[e.z], B.x[e.w], a);
     }
 }
 
@@ -480,7 +483,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp
 // separations are parked in LDS, one column per thread, so that angle and
 // dihedral entries can index them at run time without holding 24 registers.
 template <typename R>
-__device__ __forceinline__ void halo_bonded(const Params& P, const Coef<R>& C, const Bank& B, const Halo& H, int i,
+__device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const Coef<R>& C, const Bank& B, const Halo& H, int i,
                                             const double4& xi, int nu, Acc<R>& a) {
     const int n = P.n;
     const int tid = threadIdx.x;
@@ -497,9 +500,9 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Coef<R>& C, c
         for (int q = 0; q < 4; ++q) xk[q] = B.x[s[q]];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            hx[k0 + q] = (R)near_image(xk[q].x - xi.x, P);
-            hy[k0 + q] = (R)near_image(xk[q].y - xi.y, P);
-            hz[k0 + q] = (R)near_image(xk[q].z - xi.z, P);
+            hx[k0 + q] = (R)near_image(xk[q].x - xi.x, X);
+            hy[k0 + q] = (R)near_image(xk[q].y - xi.y, X);
+            hz[k0 + q] = (R)near_image(xk[q].z - xi.z, X);
             hs[0][k0 + q][tid] = hx[k0 + q];
             hs[1][k0 + q][tid] = hy[k0 + q];
             hs[2][k0 + q][tid] = hz[k0 + q];
@@ -561,13 +564,9 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-__device__ __forceinline__ double temperature(const Params& P, int64_t step) {
-    if (P.ramp <= 0) return P.T0;
-    int64_t k = step < P.ramp ? step : P.ramp;
-    return P.T0 + (P.T1 - P.T0) * (double)k / (double)P.ramp;
-}
-
-template <typename R, int MODE>
+// pref: sqrt(24 gamma T / dt) of a single system (from the host); a batch
+// forms it per bead from the replica's temperature
+template <typename R, int MODE, bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
                                                     double4* __restrict__ xout, int64_t step, double pref,
                                                     unsigned int* __restrict__ vmax2_slot,
@@ -586,16 +585,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
     double vx = 0, vy = 0, vz = 0;
     if (active) {
         xi = B.x[i];
+        const Box& X = box_of<BATCH>(P, meta_word(xi));
         const int nu = H.nu[i];
         if (nu <= DB_MAXU) {
-            halo_bonded<R>(P, C, B, H, i, xi, nu, a);
+            halo_bonded<R>(P, X, C, B, H, i, xi, nu, a);
         } else {
             // more distinct bonded partners than the halo holds: read them per entry
-            bond_terms<R, MODE_STEP>(P, C, B, i, xi, B.nb[i], a);
-            angle_terms<R, MODE_STEP>(P, C, B, i, B.na[i], a);
-            dihedral_terms<R, MODE_STEP>(P, C, B, i, B.nd[i], a);
+            bond_terms<R, MODE_STEP>(P, X, C, B, i, xi, B.nb[i], a);
+            angle_terms<R, MODE_STEP>(P, X, C, B, i, B.na[i], a);
+            dihedral_terms<R, MODE_STEP>(P, X, C, B, i, B.nd[i], a);
         }
-        if (P.have_pair) list_pair_forces<R>(P, B, NL, i, xi, a);
+        if (P.have_pair) list_pair_forces<R>(P, X, B, NL, i, xi, a);
         if (MODE == MODE_FORCES) {
             int g = meta_gid(xi);
             fout[3 * (size_t)g] = a.fx;
@@ -608,7 +608,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         vz = B.v[2 * n + i];
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
-            uint4 w = rng_draw(P, (uint32_t)meta_gid(xi), 0u, step, RNG_LANGEVIN);
+            if (BATCH) pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
+            uint4 w = rng_draw(X, (uint32_t)(meta_gid(xi) - X.gid_off), 0u, step, RNG_LANGEVIN);
             const double s32 = 1.0 / 4294967296.0;
             double ux = ((double)w.x + 0.5) * s32, uy = ((double)w.y + 0.5) * s32, uz = ((double)w.z + 0.5) * s32;
             Fx = (Fx - P.gamma * vx) + pref * (ux - 0.5);
@@ -623,11 +624,11 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
             vz = hz + hdt * Fz;
             double nxp = xi.x + P.dt * vx, nyp = xi.y + P.dt * vy, nzp = xi.z + P.dt * vz;
             double4 xo;
-            xo.x = wrap1(nxp, P.L);
-            xo.y = wrap1(nyp, P.L);
-            xo.z = wrap1(nzp, P.L);
+            xo.x = wrap1(nxp, X.L);
+            xo.y = wrap1(nyp, X.L);
+            xo.z = wrap1(nzp, X.L);
             xo.w = xi.w;
-            bool bad = !(xo.x >= 0.0 && xo.x < P.L && xo.y >= 0.0 && xo.y < P.L && xo.z >= 0.0 && xo.z < P.L);
+            bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
             if (bad) atomicOr(err, ERR_NONFINITE);
             xout[i] = xo;
             B.v[i] = vx;
@@ -652,7 +653,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
 }
 
 // energy reduction: a separate, simpler kernel keeps the step kernel lean
-template <typename R>
+template <typename R, bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ Pp, Bank B,
                                                       const int* __restrict__ cstart, const int* __restrict__ clist,
                                                       int64_t step, double* __restrict__ epart) {
@@ -666,20 +667,21 @@ __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ 
     if (i < n) {
         Acc<R> a;
         double4 xi = B.x[i];
+        const Box& X = box_of<BATCH>(P, meta_word(xi));
         int nb = B.nb[i];
         int p0 = nb > 0 ? B.bp[i] : -1;
         int p1 = nb > 1 ? B.bp[n + i] : -1;
         int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
         int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
-        if (P.have_pair) pair_forces<R, MODE_ENERGY>(P, B, cstart, clist, i, xi, nb, p0, p1, p2, p3, a);
-        bond_terms<R, MODE_ENERGY>(P, C, B, i, xi, nb, a);
-        angle_terms<R, MODE_ENERGY>(P, C, B, i, B.na[i], a);
-        dihedral_terms<R, MODE_ENERGY>(P, C, B, i, B.nd[i], a);
+        if (P.have_pair) pair_forces<R, MODE_ENERGY>(P, X, B, cstart, clist, i, xi, nb, p0, p1, p2, p3, a);
+        bond_terms<R, MODE_ENERGY>(P, X, C, B, i, xi, nb, a);
+        angle_terms<R, MODE_ENERGY>(P, X, C, B, i, B.na[i], a);
+        dihedral_terms<R, MODE_ENERGY>(P, X, C, B, i, B.nd[i], a);
         double vx = B.v[i], vy = B.v[n + i], vz = B.v[2 * n + i];
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
-            double pref = sqrt(24.0 * P.gamma * temperature(P, step) / P.dt);
-            uint4 w = rng_draw(P, (uint32_t)meta_gid(xi), 0u, step, RNG_LANGEVIN);
+            double pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
+            uint4 w = rng_draw(X, (uint32_t)(meta_gid(xi) - X.gid_off), 0u, step, RNG_LANGEVIN);
             const double s32 = 1.0 / 4294967296.0;
             double ux = ((double)w.x + 0.5) * s32, uy = ((double)w.y + 0.5) * s32, uz = ((double)w.z + 0.5) * s32;
             Fx = (Fx - P.gamma * vx) + pref * (ux - 0.5);
@@ -723,19 +725,44 @@ static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOC
 void launch_build_nlist(db_ctx* c) {
     if (c->n == 0) return;
     hipLaunchKernelGGL(k_halo, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur], c->halo);
-    hipLaunchKernelGGL(k_build_nlist, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
-                       c->cells.start, c->cells.xs, c->nlist, c->err_d);
+    if (c->nrep > 0)
+        hipLaunchKernelGGL(k_build_nlist<true>, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d);
+    else
+        hipLaunchKernelGGL(k_build_nlist<false>, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d);
 }
 
-// sqrt(24 gamma T(step) / dt), the amplitude of the uniform Langevin noise
+// sqrt(24 gamma T(step) / dt), the amplitude of the uniform Langevin noise of a single system
 static double langevin_prefactor(const Params& P, int64_t step) {
     if (P.gamma == 0.0) return 0.0;
-    double T = P.T0;
-    if (P.ramp > 0) {
-        int64_t k = step < P.ramp ? step : P.ramp;
-        T = P.T0 + (P.T1 - P.T0) * (double)k / (double)P.ramp;
+    const Box& X = P.box;
+    double T = X.T0;
+    if (X.ramp > 0) {
+        int64_t k = step < X.ramp ? step : X.ramp;
+        T = X.T0 + (X.T1 - X.T0) * (double)k / (double)X.ramp;
     }
     return sqrt(24.0 * P.gamma * T / P.dt);
+}
+
+template <typename R, int MODE, bool BATCH>
+static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, int64_t step, double pref, unsigned* vm,
+                               double* f) {
+    hipLaunchKernelGGL((k_step<R, MODE, BATCH>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
+                       c->nlist, c->halo, xout, step, pref, vm, f, c->err_d);
+}
+
+template <int MODE>
+static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, int64_t step, double pref, unsigned* vm,
+                            double* f) {
+    const bool batch = c->nrep > 0;
+    if (c->precision == DB_MIXED) {
+        if (batch) launch_step_kernel<float, MODE, true>(c, B, xout, step, pref, vm, f);
+        else launch_step_kernel<float, MODE, false>(c, B, xout, step, pref, vm, f);
+    } else {
+        if (batch) launch_step_kernel<double, MODE, true>(c, B, xout, step, pref, vm, f);
+        else launch_step_kernel<double, MODE, false>(c, B, xout, step, pref, vm, f);
+    }
 }
 
 void launch_step(db_ctx* c, int64_t step, int slot_in_block) {
@@ -743,12 +770,7 @@ void launch_step(db_ctx* c, int64_t step, int slot_in_block) {
     const double pref = langevin_prefactor(c->hp, step);
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
-    if (c->precision == DB_MIXED)
-        hipLaunchKernelGGL((k_step<float, MODE_STEP>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
-                           c->nlist, c->halo, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
-    else
-        hipLaunchKernelGGL((k_step<double, MODE_STEP>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           B, c->nlist, c->halo, c->xnext, step, pref, vm, (double*)nullptr, c->err_d);
+    launch_step_any<MODE_STEP>(c, B, c->xnext, step, pref, vm, nullptr);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;
@@ -756,26 +778,26 @@ void launch_step(db_ctx* c, int64_t step, int slot_in_block) {
 
 void launch_forces(db_ctx* c, double* f) {
     if (c->n == 0) return;
-    Bank& B = c->bank[c->cur];
-    if (c->precision == DB_MIXED)
-        hipLaunchKernelGGL((k_step<float, MODE_FORCES>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           B, c->nlist, c->halo, (double4*)nullptr, (int64_t)0, 0.0, (unsigned*)nullptr, f, c->err_d);
-    else
-        hipLaunchKernelGGL((k_step<double, MODE_FORCES>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream,
-                           c->dp, B, c->nlist, c->halo, (double4*)nullptr, (int64_t)0, 0.0,
-                           (unsigned*)nullptr, f, c->err_d);
+    launch_step_any<MODE_FORCES>(c, c->bank[c->cur], nullptr, 0, 0.0, nullptr, f);
+}
+
+template <typename R, bool BATCH>
+static void launch_energy_kernel(db_ctx* c, unsigned nb) {
+    hipLaunchKernelGGL((k_energy<R, BATCH>), dim3(nb), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
+                       c->cells.start, c->cells.list, c->step, c->red);
 }
 
 void launch_energy(db_ctx* c, double* out6) {
     unsigned nb = grid_for(c->n);
-    Bank& B = c->bank[c->cur];
     if (c->n > 0) {
-        if (c->precision == DB_MIXED)
-            hipLaunchKernelGGL((k_energy<float>), dim3(nb), dim3(DB_BLOCK), 0, c->stream, c->dp, B, c->cells.start,
-                               c->cells.list, c->step, c->red);
-        else
-            hipLaunchKernelGGL((k_energy<double>), dim3(nb), dim3(DB_BLOCK), 0, c->stream, c->dp, B, c->cells.start,
-                               c->cells.list, c->step, c->red);
+        const bool batch = c->nrep > 0;
+        if (c->precision == DB_MIXED) {
+            if (batch) launch_energy_kernel<float, true>(c, nb);
+            else launch_energy_kernel<float, false>(c, nb);
+        } else {
+            if (batch) launch_energy_kernel<double, true>(c, nb);
+            else launch_energy_kernel<double, false>(c, nb);
+        }
     }
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, c->stream, c->red, (int)(c->n > 0 ? nb : 0), out6);
 }

@@ -95,6 +95,7 @@ __device__ __forceinline__ bool create_admits(const Params& P, int ti, const Tab
     return false;
 }
 
+template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
                                                               const int* __restrict__ cstart,
                                                               const float4* __restrict__ xs, SweepBuf S) {
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
     if (i >= n) return;
     const double4 xi = B.x[i];
     const int mi = meta_word(xi);
+    const Box& X = box_of<BATCH>(P, mi);
     const int ti = meta_type(mi);
     const int gi = meta_gid(xi);
     int best = -1, best_rule = -1, best_bt = 0, best_g = 0;
@@ -113,12 +115,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
     can = can && create_admits(P, ti, Ti);
     if (can) {
         const float cut2 = (float)(P.rmax2_create * 1.0001);
-        scan_cells(P, cstart, xs, i, xi, cut2, [&](int j, float) {
+        scan_cells(X, cstart, xs, i, xi, cut2, [&](int j, float) {
             const double4 xj = B.x[j];
             const int mj = meta_word(xj);
             if (!meta_reactive(mj)) return;
             double dx, dy, dz;
-            const double r2 = separation(P, xi, xj, dx, dy, dz);
+            const double r2 = separation(X, xi, xj, dx, dy, dz);
             if (!(r2 < P.rmax2_create)) return;
             const int tj = meta_type(mj);
             const int gj = meta_gid(xj);
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
 }
 
 // ---- steps 3 and 5: breakage nomination and killbond marks ----------------------
+template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __restrict__ Pp, Bank B, SweepBuf S) {
     const Params& P = *Pp;
     const int n = P.n;
@@ -181,6 +184,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
     if (i >= n) return;
     double4 xi = B.x[i];
     int mi = meta_word(xi);
+    const Box& X = box_of<BATCH>(P, mi);
     int gi = meta_gid(xi);
     int best = -1, best_rule = -1, best_g = 0;
     double best_r2 = 0.0;
@@ -197,7 +201,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
             Tab Tj = load_tab(B, n, j);
             if (tab_type_of(Tj, i) != t) continue;   // only symmetric bonds break
             double dx, dy, dz;
-            double r2 = separation(P, xi, xj, dx, dy, dz);
+            double r2 = separation(X, xi, xj, dx, dy, dz);
             int gj = meta_gid(xj);
             bool killed = false;
             int rule = -1;
@@ -233,6 +237,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
 }
 
 // ---- step 5: mutual breakage nominations ----------------------------------------
+template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_resolve(const Params* __restrict__ Pp, Bank B, SweepBuf S,
                                                       int64_t step) {
     const Params& P = *Pp;
@@ -247,9 +252,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_resolve(const Params* __restrict__
         for (int k = 0; k < rm; ++k)
             if (S.rmlist[k * n + i] == j) killed = true;   // killbond wins over the nomination
         if (!killed) {
-            int gi = meta_gid(B.x[i]), gj = meta_gid(B.x[j]);
+            const double4 xi = B.x[i];
+            int gi = meta_gid(xi), gj = meta_gid(B.x[j]);
             const Rule& r = P.rule[S.ruleK[i]];
-            if (pair_uniform(P, gi, gj, step, RNG_BREAK) < r.p) {
+            if (pair_uniform(box_of<BATCH>(P, meta_word(xi)), gi, gj, step, RNG_BREAK) < r.p) {
                 S.rmlist[rm * n + i] = j;
                 S.rmcnt[i] = (uint8_t)(rm + 1);
                 if (r.kind == RK_CONVERT) {
@@ -274,6 +280,7 @@ __device__ __forceinline__ bool bond_removed(const SweepBuf& S, int n, int u, in
 }
 
 // ---- steps 6-8: purge, remove / convert, create ---------------------------------
+template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ Pp, Bank B, SweepBuf S, int64_t step,
                                                     int* __restrict__ err) {
     const Params& P = *Pp;
@@ -328,9 +335,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
     // step 8: mutual creation nominations, no creation for converting beads
     int j = S.nomC[i];
     if (j >= 0 && !conv && S.nomC[j] == i && !S.conv[j]) {
-        int gi = meta_gid(B.x[i]), gj = meta_gid(B.x[j]);
+        const double4 xi = B.x[i];
+        int gi = meta_gid(xi), gj = meta_gid(B.x[j]);
         const Rule& r = P.rule[S.ruleC[i]];
-        if (pair_uniform(P, gi, gj, step, RNG_CREATE) < r.p) {
+        if (pair_uniform(box_of<BATCH>(P, meta_word(xi)), gi, gj, step, RNG_CREATE) < r.p) {
             if (w >= DB_MAXB) {
                 atomicOr(err, ERR_BOND_CAP);
             } else {
@@ -541,17 +549,24 @@ __global__ void k_clear_angles(int n, uint8_t* na, uint8_t* nd) {
 
 static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK); }
 
+template <bool BATCH>
+static void sweep_kernels(db_ctx* c, const Bank& B, unsigned g, int64_t step) {
+    hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_nominate_create<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
+                       c->cells.xs, c->sw);
+    hipLaunchKernelGGL(k_nominate_break<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
+    hipLaunchKernelGGL(k_resolve<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step);
+    hipLaunchKernelGGL(k_apply<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step, c->err_d);
+}
+
 void launch_sweep(db_ctx* c, int64_t step) {
     if (c->n == 0) return;
     hipStream_t s = c->stream;
     Bank& B = c->bank[c->cur];
     unsigned g = grid_for(c->n);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, c->sw.stats, 8);
-    hipLaunchKernelGGL(k_nominate_create, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start, c->cells.xs,
-                       c->sw);
-    hipLaunchKernelGGL(k_nominate_break, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
-    hipLaunchKernelGGL(k_resolve, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step);
-    hipLaunchKernelGGL(k_apply, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step, c->err_d);
+    if (c->nrep > 0) sweep_kernels<true>(c, B, g, step);
+    else sweep_kernels<false>(c, B, g, step);
     hipLaunchKernelGGL(k_generate<false>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
 }
 

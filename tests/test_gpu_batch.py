@@ -1,0 +1,108 @@
+"""Batches of independent replicas: every replica of a batch must evolve exactly
+as it does alone (same forces bit for bit, same sweep decisions, trajectories
+within rounding), with per-replica box edge, seed and temperature."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import perturbed
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1108_4214_amd  # noqa: F401
+
+
+def _replicas(precision, temps=(0.7, 1.0, 1.3), sizes=((12, 8, 0.3), (8, 6, 0.1), (40, 8, 0.3)), seed0=21):
+    """Standalone systems of different sizes, densities, seeds and temperatures."""
+    import paper_1108_4214_amd as pk
+    out = []
+    for r, ((nd, nbp, rho), T) in enumerate(zip(sizes, temps)):
+        s = perturbed(synth.duplex_box(nd, nbp, rho, seed0 + r, seed0 + 10 + r, T=T), 0.05, seed0 + r)
+        ff = synth.ff_t2(T0=T, T1=T)
+        g = pk.System(s.n, s.L, seed0 + 100 + r, precision).configure(s, ff, synth.rules_t2(p=0.5))
+        # round-trip the generated topology through the host, as the batch does, so
+        # that both hold their per-bead table entries in the same order
+        pk.db_set_reactive(g.ctx, s.reactive)
+        out.append((s, ff, g))
+    return out
+
+
+def _split(a, sizes):
+    return np.split(a, np.cumsum(sizes)[:-1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_forces_equal_standalone_bitwise(precision):
+    import paper_1108_4214_amd as pk
+    reps = _replicas(precision)
+    b = pk.Batch([g for _, _, g in reps])
+    fb = _split(b.forces(), b.sizes)
+    for (_, _, g), f in zip(reps, fb):
+        assert np.array_equal(f, g.forces())
+
+
+def test_batch_sweep_equal_standalone():
+    """Creation acceptance is keyed by replica-local ids and the replica's seed."""
+    import paper_1108_4214_amd as pk
+    reps = []
+    for r, m in enumerate((40, 70, 25)):
+        s = synth.isolated_pairs(m, 1.2, seed=r)
+        g = pk.System(s.n, s.L, 500 + r).configure(s, synth.ff_t2(), synth.rules_t2(p=0.5))
+        reps.append((s, g))
+    b = pk.Batch([g for _, g in reps])
+    b.sweep_now()
+    created = 0
+    off = 0
+    bb = b.bonds()
+    for s, g in reps:
+        g.sweep_now()
+        mine = bb[(bb[:, 0] >= off) & (bb[:, 0] < off + s.n)].copy()
+        mine[:, :2] -= off
+        assert np.array_equal(mine, g.bonds())
+        created += g.stats()["bonds_created"]
+        off += s.n
+    assert b.stats()["bonds_created"] == created > 0
+
+
+def test_batch_trajectory_matches_standalone():
+    import paper_1108_4214_amd as pk
+    reps = _replicas(0)
+    b = pk.Batch([g for _, _, g in reps])
+    b.step(30)
+    for r, (_, _, g) in enumerate(reps):
+        g.step(30)
+        xb, vb = b.replica_state(r)
+        xg, vg = g.state()
+        assert np.max(np.abs(xb - xg)) < 1e-9
+        assert np.max(np.abs(vb - vg)) < 1e-7
+    nb = sum(g.counts()[0] for _, _, g in reps)
+    assert b.counts()[0] == nb
+
+
+def test_batch_rejects_mismatched_physics_and_state_setters():
+    import paper_1108_4214_amd as pk
+    s = synth.duplex_box(5, 6, 0.2, 3, 13)
+    g1 = pk.System(s.n, s.L, 1).configure(s, synth.ff_t2(), synth.rules_t2())
+    ff = synth.ff_t2()
+    ff.dt = 0.004
+    g2 = pk.System(s.n, s.L, 2).configure(s, ff, synth.rules_t2())
+    with pytest.raises(pk.DynBondError):
+        pk.Batch([g1, g2])
+    b = pk.Batch([g1, g1])
+    with pytest.raises(pk.DynBondError) as e:
+        pk.db_set_state(b.ctx, s.x, s.v, s.type)
+    assert e.value.code == pk.DB_ESTATE
+
+
+def test_autotune_picks_a_grid_point():
+    import paper_1108_4214_amd as pk
+    s = perturbed(synth.duplex_box(40, 8, 0.3, 5, 15), 0.05, 5)
+    g = pk.System(s.n, s.L, 3, 1).configure(s, synth.ff_t2(), synth.rules_t2())
+    skin, perm = pk.db_autotune(g.ctx, 3)
+    assert skin in (0.4, 0.5, 0.6, 0.8) and perm in (1, 2, 4, 8)
+    assert g.stats()["steps"] == 16 * 4
