@@ -79,6 +79,43 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
     return out
 
 
+def run_batch(steps, warmup, precision=1):
+    """The replica ladder: 64 uneven replicas advanced together (one launch per
+    kernel for all of them) against the same replicas stepped one after another."""
+    import torch
+
+    import paper_1108_4214_amd as pk
+    import synth
+
+    ws = synth.c4()
+    reps = [pk.System(w.system.n, w.system.L, w.seed, precision).configure(w.system, w.ff, w.rules) for w in ws]
+    ntot = sum(g.n for g in reps)
+    b = pk.Batch(reps)
+    for g in reps:
+        g.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in reps:
+        g.step(steps)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - t0
+    for g in reps:
+        g.close()
+    b.close()
+    return {"workload": f"{len(ws)} replicas of 2k-50k beads (log-uniform), {ntot} beads, duplexes at rho=0.5, "
+                        "T_r = 0.6 + 0.8 r/63, sweep every 10 steps",
+            "beads": ntot, "replicas": len(ws), "steps": steps,
+            "value": ntot * steps / bat_s, "unit": "bead-steps/s", "ms_per_step": 1e3 * bat_s / steps,
+            "sequential_value": ntot * steps / seq_s, "sequential_ms_per_step": 1e3 * seq_s / steps,
+            "speedup": seq_s / bat_s}
+
+
 def cpu_baseline(w, steps):
     import oracle
 
@@ -102,6 +139,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--permute-every", type=int, default=None)
+    ap.add_argument("--no-batch", action="store_true", help="skip the replica-ladder measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build: a large box "
@@ -150,6 +188,8 @@ def main():
         "mixed_detail": mixed,
         "fp64_detail": fp64,
     }
+    if not args.no_batch:
+        line["batch"] = run_batch(max(100, args.steps // 4), min(args.warmup, 50))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)

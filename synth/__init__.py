@@ -318,6 +318,42 @@ def pack_duplexes(lengths: Sequence[int], L: float, rng, hybridized=True, seqs=N
     return b
 
 
+def pack_duplexes_rows(lengths: Sequence[int], L: float, rng, jitter=0.1) -> _Builder:
+    """Flat ladders laid end to end along x-rows (each takes its length + 1.5 sigma),
+    rows on a ny x nz lattice (row pitch at least 4.2 sigma in y, 1 sigma in z) in
+    random order, with jitter and flips; for boxes too small for one ladder per slot."""
+    b = _Builder()
+    order = rng.permutation(len(lengths))
+    rows, cur, used = [], [], 0.0
+    for d in order:
+        w = lengths[d] + 1.5
+        if w > L:
+            raise ValueError("duplexes do not fit in the box")
+        if used + w > L and cur:
+            rows.append(cur)
+            cur, used = [], 0.0
+        cur.append(int(d))
+        used += w
+    if cur:
+        rows.append(cur)
+    ny = max(1, int(L // 4.2))
+    nz = -(-len(rows) // ny)
+    dz = L / nz
+    if dz < 1.0:
+        raise ValueError("duplexes do not fit in the box")
+    sy = L / ny
+    slots = rng.permutation(ny * nz)[: len(rows)]
+    for row, sl in zip(rows, slots):
+        iy, iz = int(sl) % ny, int(sl) // ny
+        x0 = 0.0
+        for d in row:
+            n = lengths[d]
+            org = np.array([x0, iy * sy, iz * dz]) + rng.uniform(-jitter, jitter, size=3)
+            add_duplex(b, random_sequence(rng, n), org, flip_x=bool(rng.integers(2)), flip_y=bool(rng.integers(2)))
+            x0 += n + 1.5
+    return b
+
+
 # ----------------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------------
@@ -405,20 +441,31 @@ def c5(seed_w=5, seed_d=15, n_strands=100000) -> Workload:
 
 def c4(seed_w=4, seed_d=14, n_rep=64) -> List[Workload]:
     """Temperature ladder of uneven replicas (log-uniform 2k..50k beads) filled with
-    10-40 nt duplexes at density 0.5; T_r = 0.6 + 0.8 r/63."""
+    duplexes at density 0.5; T_r = 0.6 + 0.8 r/63.  Duplex lengths are uniform on
+    10..40 bp, capped by the box edge minus 3; ladders are laid end to end along
+    x-rows.  When a draw does not fit, the cap is lowered by 1 and the replica is
+    drawn again."""
     rng = np.random.default_rng(seed_w)
     out = []
     for r in range(n_rep):
         target = int(round(math.exp(rng.uniform(math.log(2000), math.log(50000)))))
         L = (target / 0.5) ** (1.0 / 3.0)
         cap = min(40, int(L - 3.0))
-        lengths, tot = [], 0
-        while tot < target:
-            n = int(rng.integers(10, cap + 1)) if cap > 10 else cap
-            lengths.append(n)
-            tot += 4 * n
-        Lr = (tot / 0.5) ** (1.0 / 3.0)
-        b = pack_duplexes(lengths, Lr, rng)
+        while True:
+            lo = min(10, cap)
+            lengths, tot = [], 0
+            while tot < target:
+                n = int(rng.integers(lo, cap + 1))
+                lengths.append(n)
+                tot += 4 * n
+            Lr = (tot / 0.5) ** (1.0 / 3.0)
+            try:
+                b = pack_duplexes_rows(lengths, Lr, rng)
+                break
+            except ValueError:
+                if cap <= 3:
+                    raise
+                cap -= 1
         T = 0.6 + 0.8 * r / max(1, n_rep - 1)
         s = _finish(b, Lr, np.random.default_rng(seed_d + 1000 * r), T)
         out.append(Workload(f"c4 replica {r}", s, ff_t2(T0=T, T1=T), rules_t2(p=0.5, every=10), 10000,

@@ -106,3 +106,24 @@ def test_autotune_picks_a_grid_point():
     skin, perm = pk.db_autotune(g.ctx, 3)
     assert skin in (0.4, 0.5, 0.6, 0.8) and perm in (1, 2, 4, 8)
     assert g.stats()["steps"] == 16 * 4
+
+
+def test_ladder_replicas_batch_forces_and_sweep():
+    """Replicas of the temperature-ladder recipe (uneven sizes, own T and seed)."""
+    import paper_1108_4214_amd as pk
+    ws = synth.c4(n_rep=4)
+    reps = []
+    for w in ws:
+        g = pk.System(w.system.n, w.system.L, w.seed, 1).configure(w.system, w.ff, w.rules)
+        pk.db_set_reactive(g.ctx, w.system.reactive)
+        reps.append(g)
+    b = pk.Batch(reps)
+    fb = _split(b.forces(), b.sizes)
+    for g, f in zip(reps, fb):
+        assert np.array_equal(f, g.forces())
+    b.step(25)
+    for r, g in enumerate(reps):
+        g.step(25)
+        xb, _ = b.replica_state(r)
+        xg, _ = g.state()
+        assert np.max(np.abs(xb - xg)) < 1e-4   # mixed precision, 25 steps
