@@ -936,7 +936,7 @@ static void record_sweep_stats(db_ctx* c) {
     c->sweeps++;
 }
 
-static int launch_timed_step(db_ctx* c, int64_t step, int slot) {
+static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save) {
     if (c->profile) {
         if ((size_t)c->ev_used + 2 > c->ev_pool.size()) {
             for (int k = 0; k < 2 * kMaxBlock; ++k) {
@@ -946,11 +946,11 @@ static int launch_timed_step(db_ctx* c, int64_t step, int slot) {
             }
         }
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
-        launch_step(c, step, slot);
+        launch_step(c, step, slot, save);
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     } else {
-        launch_step(c, step, slot);
+        launch_step(c, step, slot, save);
     }
     return DB_OK;
 }
@@ -989,13 +989,13 @@ int db_step(db_ctx* c, int64_t nsteps) {
             c->swept_step = k0;
         }
         launch_build_nlist(c);   // after the sweep: exclusions follow the new bonds
-        Bank& B = c->bank[c->cur];
-        if (guard && !permute) {
-            HIPCHK(c, hipMemcpyAsync(c->xsave, B.x, 32 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
-            HIPCHK(c, hipMemcpyAsync(c->vsave, B.v, 24 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
-        }
         launch_fill_int((int*)c->vmax2, 0, (size_t)len * DB_VMAX_SPREAD, s);
-        for (int64_t q = 0; q < len; ++q) launch_timed_step(c, k0 + q, (int)q);
+        // the block's input state is kept for a re-run: by the reorder, or else by
+        // the first step kernel of the block
+        for (int64_t q = 0; q < len; ++q) {
+            rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0);
+            if (rc) return rc;
+        }
         hipLaunchKernelGGL(k_report, dim3(1), dim3(kMaxBlock), 0, s, c->vmax2, (int)len, c->err_d, c->sw.stats,
                            sweep_due ? 1 : 0, X.pin_dev);
         HIPCHK(c, hipStreamSynchronize(s));

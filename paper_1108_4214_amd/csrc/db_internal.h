@@ -215,7 +215,7 @@ void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, 
 
 // kernels_force.hip
 void launch_build_nlist(db_ctx* c);                  // Verlet list from the current cell list
-void launch_step(db_ctx* c, int64_t step, int slot_in_block);
+void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save = false);   // save: keep the input x, v
 void launch_forces(db_ctx* c, double* f_gid_order);
 void launch_energy(db_ctx* c, double* out6_device);
 

@@ -570,7 +570,8 @@ template <typename R, int MODE, bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
                                                     double4* __restrict__ xout, int64_t step, double pref,
                                                     unsigned int* __restrict__ vmax2_slot,
-                                                    double* __restrict__ fout, int* __restrict__ err) {
+                                                    double* __restrict__ fout, int* __restrict__ err,
+                                                    double4* __restrict__ xsave, double* __restrict__ vsave) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
     const Params& P = *Pp;
     const int n = P.n;
@@ -606,6 +607,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         vx = B.v[i];
         vy = B.v[n + i];
         vz = B.v[2 * n + i];
+        if (xsave) {   // first step of a block: keep its input state for a re-run
+            xsave[i] = xi;
+            vsave[i] = vx;
+            vsave[n + i] = vy;
+            vsave[2 * n + i] = vz;
+        }
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
             if (BATCH) pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
@@ -747,30 +754,31 @@ static double langevin_prefactor(const Params& P, int64_t step) {
 
 template <typename R, int MODE, bool BATCH>
 static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, int64_t step, double pref, unsigned* vm,
-                               double* f) {
+                               double* f, bool save) {
     hipLaunchKernelGGL((k_step<R, MODE, BATCH>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
-                       c->nlist, c->halo, xout, step, pref, vm, f, c->err_d);
+                       c->nlist, c->halo, xout, step, pref, vm, f, c->err_d, save ? c->xsave : nullptr,
+                       save ? c->vsave : nullptr);
 }
 
 template <int MODE>
 static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, int64_t step, double pref, unsigned* vm,
-                            double* f) {
+                            double* f, bool save = false) {
     const bool batch = c->nrep > 0;
     if (c->precision == DB_MIXED) {
-        if (batch) launch_step_kernel<float, MODE, true>(c, B, xout, step, pref, vm, f);
-        else launch_step_kernel<float, MODE, false>(c, B, xout, step, pref, vm, f);
+        if (batch) launch_step_kernel<float, MODE, true>(c, B, xout, step, pref, vm, f, save);
+        else launch_step_kernel<float, MODE, false>(c, B, xout, step, pref, vm, f, save);
     } else {
-        if (batch) launch_step_kernel<double, MODE, true>(c, B, xout, step, pref, vm, f);
-        else launch_step_kernel<double, MODE, false>(c, B, xout, step, pref, vm, f);
+        if (batch) launch_step_kernel<double, MODE, true>(c, B, xout, step, pref, vm, f, save);
+        else launch_step_kernel<double, MODE, false>(c, B, xout, step, pref, vm, f, save);
     }
 }
 
-void launch_step(db_ctx* c, int64_t step, int slot_in_block) {
+void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
     if (c->n == 0) return;
     const double pref = langevin_prefactor(c->hp, step);
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
-    launch_step_any<MODE_STEP>(c, B, c->xnext, step, pref, vm, nullptr);
+    launch_step_any<MODE_STEP>(c, B, c->xnext, step, pref, vm, nullptr, save);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;

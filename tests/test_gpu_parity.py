@@ -203,6 +203,30 @@ def test_short_trajectory_fp64():
     assert same_topology(g, o), topo_diff(g, o)
 
 
+@pytest.mark.parametrize("permute_every", [1, 3])
+def test_rollback_reruns_the_block(permute_every):
+    """A skin far too thin for the speeds forces the scheduler to restore the
+    block's input state and re-run it with a fresh list every step (the state is
+    kept by the reorder when it runs, else by the block's first step kernel); the
+    trajectory must still be the oracle's."""
+    import paper_1108_4214_amd as pk
+    s = synth.single_strands(24, 6, L=11.0, seed_w=3, seed_d=4, T=2.0)
+    rules = synth.rules_t2(p=0.7, every=5, r_kill=1.35)
+    ff = synth.ff_t2(T0=2.0, T1=2.0)
+    g, o = both(s, ff, rules, seed=9)
+    pk.db_tune(g.ctx, 0.02, permute_every)
+    g.step(20)
+    o.step(20)
+    assert g.stats()["rollbacks"] > 0
+    xg, vg = g.state()
+    xo, vo = o.state()
+    d = xg - xo
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-7
+    assert same_topology(g, o), topo_diff(g, o)
+
+
 def test_shadow_mode_dynamic_run():
     s = synth.single_strands(24, 6, L=11.0, seed_w=3, seed_d=4)
     rules = synth.rules_t2(p=0.7, every=2, r_kill=1.35)
