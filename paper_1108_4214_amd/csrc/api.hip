@@ -168,6 +168,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->cells.list, 4 * n);
     put(c->cells.xs, 16 * n);
     put(c->cells.cellid, 4 * n);
+    put(c->cells.rank, 4 * n);
     put(c->cells.blocksum, 4 * (size_t)blocksum_ints((int)std::max(n, nc) + 1));
     put(c->slot_of_gid, 4 * n);
     put(c->err_d, 64);

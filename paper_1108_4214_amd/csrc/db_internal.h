@@ -136,6 +136,7 @@ struct Cells {
     int* list;        // [n] slots, cell by cell, ascending within a cell
     float4* xs;       // [n] in list order: float x, y, z and the slot (bits) of each entry
     int* cellid;      // [n]
+    int* rank;        // [n] place of the bead among the beads of its cell
     int* blocksum;    // scan scratch
 };
 

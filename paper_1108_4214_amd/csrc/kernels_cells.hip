@@ -19,20 +19,40 @@ void launch_fill_int(int* p, int value, size_t count, hipStream_t s) {
 }
 
 // ---- binning -----------------------------------------------------------------
+// Cell of every bead and its rank among the beads of that cell.  Beads in slot
+// order are mostly sorted by cell, so neighbouring lanes of a wavefront usually
+// share a cell: each run of equal cells takes one atomic for the whole run and
+// hands out consecutive ranks.
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_bin(const Params* __restrict__ Pp, const double4* __restrict__ x,
-                                                   int* __restrict__ cellid, int* __restrict__ cnt) {
+                                                   int* __restrict__ cellid, int* __restrict__ rank,
+                                                   int* __restrict__ cnt) {
     const Params& P = *Pp;
-    int i = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (i >= P.n) return;
-    double4 xi = x[i];
-    const Box& X = box_of<BATCH>(P, meta_word(xi));
-    int cx = cell_coord(xi.x, X.cell_scale, X.nc);
-    int cy = cell_coord(xi.y, X.cell_scale, X.nc);
-    int cz = cell_coord(xi.z, X.cell_scale, X.nc);
-    int c = X.cell_off + (cz * X.nc + cy) * X.nc + cx;
-    cellid[i] = c;
-    atomicAdd(&cnt[c], 1);
+    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int c = -1;
+    if (i < P.n) {
+        const double4 xi = x[i];
+        const Box& X = box_of<BATCH>(P, meta_word(xi));
+        const int cx = cell_coord(xi.x, X.cell_scale, X.nc);
+        const int cy = cell_coord(xi.y, X.cell_scale, X.nc);
+        const int cz = cell_coord(xi.z, X.cell_scale, X.nc);
+        c = X.cell_off + (cz * X.nc + cy) * X.nc + cx;
+    }
+    const int prev = __shfl_up(c, 1, 64);
+    const bool head = lane == 0 || prev != c;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int start = 63 - __clzll(heads & upto);
+    const unsigned long long after = start == 63 ? 0ull : (heads & ~((2ull << start) - 1ull));
+    const int end = after ? __ffsll((long long)after) - 1 : 64;
+    int base = 0;
+    if (lane == start && c >= 0) base = atomicAdd(&cnt[c], end - start);
+    base = __shfl(base, start, 64);
+    if (i < P.n) {
+        cellid[i] = c;
+        rank[i] = base + (lane - start);
+    }
 }
 
 // ---- exclusive scan (1024 items per workgroup, multi-level) -------------------
@@ -123,14 +143,16 @@ void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, 
 }
 
 // ---- scatter and in-cell ordering --------------------------------------------
+// the bead's place in the list from its cell start and rank; the first bead of
+// every cell clears the count for the next build (the scan has consumed it)
 __global__ __launch_bounds__(DB_BLOCK) void k_scatter(int n, const int* __restrict__ cellid,
-                                                       const int* __restrict__ start, int* __restrict__ cnt,
-                                                       int* __restrict__ list) {
+                                                       const int* __restrict__ rank, const int* __restrict__ start,
+                                                       int* __restrict__ cnt, int* __restrict__ list) {
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i >= n) return;
-    int c = cellid[i];
-    int k = atomicSub(&cnt[c], 1) - 1;   // leaves cnt at zero for the next build
+    const int c = cellid[i], k = rank[i];
     list[start[c] + k] = i;
+    if (k == 0) cnt[c] = 0;
 }
 
 // ascending slot order inside each cell makes the list independent of the
@@ -166,16 +188,18 @@ void launch_build_cells(db_ctx* c) {
     unsigned nb = (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK);
     if (n > 0) {
         if (c->nrep > 0)
-            hipLaunchKernelGGL(k_bin<true>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid, c->cells.cnt);
+            hipLaunchKernelGGL(k_bin<true>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid,
+                               c->cells.rank, c->cells.cnt);
         else
-            hipLaunchKernelGGL(k_bin<false>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid, c->cells.cnt);
+            hipLaunchKernelGGL(k_bin<false>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid,
+                               c->cells.rank, c->cells.cnt);
     }
     // start = exclusive scan of cnt; start[ncell] = n
     scan_into(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, c->cells.start + ncell, n, (size_t)1);
     if (n > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.cellid, c->cells.start,
-                           c->cells.cnt, c->cells.list);
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.cellid, c->cells.rank,
+                           c->cells.start, c->cells.cnt, c->cells.list);
         unsigned cb = (unsigned)((ncell + DB_BLOCK - 1) / DB_BLOCK);
         hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(DB_BLOCK), 0, s, ncell, c->cells.start, c->cells.list, B.x,
                            c->cells.xs);

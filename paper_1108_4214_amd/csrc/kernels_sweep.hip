@@ -288,8 +288,13 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i >= n) return;
     unsigned long long ang_del = 0, dih_del = 0;
+    // removals of this sweep were all counted by the kernels before this one; with
+    // none (the common case at low reaction density) no table needs editing
+    const bool any_removed = (S.stats[ST_BROKEN] | S.stats[ST_KILLED] | S.stats[ST_CONVERTED]) != 0;
+    int w = 0;
     // step 6: angles and dihedrals crossing a removed bond (judged on the old graph)
-    int na = B.na[i], w = 0;
+    if (any_removed) {
+    int na = B.na[i];
     for (int k = 0; k < na; ++k) {
         int4 e = B.ang[k * n + i];
         if (bond_removed(S, n, e.x, e.y) || bond_removed(S, n, e.y, e.z)) {
@@ -315,22 +320,26 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
         ++w;
     }
     B.nd[i] = (uint8_t)w;
-    // step 7: own bond entries
-    int rm = S.rmcnt[i];
-    int conv = S.conv[i];
-    int convp = conv ? S.newp[i] : -1;
-    int nb = B.nb[i];
-    w = 0;
-    for (int k = 0; k < nb; ++k) {
-        int j = B.bp[k * n + i];
-        int t = B.bt[k * n + i];
-        if (rm > 0 && bond_removed(S, n, i, j)) {
-            if (j != convp) continue;
-            t = P.rule[S.ruleK[i]].bt2;   // converted: same partner, new type
+    }
+    // step 7: own bond entries (a conversion is listed among the removed entries)
+    const int rm = S.rmcnt[i];
+    const int conv = S.conv[i];
+    const int nb = B.nb[i];
+    w = nb;
+    if (rm > 0) {
+        const int convp = conv ? S.newp[i] : -1;
+        w = 0;
+        for (int k = 0; k < nb; ++k) {
+            int j = B.bp[k * n + i];
+            int t = B.bt[k * n + i];
+            if (bond_removed(S, n, i, j)) {
+                if (j != convp) continue;
+                t = P.rule[S.ruleK[i]].bt2;   // converted: same partner, new type
+            }
+            B.bp[w * n + i] = j;
+            B.bt[w * n + i] = (int8_t)t;
+            ++w;
         }
-        B.bp[w * n + i] = j;
-        B.bt[w * n + i] = (int8_t)t;
-        ++w;
     }
     // step 8: mutual creation nominations, no creation for converting beads
     int j = S.nomC[i];
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
             if (gi < gj) stat_add(S.stats, ST_CREATED, 1);
         }
     }
-    B.nb[i] = (uint8_t)w;
+    if (w != nb) B.nb[i] = (uint8_t)w;
     stat_add(S.stats, ST_ANG_DEL, ang_del);
     stat_add(S.stats, ST_DIH_DEL, dih_del);
 }
@@ -406,6 +415,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i >= n) return;
     if (P.narule == 0 && P.ndrule == 0) return;
+    // no bond was created or converted in this sweep: nothing to generate
+    if (!ALL && (S.stats[ST_CREATED] | S.stats[ST_CONVERTED]) == 0) return;
     Tab Ti = load_tab(B, n, i);
     if (!ALL) {
         // only beads within two bonds of a new bond can lie on a qualifying path
