@@ -363,6 +363,7 @@ static int upload_system(db_ctx* c) {
     HIPCHK(c, hipStreamSynchronize(s));
     X.dev_valid = true;
     X.dev_error = 0;
+    c->halo_force = true;
     launch_fill_int(c->err_d, 0, 16, s);
     return DB_OK;
 }

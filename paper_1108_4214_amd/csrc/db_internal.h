@@ -27,6 +27,9 @@ enum RuleKind { RK_CREATE = 1, RK_CREATEDIR = 2, RK_BREAK = 3, RK_KILL = 4, RK_C
 // random-number stream tags (top 4 bits of the last counter word)
 enum RngKind : uint32_t { RNG_LANGEVIN = 0u, RNG_CREATE = 1u, RNG_BREAK = 2u };
 
+// counters of one sweep (SweepBuf::stats)
+enum { ST_CREATED = 0, ST_BROKEN, ST_KILLED, ST_CONVERTED, ST_ANG_NEW, ST_ANG_DEL, ST_DIH_NEW, ST_DIH_DEL };
+
 // device error word bits
 enum ErrBit : int { ERR_BOND_CAP = 1, ERR_ANGLE_CAP = 2, ERR_DIH_CAP = 4, ERR_NONFINITE = 8, ERR_NLIST = 16 };
 
@@ -172,6 +175,8 @@ struct db_ctx {
     db::Cells cells;
     db::NList nlist;
     db::Halo halo;
+    bool halo_force;     // slots or tables changed: rebuild the halo
+    bool halo_sweep;     // a sweep ran since the last halo build: rebuild it if the sweep changed bonds
     // a batch of independent replicas (nrep > 0): one box per replica
     int nrep;
     std::vector<db::Box> reps;   // host copy; cell_off and gid_off fixed at creation

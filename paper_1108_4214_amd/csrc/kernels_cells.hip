@@ -266,6 +266,7 @@ void launch_permute(db_ctx* c, bool save) {
                        c->cells.list, newslot, c->slot_of_gid, save ? c->xsave : (double4*)nullptr,
                        save ? c->vsave : (double*)nullptr, c->cells.xs);
     c->cur = 1 - c->cur;
+    c->halo_force = true;
 }
 
 }  // namespace db

@@ -423,11 +423,17 @@ __device__ __forceinline__ void dihedral_terms(const Params& P, const Box& X, co
 // bead i, instead of once per entry that names it.
 //   acode: role (2 bits) | other member 1 << 2 | other member 2 << 5 | type << 8
 //   dcode: role (2 bits) | others 1..3 << 2, 5, 8 (3 bits each) | type << 11
-__global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp, Bank B, Halo H) {
+// sweep_stats: the counters of a sweep that ran since the last build, which is
+// then repeated only if that sweep changed a bond (NULL: rebuild regardless)
+__global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp, Bank B, Halo H,
+                                                   const unsigned long long* __restrict__ sweep_stats) {
     const Params& P = *Pp;
     const int n = P.n;
     const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i >= n) return;
+    if (sweep_stats &&
+        (sweep_stats[ST_CREATED] | sweep_stats[ST_BROKEN] | sweep_stats[ST_KILLED] | sweep_stats[ST_CONVERTED]) == 0)
+        return;
     int u[DB_MAXU];
     const int nb = B.nb[i];
 #pragma unroll
@@ -731,7 +737,11 @@ static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOC
 
 void launch_build_nlist(db_ctx* c) {
     if (c->n == 0) return;
-    hipLaunchKernelGGL(k_halo, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur], c->halo);
+    if (c->halo_force || c->halo_sweep)
+        hipLaunchKernelGGL(k_halo, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
+                           c->halo, c->halo_force ? (const unsigned long long*)nullptr : c->sw.stats);
+    c->halo_force = false;
+    c->halo_sweep = false;
     if (c->nrep > 0)
         hipLaunchKernelGGL(k_build_nlist<true>, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                            c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d);

@@ -17,7 +17,6 @@
 
 namespace db {
 
-enum { ST_CREATED = 0, ST_BROKEN, ST_KILLED, ST_CONVERTED, ST_ANG_NEW, ST_ANG_DEL, ST_DIH_NEW, ST_DIH_DEL };
 
 // A bead's bond table held in registers.  Entries are read through selects, so
 // loops over a run-time count never index a private array (which would spill it
@@ -198,24 +197,32 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
             double4 xj = B.x[j];
             int mj = meta_word(xj);
             if (!meta_reactive(mj)) continue;
-            Tab Tj = load_tab(B, n, j);
-            if (tab_type_of(Tj, i) != t) continue;   // only symmetric bonds break
             double dx, dy, dz;
             double r2 = separation(X, xi, xj, dx, dy, dz);
             int gj = meta_gid(xj);
             bool killed = false;
             int rule = -1;
+            // the partner's table is read only for a bond some rule could act on
+            bool have_tj = false;
+            Tab Tj{0, -1, -1, -1, -1, 0, 0, 0, 0};
             for (int q = 0; q < P.nrule; ++q) {
                 const Rule& r = P.rule[q];
+                if (r.bt1 != t || !(r2 > r.r2)) continue;
                 if (r.kind == RK_KILL) {
-                    if (r.bt1 == t && r2 > r.r2) killed = true;
+                    killed = true;
                 } else if (r.kind == RK_BREAK) {
-                    if (r.bt1 == t && r2 > r.r2) rule = q;
+                    rule = q;
                 } else if (r.kind == RK_CONVERT) {
-                    if (r.bt1 == t && r2 > r.r2 && max_ok(P, ti, Ti, r.bt2) && max_ok(P, meta_type(mj), Tj, r.bt2))
-                        rule = q;
+                    if (!have_tj) {
+                        Tj = load_tab(B, n, j);
+                        have_tj = true;
+                    }
+                    if (max_ok(P, ti, Ti, r.bt2) && max_ok(P, meta_type(mj), Tj, r.bt2)) rule = q;
                 }
             }
+            if (!killed && rule < 0) continue;
+            if (!have_tj) Tj = load_tab(B, n, j);
+            if (tab_type_of(Tj, i) != t) continue;   // only symmetric bonds break
             if (killed) {
                 S.rmlist[rm * n + i] = j;
                 ++rm;
@@ -572,6 +579,10 @@ static void sweep_kernels(db_ctx* c, const Bank& B, unsigned g, int64_t step) {
 
 void launch_sweep(db_ctx* c, int64_t step) {
     if (c->n == 0) return;
+    // the halo follows any topology event of this sweep; a second sweep before the
+    // next build would reset the counters of the first, so then rebuild regardless
+    if (c->halo_sweep) c->halo_force = true;
+    c->halo_sweep = true;
     hipStream_t s = c->stream;
     Bank& B = c->bank[c->cur];
     unsigned g = grid_for(c->n);
@@ -588,6 +599,7 @@ void launch_generate_all(db_ctx* c) {
     unsigned g = grid_for(c->n);
     hipLaunchKernelGGL(k_clear_angles, dim3(g), dim3(DB_BLOCK), 0, s, c->n, B.na, B.nd);
     hipLaunchKernelGGL(k_generate<true>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
+    c->halo_force = true;
 }
 
 // ---- canonical output lists: each bond / angle / dihedral is emitted once -------
