@@ -7,6 +7,10 @@
 #pragma once
 #include "db_device.h"
 
+#ifndef DB_SCAN_W
+#define DB_SCAN_W 4   // candidates requested together per run
+#endif
+
 namespace db {
 
 __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
@@ -19,28 +23,10 @@ __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
 // With three or more cells per edge, the periodic image of a neighbour cell is
 // fixed by whether its index wrapped, so the bead's own coordinates are shifted
 // once per run and the candidates need no minimum-image test (the true nearest
-// image is that one for every candidate within one cell edge).  Smaller grids
-// visit every cell once and take the per-candidate minimum image.  The visitor
-// has a single call site per grid case, which keeps it inlined once.
-template <class F>
-__device__ __forceinline__ void scan_run(const float4* __restrict__ xs, int s0, int s1, int i, float qx, float qy,
-                                         float qz, float cut2, F&& f) {
-    for (int p = s0; p < s1; p += 4) {
-        float4 e[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) e[q] = xs[min(p + q, s1 - 1)];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            // one branch per candidate: range, self and distance folded into one predicate
-            const int j = __float_as_int(e[q].w);
-            const float dx = e[q].x - qx, dy = e[q].y - qy, dz = e[q].z - qz;
-            const float r2 = (dx * dx + dy * dy) + dz * dz;
-            const bool hit = (p + q < s1) & (j != i) & (r2 < cut2);
-            if (hit) f(j, r2);
-        }
-    }
-}
-
+// image is that one for every candidate within one cell edge).  Runs are read
+// four entries at a time.  Smaller grids visit every cell once and take the
+// per-candidate minimum image.  The visitor has a single call site per grid
+// case, which keeps it inlined once.
 template <class F>
 __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__ cstart,
                                            const float4* __restrict__ xs, int i, const double4& xi, float cut2,
@@ -53,31 +39,64 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
     const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
     cstart += X.cell_off;
     if (X.noff == 3) {
-        // nine x-rows of three cells; a row that wraps in x splits into two runs
-        // (the wrapped cell seen through its image, and the two contiguous ones),
-        // so each row is visited as two runs, the second empty unless it wraps
+        // Nine x-rows of three cells.  The x-part of a row is the same for every
+        // row: cells [a0, a1), and only when it wraps in x a second range [b0, b1)
+        // seen through its image; both are read as one run.  The bounds of the
+        // next row are requested before the current row is scanned.
         auto shift = [&](int c) { return c < 0 ? -Lf : (c >= nc ? Lf : 0.0f); };
-        for (int r = 0; r < 18; ++r) {
-            const int zr = cz + r / 6 - 1, yr = cy + (r >> 1) % 3 - 1, part = r & 1;
-            const float qz = pz - shift(zr), qy = py - shift(yr);
-            const int row = (wrap_cell(zr, nc) * nc + wrap_cell(yr, nc)) * nc;
-            int a0, a1;          // cell range [a0, a1) of the row, contiguous in the list
-            float qx = px;
-            if (cx >= 1 && cx <= nc - 2) {
-                a0 = part ? 0 : cx - 1;
-                a1 = part ? 0 : cx + 2;
-            } else if (cx == 0) {
-                a0 = part ? 0 : nc - 1;
-                a1 = part ? 2 : nc;
-                if (!part) qx = px + Lf;
-            } else {
-                a0 = part ? 0 : nc - 2;
-                a1 = part ? 1 : nc;
-                if (part) qx = px - Lf;
+        int a0, a1, b0 = 0, b1 = 0;
+        float qx1 = px;
+        if (cx >= 1 && cx <= nc - 2) {
+            a0 = cx - 1;
+            a1 = cx + 2;
+        } else if (cx == 0) {
+            a0 = 0;
+            a1 = 2;
+            b0 = nc - 1;
+            b1 = nc;
+            qx1 = px + Lf;
+        } else {
+            a0 = nc - 2;
+            a1 = nc;
+            b0 = 0;
+            b1 = 1;
+            qx1 = px - Lf;
+        }
+        const bool wrapx = b1 > b0;
+        auto row_of = [&](int r) {
+            return (wrap_cell(cz + r / 3 - 1, nc) * nc + wrap_cell(cy + r % 3 - 1, nc)) * nc;
+        };
+        int row = row_of(0);
+        int s0 = cstart[row + a0], s1 = cstart[row + a1];
+        int t0 = wrapx ? cstart[row + b0] : 0, t1 = wrapx ? cstart[row + b1] : 0;
+        for (int r = 0; r < 9; ++r) {
+            const float qz = pz - shift(cz + r / 3 - 1), qy = py - shift(cy + r % 3 - 1);
+            const int c0 = s0, d0 = t0;
+            const int len0 = s1 - s0, len = len0 + (t1 - t0);
+            if (r < 8) {
+                row = row_of(r + 1);
+                s0 = cstart[row + a0];
+                s1 = cstart[row + a1];
+                t0 = wrapx ? cstart[row + b0] : 0;
+                t1 = wrapx ? cstart[row + b1] : 0;
             }
-            const int s0 = a1 > a0 ? cstart[row + a0] : 0;
-            const int s1 = a1 > a0 ? cstart[row + a1] : 0;
-            scan_run(xs, s0, s1, i, qx, qy, qz, cut2, f);
+            for (int p = 0; p < len; p += DB_SCAN_W) {
+                float4 e[DB_SCAN_W];
+#pragma unroll
+                for (int q = 0; q < DB_SCAN_W; ++q) {
+                    const int k = min(p + q, len - 1);
+                    e[q] = xs[k < len0 ? c0 + k : d0 + (k - len0)];
+                }
+#pragma unroll
+                for (int q = 0; q < DB_SCAN_W; ++q) {
+                    // one branch per candidate: range, self and distance folded into one predicate
+                    const int j = __float_as_int(e[q].w);
+                    const float dx = e[q].x - (p + q < len0 ? px : qx1), dy = e[q].y - qy, dz = e[q].z - qz;
+                    const float r2 = (dx * dx + dy * dy) + dz * dz;
+                    const bool hit = (p + q < len) & (j != i) & (r2 < cut2);
+                    if (hit) f(j, r2);
+                }
+            }
         }
         return;
     }
