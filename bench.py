@@ -26,6 +26,46 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the step kernel from hardware counters (rocprofv3 --pmc FETCH_SIZE,
+# then WRITE_SIZE), recorded with a hash of the kernel sources it was taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c3_1M_traffic.txt")
+KERNEL_SOURCES = ["kernels_force.hip", "cell_scan.h", "db_device.h", "db_internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1108_4214_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """bytes per launch from the counters, or None if absent or taken on other sources"""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def copy_probe():
+    """a plain device copy of 256 MiB, three times: the reference that scales the
+    FETCH_SIZE / WRITE_SIZE counters"""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
 
 def algorithmic_bytes_per_bead_step(b, a, d, every):
     """Bytes the method must move per bead and step: position and velocity read and
@@ -140,6 +180,8 @@ def main():
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--permute-every", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the replica-ladder measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build: a large box "
@@ -159,6 +201,9 @@ def main():
     kernel_bytes, step_bytes = algorithmic_bytes_per_bead_step(b, a, d, every)
     n = w.system.n
     achieved = kernel_bytes * n / (mixed["step_kernel_us"] * 1e-6) / 1e9 if mixed["step_kernel_us"] > 0 else 0.0
+    tb = recorded_traffic()
+    # measured HBM bytes per launch over the same live launch time: GB/s, comparable with achieved
+    traffic = tb / (mixed["step_kernel_us"] * 1e-6) / 1e9 if (tb is not None and mixed["step_kernel_us"] > 0) else None
     line = {
         "metric": "bead-steps/s at 1M beads incl. bond sweep; mixed vs FP64 on same GPU",
         "value": mixed["bead_steps_per_s"],
@@ -176,7 +221,7 @@ def main():
                                "1000000 beads, rho=0.5, T ramp 0.5->1.5 over 1e5 steps, sweep every 10 steps",
                    "beads": n, "sweep_every": every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tb,
                      "kernel": "k_step<float> (fused pair + bonded + Langevin + velocity Verlet)",
                      "bytes_per_bead_step": kernel_bytes, "beads_per_launch": n,
                      "launch_us": mixed["step_kernel_us"], "launches_timed": mixed["step_kernel_launches"]},
@@ -188,6 +233,8 @@ def main():
         "mixed_detail": mixed,
         "fp64_detail": fp64,
     }
+    if args.copy_probe:
+        copy_probe()
     if not args.no_batch:
         line["batch"] = run_batch(max(100, args.steps // 4), min(args.warmup, 50))
     if not args.no_cpu_baseline:

@@ -168,8 +168,8 @@ int db_get_stats(db_ctx* ctx, db_stats* out);
 /* current step counter; db_set_step also allows the sweep of that step again */
 int db_set_step(db_ctx* ctx, int64_t step);
 /* tuning knobs of the step scheduler: the neighbour-list skin (list cutoff minus
- * pair cutoff, > 0; default 0.6) and how many cell-list rebuilds pass between
- * reorderings of the per-bead state into cell order (>= 1; default 4) */
+ * pair cutoff, > 0; default 0.55) and how many cell-list rebuilds pass between
+ * reorderings of the per-bead state into cell order (>= 1; default 8) */
 int db_tune(db_ctx* ctx, double skin, int32_t permute_every);
 /* enable (1) / disable (0) HIP-event timing of every launch of the fused step
  * kernel on the handle's stream */

@@ -27,7 +27,7 @@ using namespace db;
 namespace {
 
 const int kMaxBlock = 64;
-const double kSkinDefault = 0.6;
+const double kSkinDefault = 0.55;
 
 // host memory the device writes its end-of-block report into (mapped, pinned)
 struct Pinned {
@@ -581,7 +581,7 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->skin = kSkinDefault;
     c->swept_step = -1;
     c->rebuild_interval = 8;
-    c->permute_every = 4;
+    c->permute_every = 8;
     c->vmax_est = 0;
     HostSys& h = c->hx->h;
     h.x.assign(3 * (size_t)n, 0.0);
