@@ -68,6 +68,11 @@ typedef struct {
     int64_t steps;           /* current step counter */
     int64_t rebuilds;        /* cell-list rebuilds */
     int64_t rollbacks;       /* blocks re-run because beads moved further than the skin */
+    /* topology-energy ledger (appendix step 9 statistics, extended): change of the
+     * potential energy (pair + bond + angle + dihedral, FP64) across the last sweep
+     * at fixed positions, and its sum over all sweeps; 0 while not tracked
+     * (db_track_topology_energy) */
+    double du_topo_last, du_topo_cum;
 } db_stats;
 
 /* ---- lifecycle ---------------------------------------------------------------- */
@@ -178,6 +183,10 @@ int db_profile(db_ctx* ctx, int enable);
  * launches timed since the last call, and their number; resets the tally */
 int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);
 
+/* enable (1) / disable (0) the topology-energy ledger of db_stats: every sweep is
+ * then bracketed by two potential-energy evaluations (costs about two force
+ * passes per sweep) */
+int db_track_topology_energy(db_ctx* ctx, int enable);
 /* tries skin in {0.4, 0.5, 0.6, 0.8} x permute_every in {1, 2, 4, 8}, running
  * steps_per_trial steps of the trajectory with each (the system advances by
  * 16 x steps_per_trial steps), and keeps the fastest; best_skin / best_permute

@@ -32,7 +32,7 @@ EXPORTS = [
     "db_angle_pattern", "db_dihedral_pattern", "db_step", "db_sweep_now", "db_forces", "db_energy",
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
-    "db_batch_create", "db_batch_get_state",
+    "db_batch_create", "db_batch_get_state", "db_track_topology_energy",
 ]
 
 STAT_FIELDS = [
@@ -44,8 +44,11 @@ STAT_FIELDS = [
 ]
 
 
+LEDGER_FIELDS = ["du_topo_last", "du_topo_cum"]
+
+
 class db_stats(C.Structure):
-    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS]
+    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS] + [(f, C.c_double) for f in LEDGER_FIELDS]
 
 
 class DynBondError(RuntimeError):
@@ -104,6 +107,7 @@ _SIG = {
     "db_autotune": [_P, _i64, C.POINTER(C.c_double), C.POINTER(C.c_int32)],
     "db_batch_create": [C.POINTER(C.c_void_p), _P, _i32, _P],
     "db_batch_get_state": [_P, _i32, _P, _P, _int],
+    "db_track_topology_energy": [_P, _int],
 }
 for _name, _args in _SIG.items():
     _f = getattr(_lib, _name)
@@ -332,7 +336,9 @@ def db_get_dihedrals(ctx):
 def db_get_stats(ctx):
     s = db_stats()
     _check(ctx, _lib.db_get_stats(ctx, C.byref(s)))
-    return {f: int(getattr(s, f)) for f in STAT_FIELDS}
+    out = {f: int(getattr(s, f)) for f in STAT_FIELDS}
+    out.update({f: float(getattr(s, f)) for f in LEDGER_FIELDS})
+    return out
 
 
 def db_set_step(ctx, step):
@@ -359,6 +365,10 @@ def db_autotune(ctx, steps_per_trial):
     pe = C.c_int32()
     _check(ctx, _lib.db_autotune(ctx, int(steps_per_trial), C.byref(sk), C.byref(pe)))
     return float(sk.value), int(pe.value)
+
+
+def db_track_topology_energy(ctx, enable):
+    _check(ctx, _lib.db_track_topology_energy(ctx, int(enable)))
 
 
 def db_batch_create(replica_ctxs, hip_stream=None):

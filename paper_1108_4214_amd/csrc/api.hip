@@ -37,6 +37,7 @@ struct Pinned {
     unsigned long long stats[8];
     double energy[6];
     int total[4];
+    double ledger[12];             // energies before and after the sweep of the block
 };
 
 __global__ void k_report(const float* __restrict__ vmax2, int len, const int* __restrict__ err,
@@ -174,6 +175,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->err_d, 64);
     put(c->vmax2, 4 * (size_t)kMaxBlock * DB_VMAX_SPREAD);
     put(c->red, 8 * 6 * ((n + DB_BLOCK - 1) / DB_BLOCK + 1));
+    put(c->ledger_d, 8 * 16);
     put(c->dp, sizeof(Params));
     put(c->rep_d, sizeof(Box) * (size_t)std::max(1, c->nrep));
     int* t1 = nullptr;
@@ -935,7 +937,24 @@ static void record_sweep_stats(db_ctx* c) {
         c->stat_last[q] = (int64_t)pin->stats[q];
         c->stat_cum[q] += (int64_t)pin->stats[q];
     }
+    if (c->ledger) {
+        double du = 0.0;
+        for (int k = 1; k <= 4; ++k) du += pin->ledger[6 + k] - pin->ledger[k];
+        c->du_last = du;
+        c->du_cum += du;
+    }
     c->sweeps++;
+}
+
+// the sweep of a step, bracketed by potential-energy evaluations when the ledger is on
+static int run_sweep(db_ctx* c, int64_t step) {
+    if (c->ledger) launch_energy(c, c->ledger_d);
+    launch_sweep(c, step);
+    if (c->ledger) {
+        launch_energy(c, c->ledger_d + 6);
+        HIPCHK(c, hipMemcpyAsync(ext(c).pin->ledger, c->ledger_d, 96, hipMemcpyDeviceToHost, c->stream));
+    }
+    return DB_OK;
 }
 
 static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save) {
@@ -987,7 +1006,8 @@ int db_step(db_ctx* c, int64_t nsteps) {
         const bool guard = std::isfinite(skin) && len > 1;
         rebuild(c, permute, guard);
         if (sweep_due) {
-            launch_sweep(c, k0);
+            rc = run_sweep(c, k0);
+            if (rc) return rc;
             c->swept_step = k0;
         }
         launch_build_nlist(c);   // after the sweep: exclusions follow the new bonds
@@ -1051,7 +1071,8 @@ int db_sweep_now(db_ctx* c) {
     if (rc) return rc;
     if (c->swept_step == c->step) return fail(c, DB_ESTATE, "the sweep of step %lld was already done", (long long)c->step);
     rebuild(c, (c->rebuild_count++ % c->permute_every) == 0);
-    launch_sweep(c, c->step);
+    rc = run_sweep(c, c->step);
+    if (rc) return rc;
     Pinned* pin = ext(c).pin;
     HIPCHK(c, hipMemcpyAsync(pin->stats, c->sw.stats, 64, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1175,6 +1196,14 @@ int db_get_stats(db_ctx* c, db_stats* o) {
     o->steps = c->step;
     o->rebuilds = c->rebuilds;
     o->rollbacks = c->rollbacks;
+    o->du_topo_last = c->du_last;
+    o->du_topo_cum = c->du_cum;
+    return DB_OK;
+}
+
+int db_track_topology_energy(db_ctx* c, int enable) {
+    if (!c) return DB_EINVAL;
+    c->ledger = enable != 0;
     return DB_OK;
 }
 

@@ -187,6 +187,9 @@ struct db_ctx {
     int* err_d;          // device error word
     float* vmax2;        // [max block length][DB_VMAX_SPREAD] max |v|^2 after each step (float bits)
     double* red;         // reduction scratch
+    double* ledger_d;    // [12] energies before and after the last sweep
+    bool ledger;         // track the topology-energy ledger
+    double du_last, du_cum;
     int64_t* cnt64;      // small device counters
     void* pinned;        // pinned host staging
     int max_block;

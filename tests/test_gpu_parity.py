@@ -148,6 +148,32 @@ def test_sweep_dense_gas_with_bonds(seed):
     assert g.stats()["bonds_created"] > 50 and g.stats()["bonds_broken"] > 10
 
 
+def test_topology_energy_ledger():
+    """The ledger is the change of the potential energy across a sweep at fixed
+    positions: the oracle's energies before and after the same sweep."""
+    import paper_1108_4214_amd as pk
+    s = synth.random_gas(900, 11.0, seed=3, n_types=4, min_dist=0.85)
+    s.bonds = np.array([(2 * k, 2 * k + 1, 1, 1) for k in range(120)], dtype=np.int32)
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 0.7), ("create", 1, 3, 4, 1.5, 0.7),
+                                          ("break", 1, 1.2, 0.6), ("maxbond", 1, 0, 1)])
+    ff = synth.ForceField(bonds={1: (20.0, 1.0)})
+    g, o = both(s, ff, rules, seed=5)
+    pk.db_track_topology_energy(g.ctx, 1)
+    g.set_step(40)
+    o.set_step(40)
+    e0 = np.asarray(o.energy())
+    g.sweep_now()
+    o.sweep_now()
+    e1 = np.asarray(o.energy())
+    assert same_topology(g, o), topo_diff(g, o)
+    du = float(np.sum(e1[1:5] - e0[1:5]))
+    st = g.stats()
+    assert st["bonds_created"] > 10 and st["bonds_broken"] > 0
+    assert abs(du) > 1.0
+    assert abs(st["du_topo_last"] - du) <= 1e-9 * max(1.0, float(np.abs(e0[1:5]).sum()))
+    assert st["du_topo_cum"] == st["du_topo_last"]
+
+
 def test_sweep_kill_and_purge_on_stretched_duplexes():
     s = _duplex_system(40, 8, 0.1, seed=6, scale=0.35)
     rules = synth.rules_t2(p=0.5, every=1, r_kill=1.4)
