@@ -156,6 +156,88 @@ def run_batch(steps, warmup, precision=1):
             "speedup": seq_s / bat_s}
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_accuracy(ramp_steps=100000, ramp_every=5000, nve_steps=10000, nve_every=1000, warm_steps=2000):
+    """Mixed precision against FP64 on the GPU: force error on the 80,000-bead case, the
+    hybridized fraction along the whole 1M-bead temperature ramp, and NVE energy drift
+    on the 4M-bead stress case (energy minus the topology-energy ledger, which takes
+    out the jumps of bond events)."""
+    import numpy as np
+    import torch
+
+    import paper_1108_4214_amd as pk
+    import synth
+
+    out = {}
+    w = synth.c2()
+    f = {}
+    for prec in (0, 1):
+        g = pk.System(w.system.n, w.system.L, w.seed, prec).configure(w.system, w.ff, w.rules)
+        f[prec] = g.forces()
+        g.close()
+    out["c2_force_rel_l2_mixed_vs_fp64"] = float(np.linalg.norm(f[1] - f[0]) / np.linalg.norm(f[0]))
+    log(f"accuracy: 80k-bead force error {out['c2_force_rel_l2_mixed_vs_fp64']:.3e}")
+
+    w = synth.c3()
+    h0 = int(np.sum(w.system.bonds[:, 2] == synth.H_BOND))
+    curves = {}
+    for prec in (1, 0):
+        g = pk.System(w.system.n, w.system.L, w.seed, prec).configure(w.system, w.ff, w.rules)
+        pts = []
+        t0 = time.perf_counter()
+        for k in range(0, ramp_steps + 1, ramp_every):
+            if k:
+                g.step(ramp_every)
+            st = g.stats()
+            nh = h0 + st["cum_bonds_created"] - st["cum_bonds_killed"] - st["cum_bonds_broken"]
+            T = w.ff.T0 + (w.ff.T1 - w.ff.T0) * min(k, w.ff.ramp_steps) / w.ff.ramp_steps
+            pts.append([k, round(T, 4), nh / h0])
+            log(f"accuracy: ramp {'mixed' if prec else 'fp64'} step {k} T {T:.3f} hybridized {nh / h0:.4f}")
+        torch.cuda.synchronize()
+        curves["mixed" if prec else "fp64"] = {"points": pts, "seconds": time.perf_counter() - t0}
+        g.close()
+    out["c3_hybridized_fraction"] = {"columns": ["step", "T", "fraction"], **curves}
+
+    w = synth.c5()
+    # bond rules only (creation, conversion, kill, maxbond): with the angle and dihedral
+    # patterns, the strained rungs formed across the packed lattice drive both paths alike
+    # into the near-collinear configurations where the dihedral force diverges (~550 steps)
+    rules = synth.RuleSet(every=w.rules.every, rules=[r for r in w.rules.rules if r[0] not in ("angle", "dihedral")])
+    s5 = synth.System(L=w.system.L, x=w.system.x, v=w.system.v, type=w.system.type, reactive=w.system.reactive,
+                      bonds=w.system.bonds)
+    drift = {}
+    for prec in (1, 0):
+        g = pk.System(s5.n, s5.L, w.seed, prec).configure(s5, w.ff, rules)
+        # Langevin warm-up (T = 1, gamma = 1): the first sweeps bond most bases of the
+        # lattice and release the strain of the new angles as heat
+        pk.db_langevin(g.ctx, 1.0, 1.0, w.ff.dt)
+        g.step(warm_steps)
+        pk.db_langevin(g.ctx, 1.0, 0.0, w.ff.dt)
+        pk.db_track_topology_energy(g.ctx, 1)
+        du0 = g.stats()["du_topo_cum"]
+        e0 = g.energy()
+        c0 = float(np.sum(e0[:5]))
+        series = []
+        for k in range(nve_every, nve_steps + 1, nve_every):
+            g.step(nve_every)
+            e = g.energy()
+            st = g.stats()
+            series.append([k, (float(np.sum(e[:5])) - (st["du_topo_cum"] - du0) - c0) / abs(c0)])
+            log(f"accuracy: NVE {'mixed' if prec else 'fp64'} step {k} drift {series[-1][1]:.3e}")
+        drift["mixed" if prec else "fp64"] = {"relative_drift": series,
+                                              "bonds_created": g.stats()["cum_bonds_created"],
+                                              "bonds_converted": g.stats()["cum_bonds_converted"]}
+        g.close()
+    out["c5_nve_drift"] = {"columns": ["step", "(E - E0 - dU_topo) / |E0|"], "dt": w.ff.dt,
+                           "rules": "bond rules of the stress case (create, convert, kill, maxbond); no angle or "
+                                    "dihedral patterns",
+                           "warmup": f"{warm_steps} Langevin steps (T = 1, gamma = 1)", **drift}
+    return out
+
+
 def cpu_baseline(w, steps):
     import oracle
 
@@ -180,6 +262,8 @@ def main():
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--permute-every", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the replica-ladder measurement")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="also report mixed-vs-FP64 accuracy: force error, hybridized-fraction ramp, NVE drift")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the traffic counters)")
     args = ap.parse_args()
@@ -235,6 +319,8 @@ def main():
     }
     if args.copy_probe:
         copy_probe()
+    if args.accuracy:
+        line["accuracy"] = run_accuracy()
     if not args.no_batch:
         line["batch"] = run_batch(max(100, args.steps // 4), min(args.warmup, 50))
     if not args.no_cpu_baseline:

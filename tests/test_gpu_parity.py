@@ -382,6 +382,42 @@ def c3_workload():
     return synth.c3()
 
 
+# ---- full-size stress workload (4,000,000 beads, sweep every step, conversion) ----------
+
+@pytest.fixture(scope="module")
+def c5_workload():
+    return synth.c5()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_full_size_c5_forces(precision, tol, c5_workload):
+    w = c5_workload
+    g, o = both(w.system, w.ff, w.rules, seed=w.seed, precision=precision)
+    assert rel_l2(g.forces(), o.forces()) <= tol
+    g.close()
+
+
+def test_full_size_c5_steps_with_sweeps_and_conversion(c5_workload):
+    """Three NVE steps with a sweep before each: creations on the first (about 450k
+    bonds and 900k angles), then creations, breaks and conversions; FP64 trajectory
+    and every list against the oracle."""
+    w = c5_workload
+    g, o = both(w.system, w.ff, w.rules, seed=w.seed, precision=0)
+    g.step(3)
+    o.step(3)
+    assert same_topology(g, o)
+    assert _stats_equal(g, o)
+    st = g.stats()
+    assert st["cum_bonds_created"] > 400000
+    xg, vg = g.state()
+    xo, vo = o.state()
+    d = xg - xo
+    d -= w.system.L * np.round(d / w.system.L)
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-7
+    g.close()
+
+
 def test_dense_cluster_sweep():
     # a dense clump in a dilute box: crowded cells (about 40 beads each) next to empty ones
     rng = np.random.default_rng(31)
