@@ -46,6 +46,7 @@ def lib():
             "or_set_dihedrals": (C.c_int, [P, i64, P, P]),
             "or_generate_angles_dihedrals": (C.c_int, [P]),
             "or_pair_wca": (C.c_int, [P, d, d, d, C.c_int]),
+            "or_pair_dpd": (C.c_int, [P, d, d, d, C.c_int]),
             "or_bond_harmonic": (C.c_int, [P, i32, d, d]),
             "or_angle_harmonic": (C.c_int, [P, i32, d, d]),
             "or_dihedral_cosine": (C.c_int, [P, i32, d, d]),
@@ -157,7 +158,10 @@ class Oracle:
 
     def set_forcefield(self, ff):
         L = lib()
-        _chk(L.or_pair_wca(self._h, ff.eps, ff.sigma, ff.rc, ff.exclude_depth), "or_pair_wca")
+        if getattr(ff, "pair", "wca") == "dpd":
+            _chk(L.or_pair_dpd(self._h, ff.dpd_a, ff.dpd_gamma, ff.rc, ff.exclude_depth), "or_pair_dpd")
+        else:
+            _chk(L.or_pair_wca(self._h, ff.eps, ff.sigma, ff.rc, ff.exclude_depth), "or_pair_wca")
         for t, (K, r0) in ff.bonds.items():
             _chk(L.or_bond_harmonic(self._h, t, K, r0), "or_bond_harmonic")
         for t, (K, th0) in ff.angles.items():

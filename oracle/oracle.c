@@ -18,6 +18,7 @@
 #define KIND_LANGEVIN 0u
 #define KIND_CREATE 1u
 #define KIND_BREAK 2u
+#define KIND_DPD 3u
 
 enum { R_CREATE = 1, R_CREATEDIR, R_BREAK, R_KILL, R_CONVERT };
 
@@ -55,6 +56,8 @@ struct or_sys {
 
     /* force field */
     double eps, sig, rc; int excl_depth; int have_pair;
+    int pair_style;                 /* 0: WCA, 1: DPD */
+    double dpd_a, dpd_gamma;
     double bK[MAXT], bR0[MAXT]; int bset[MAXT];
     double aK[MAXT], aT0[MAXT]; int aset[MAXT];
     double dK[MAXT], dP0[MAXT]; int dset[MAXT];
@@ -97,6 +100,17 @@ static void draw(const or_sys* s, uint32_t a, uint32_t b, int64_t step, uint32_t
     uint32_t ctr[4] = {a, b, (uint32_t)st, ((uint32_t)(st >> 32) & 0x0FFFFFFFu) | (kind << 28)};
     uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
     or_philox4x32_10(ctr, key, out);
+}
+
+/* standard normal for the unordered pair {i, j}: Box-Muller (Box and Muller, 1958)
+ * on the first two 32-bit words, each mapped to (0,1) as (w + 1/2) / 2^32 */
+static double pair_gaussian(const or_sys* s, int i, int j, int64_t step) {
+    uint32_t lo = (uint32_t)(i < j ? i : j), hi = (uint32_t)(i < j ? j : i);
+    uint32_t w[4];
+    draw(s, lo, hi, step, KIND_DPD, w);
+    double u1 = ((double)w[0] + 0.5) * (1.0 / 4294967296.0);
+    double u2 = ((double)w[1] + 0.5) * (1.0 / 4294967296.0);
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
 
 /* uniform on [0,1) with 53 random bits, for the acceptance test u < p */
@@ -296,7 +310,14 @@ int or_graph_distance(or_sys* s, int32_t i, int32_t j) {
 /* parameters and rules */
 int or_pair_wca(or_sys* s, double eps, double sigma, double rc, int depth) {
     if (!(rc > 0) || depth < 0 || depth > 2) return -1;
-    s->eps = eps; s->sig = sigma; s->rc = rc; s->excl_depth = depth; s->have_pair = 1;
+    s->eps = eps; s->sig = sigma; s->rc = rc; s->excl_depth = depth; s->have_pair = 1; s->pair_style = 0;
+    return 0;
+}
+/* DPD pair force of section 3: conservative a w(r), dissipative and random parts
+ * with friction gamma and sigma = sqrt(2 T gamma) (T from the thermostat settings) */
+int or_pair_dpd(or_sys* s, double a, double gamma, double rc, int depth) {
+    if (!(rc > 0) || depth < 0 || depth > 2 || gamma < 0) return -1;
+    s->dpd_a = a; s->dpd_gamma = gamma; s->rc = rc; s->excl_depth = depth; s->have_pair = 1; s->pair_style = 1;
     return 0;
 }
 int or_bond_harmonic(or_sys* s, int32_t t, double K, double r0) {
@@ -550,6 +571,46 @@ static void wca_pair(or_sys* s, int i, int j, const double d[3], double r2, void
     c->vir += fr * r2;
 }
 
+/* DPD, section 3.  With r_ij = x_i - x_j, r = |r_ij|, e = r_ij / r and
+ * w = 1 - r / rc: F_i = -F_j = (F^C + F^D + F^R) e with F^C = a w,
+ * F^D = -gamma w^2 (e . v_ij), F^R = sigma w xi / sqrt(dt).  U = a rc w^2 / 2. */
+static void dpd_conservative_pair(or_sys* s, int i, int j, const double d[3], double r2, void* vctx) {
+    force_ctx* c = (force_ctx*)vctx;
+    if (excluded_pair(s, i, j)) return;
+    double r = sqrt(r2);
+    if (!(r > 0)) return;
+    double w = 1.0 - r / s->rc;
+    double fc = s->dpd_a * w;
+    c->upair += 0.5 * s->dpd_a * s->rc * w * w;
+    for (int k = 0; k < 3; ++k) {
+        double e = -d[k] / r;   /* d = x_j - x_i */
+        c->f[3 * i + k] += fc * e;
+        c->f[3 * j + k] -= fc * e;
+    }
+    c->vir += fc * r;
+}
+
+typedef struct { double* f; double sigma_over_sqrt_dt; int64_t step; } dpd_thermo_ctx;
+
+static void dpd_thermostat_pair(or_sys* s, int i, int j, const double d[3], double r2, void* vctx) {
+    dpd_thermo_ctx* c = (dpd_thermo_ctx*)vctx;
+    if (excluded_pair(s, i, j)) return;
+    double r = sqrt(r2);
+    if (!(r > 0)) return;
+    double w = 1.0 - r / s->rc;
+    double e[3], ev = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        e[k] = -d[k] / r;
+        ev += e[k] * (s->v[3 * i + k] - s->v[3 * j + k]);
+    }
+    double fd = -s->dpd_gamma * w * w * ev;
+    double fr = c->sigma_over_sqrt_dt * w * pair_gaussian(s, i, j, c->step);
+    for (int k = 0; k < 3; ++k) {
+        c->f[3 * i + k] += (fd + fr) * e[k];
+        c->f[3 * j + k] -= (fd + fr) * e[k];
+    }
+}
+
 static void bonded_forces(or_sys* s, force_ctx* c) {
     double* f = c->f;
     /* bonds: bead i feels the potential of the type it stores (t_ij), bead j that of t_ji */
@@ -648,7 +709,7 @@ static void conservative(or_sys* s, force_ctx* c) {
     build_adj(s);
     memset(c->f, 0, (size_t)s->n * 3 * sizeof(double));
     c->upair = c->ubond = c->uang = c->udih = c->vir = 0.0;
-    if (s->have_pair) for_pairs(s, s->rc, 0, wca_pair, c);
+    if (s->have_pair) for_pairs(s, s->rc, 0, s->pair_style == 1 ? dpd_conservative_pair : wca_pair, c);
     bonded_forces(s, c);
 }
 
@@ -679,10 +740,18 @@ static void add_langevin(or_sys* s, double* f, int64_t step) {
     }
 }
 
+/* the dissipative and random DPD forces of a step, added to f */
+static void add_dpd(or_sys* s, double* f, int64_t step) {
+    if (!s->have_pair || s->pair_style != 1 || s->dpd_gamma == 0.0) return;
+    dpd_thermo_ctx c = {f, sqrt(2.0 * temperature(s, step) * s->dpd_gamma) / sqrt(s->dt), step};
+    for_pairs(s, s->rc, 0, dpd_thermostat_pair, &c);
+}
+
 int or_energy(or_sys* s, double out[6]) {
     double* f = (double*)malloc((size_t)(s->n > 0 ? s->n : 1) * 3 * sizeof(double));
     force_ctx c = {f, 0, 0, 0, 0, 0};
     conservative(s, &c);
+    add_dpd(s, f, s->step);
     add_langevin(s, f, s->step);
     double ke = 0.0, hdt = 0.5 * s->dt;
     for (int i = 0; i < 3 * s->n; ++i) {
@@ -944,6 +1013,7 @@ int or_step(or_sys* s, int64_t nsteps) {
         }
         force_ctx c = {f, 0, 0, 0, 0, 0};
         conservative(s, &c);
+        add_dpd(s, f, s->step);
         add_langevin(s, f, s->step);
         for (int i = 0; i < 3 * s->n; ++i) {
             double vh = s->v[i] + hdt * f[i];

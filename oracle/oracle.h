@@ -44,6 +44,7 @@ int or_set_dihedrals(or_sys* s, int64_t nd, const int32_t* abcd, const int32_t* 
 int or_generate_angles_dihedrals(or_sys* s);
 
 int or_pair_wca(or_sys* s, double eps, double sigma, double rc, int exclude_depth);
+int or_pair_dpd(or_sys* s, double a, double gamma, double rc, int exclude_depth);
 int or_bond_harmonic(or_sys* s, int32_t type, double K, double r0);
 int or_angle_harmonic(or_sys* s, int32_t type, double K, double theta0);
 int or_dihedral_cosine(or_sys* s, int32_t type, double K, double phi0);

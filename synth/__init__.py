@@ -64,6 +64,9 @@ class ForceField:
     sigma: float = 1.0
     rc: float = 2.0 ** (1.0 / 6.0)
     exclude_depth: int = 1
+    pair: str = "wca"        # "wca" or "dpd" (soft conservative + dissipative + random pair forces)
+    dpd_a: float = 25.0
+    dpd_gamma: float = 4.5
     bonds: dict = dataclasses.field(default_factory=dict)      # type -> (K, r0)
     angles: dict = dataclasses.field(default_factory=dict)     # type -> (K, theta0)
     dihedrals: dict = dataclasses.field(default_factory=dict)  # type -> (K, phi0)
