@@ -114,6 +114,16 @@ int db_generate_angles_dihedrals(db_ctx* ctx);
 /* WCA U = 4 eps[(s/r)^12 - (s/r)^6] + eps for r < rc.  exclude_depth 1 removes
  * bonded pairs, 2 also pairs two bonds apart. */
 int db_pair_wca(db_ctx* ctx, double eps, double sigma, double rc, int exclude_depth);
+/* DPD (section 3), replacing WCA: for r = |r_ij| < rc, r_ij = x_i - x_j,
+ * e = r_ij / r, w = 1 - r / rc, bead i receives (F^C + F^D + F^R) e with
+ * F^C = a w, F^D = -gamma w^2 (e . v_ij), F^R = sigma w xi / sqrt(dt),
+ * sigma = sqrt(2 T gamma), xi a standard normal drawn per unordered pair and
+ * step (Philox stream tag 3, Box-Muller on its first two words); U = a rc w^2 / 2.
+ * T and dt come from db_langevin / db_temperature_ramp (whose own gamma may be
+ * 0, leaving the DPD pair thermostat alone).  exclude_depth as for WCA (the
+ * paper's DNA runs exclude beads fewer than three bonds apart: depth 2).
+ * gamma >= 0; gamma = 0 gives the conservative force only.  Box edge > 2 rc. */
+int db_pair_dpd(db_ctx* ctx, double a, double gamma, double rc, int exclude_depth);
 /* U = K (r - r0)^2; a bead feels the potential of the type it stores */
 int db_bond_harmonic(db_ctx* ctx, int32_t type, double K, double r0);
 /* U = K (theta - theta0)^2 */

@@ -26,7 +26,7 @@ MAX_BONDS_PER_BEAD, MAX_ANGLES_PER_BEAD, MAX_DIHEDRALS_PER_BEAD = 4, 12, 16
 EXPORTS = [
     "db_create", "db_workspace_bytes", "db_bind_workspace", "db_destroy", "db_last_error",
     "db_set_state", "db_set_reactive", "db_set_bonds", "db_set_angles", "db_set_dihedrals",
-    "db_generate_angles_dihedrals", "db_pair_wca", "db_bond_harmonic", "db_angle_harmonic",
+    "db_generate_angles_dihedrals", "db_pair_wca", "db_pair_dpd", "db_bond_harmonic", "db_angle_harmonic",
     "db_dihedral_cosine", "db_langevin", "db_temperature_ramp", "db_sweep_every", "db_bond_create",
     "db_bond_create_dir", "db_bond_break", "db_bond_kill", "db_bond_convert", "db_max_bonds",
     "db_angle_pattern", "db_dihedral_pattern", "db_step", "db_sweep_now", "db_forces", "db_energy",
@@ -76,6 +76,7 @@ _SIG = {
     "db_set_dihedrals": [_P, _i64, _P, _P],
     "db_generate_angles_dihedrals": [_P],
     "db_pair_wca": [_P, _d, _d, _d, _int],
+    "db_pair_dpd": [_P, _d, _d, _d, _int],
     "db_bond_harmonic": [_P, _i32, _d, _d],
     "db_angle_harmonic": [_P, _i32, _d, _d],
     "db_dihedral_cosine": [_P, _i32, _d, _d],
@@ -214,6 +215,10 @@ def db_generate_angles_dihedrals(ctx):
 
 def db_pair_wca(ctx, eps, sigma, rc, exclude_depth):
     _check(ctx, _lib.db_pair_wca(ctx, eps, sigma, rc, int(exclude_depth)))
+
+
+def db_pair_dpd(ctx, a, gamma, rc, exclude_depth):
+    _check(ctx, _lib.db_pair_dpd(ctx, a, gamma, rc, int(exclude_depth)))
 
 
 def db_bond_harmonic(ctx, t, K, r0):
@@ -415,7 +420,10 @@ class System:
         db_set_reactive(c, system.reactive)
         db_set_bonds(c, system.bonds)
         if ff is not None:
-            db_pair_wca(c, ff.eps, ff.sigma, ff.rc, ff.exclude_depth)
+            if getattr(ff, "pair", "wca") == "dpd":
+                db_pair_dpd(c, ff.dpd_a, ff.dpd_gamma, ff.rc, ff.exclude_depth)
+            else:
+                db_pair_wca(c, ff.eps, ff.sigma, ff.rc, ff.exclude_depth)
             for t, (K, r0) in ff.bonds.items():
                 db_bond_harmonic(c, t, K, r0)
             for t, (K, th0) in ff.angles.items():

@@ -145,6 +145,7 @@ static size_t layout(db_ctx* c, bool assign) {
         put(B.dt, DB_MAXD * n);
     }
     put(c->xnext, 32 * n);
+    put(c->vnext, 24 * n);
     put(c->xsave, 32 * n);
     put(c->vsave, 24 * n);
     SweepBuf& S = c->sw;
@@ -765,9 +766,29 @@ int db_pair_wca(db_ctx* c, double eps, double sigma, double rc, int depth) {
     if (2.0 * rc > c->L) return fail(c, DB_EINVAL, "box edge must exceed twice the pair cutoff");
     Params& P = c->hp;
     P.have_pair = 1;
+    P.pair_style = PAIR_WCA;
     P.eps = eps;
     P.sig2 = sigma * sigma;
     P.rc2 = rc * rc;
+    P.rc = rc;
+    P.inv_rc = 1.0 / rc;
+    P.excl_depth = depth;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_pair_dpd(db_ctx* c, double a, double gamma, double rc, int depth) {
+    if (!c || !(rc > 0) || !std::isfinite(a) || !(gamma >= 0) || !std::isfinite(gamma) || depth < 0 || depth > 2)
+        return DB_EINVAL;
+    if (2.0 * rc > c->L) return fail(c, DB_EINVAL, "box edge must exceed twice the pair cutoff");
+    Params& P = c->hp;
+    P.have_pair = 1;
+    P.pair_style = PAIR_DPD;
+    P.dpd_a = a;
+    P.dpd_gamma = gamma;
+    P.rc2 = rc * rc;
+    P.rc = rc;
+    P.inv_rc = 1.0 / rc;
     P.excl_depth = depth;
     c->params_dirty = true;
     return DB_OK;
@@ -1257,8 +1278,8 @@ int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* 
 // the force field, thermostat and rules two handles would run with
 static bool same_physics(const Params& a, const Params& b) {
     auto eq = [](const void* x, const void* y, size_t n) { return memcmp(x, y, n) == 0; };
-    if (a.have_pair != b.have_pair || a.excl_depth != b.excl_depth || a.eps != b.eps || a.sig2 != b.sig2 ||
-        a.rc2 != b.rc2)
+    if (a.have_pair != b.have_pair || a.excl_depth != b.excl_depth || a.pair_style != b.pair_style ||
+        a.eps != b.eps || a.sig2 != b.sig2 || a.rc2 != b.rc2 || a.dpd_a != b.dpd_a || a.dpd_gamma != b.dpd_gamma)
         return false;
     if (!eq(a.bK, b.bK, sizeof a.bK) || !eq(a.bR0, b.bR0, sizeof a.bR0) || !eq(a.aK, b.aK, sizeof a.aK) ||
         !eq(a.aT0, b.aT0, sizeof a.aT0) || !eq(a.dK, b.dK, sizeof a.dK) || !eq(a.dC0, b.dC0, sizeof a.dC0) ||

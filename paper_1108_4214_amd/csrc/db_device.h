@@ -45,6 +45,30 @@ __device__ __forceinline__ double pair_uniform(const Box& X, int ga, int gb, int
     return (double)bits * (1.0 / 9007199254740992.0);
 }
 
+// Standard normal for the unordered pair {ga, gb} of global ids in box X at a
+// step (DPD random force): the Box-Muller transform (Box and Muller, 1958) of the
+// first two words, each taken to (0, 1) as (w + 1/2) / 2^32.  Both beads of the
+// pair draw the same value.
+__device__ __forceinline__ uint4 pair_draw(const Box& X, int ga, int gb, int64_t step, uint32_t kind) {
+    ga -= X.gid_off;
+    gb -= X.gid_off;
+    return rng_draw(X, (uint32_t)(ga < gb ? ga : gb), (uint32_t)(ga < gb ? gb : ga), step, kind);
+}
+__device__ __forceinline__ double pair_gaussian(const Box& X, int ga, int gb, int64_t step) {
+    const uint4 w = pair_draw(X, ga, gb, step, RNG_DPD);
+    const double s32 = 1.0 / 4294967296.0;
+    const double u1 = ((double)w.x + 0.5) * s32, u2 = ((double)w.y + 0.5) * s32;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+// single-precision form for the mixed path: the hardware base-2 logarithm and the
+// hardware cosine, whose argument is in turns (cos 2 pi u)
+__device__ __forceinline__ float pair_gaussian_f(const Box& X, int ga, int gb, int64_t step) {
+    const uint4 w = pair_draw(X, ga, gb, step, RNG_DPD);
+    const float s32 = 1.0f / 4294967296.0f;
+    const float u1 = ((float)w.x + 0.5f) * s32, u2 = ((float)w.y + 0.5f) * s32;
+    return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1)) * __builtin_amdgcn_cosf(u2);
+}
+
 // both shifted values are formed and one is selected, so the compiler emits
 // selects rather than divergent branches; the result is bit-identical to the
 // branching form

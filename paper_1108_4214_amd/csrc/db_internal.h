@@ -15,7 +15,7 @@
 #define DB_MAXT 32
 #define DB_MAXRULES 32
 #define DB_BLOCK 256
-#define DB_NLCAP 64          // neighbour-list entries per bead
+#define DB_NLCAP 128         // neighbour-list entries per bead (DPD at density 3 lists ~50-80)
 #define DB_MAXU 8            // bonded halo entries per bead (codes hold 3-bit indices)
 #define DB_HALO_OVF 255      // halo marker: more than DB_MAXU distinct bonded partners
 #define DB_VMAX_SPREAD 64    // words per step over which the speed maxima are spread
@@ -25,7 +25,10 @@ namespace db {
 enum RuleKind { RK_CREATE = 1, RK_CREATEDIR = 2, RK_BREAK = 3, RK_KILL = 4, RK_CONVERT = 5 };
 
 // random-number stream tags (top 4 bits of the last counter word)
-enum RngKind : uint32_t { RNG_LANGEVIN = 0u, RNG_CREATE = 1u, RNG_BREAK = 2u };
+enum RngKind : uint32_t { RNG_LANGEVIN = 0u, RNG_CREATE = 1u, RNG_BREAK = 2u, RNG_DPD = 3u };
+
+// pair force styles
+enum PairStyle { PAIR_WCA = 0, PAIR_DPD = 1 };
 
 // counters of one sweep (SweepBuf::stats)
 enum { ST_CREATED = 0, ST_BROKEN, ST_KILLED, ST_CONVERTED, ST_ANG_NEW, ST_ANG_DEL, ST_DIH_NEW, ST_DIH_DEL };
@@ -64,9 +67,11 @@ struct Params {
     Box box;             // the box of a single system
     int nrep;            // replicas in a batch (0: single system)
     const Box* rep;      // [nrep] device table of a batch
-    // WCA
-    int have_pair, excl_depth;
+    // pair force: WCA, or DPD (conservative a w, dissipative -gamma w^2 (e . v_ij),
+    // random sigma w xi / sqrt(dt), w = 1 - r / rc)
+    int have_pair, excl_depth, pair_style;
     double eps, sig2, rc2;
+    double rc, inv_rc, dpd_a, dpd_gamma;
     double rnl2;         // neighbour-list cutoff squared (pair cutoff + skin)
     // bonded
     double bK[DB_MAXT], bR0[DB_MAXT];
@@ -169,6 +174,7 @@ struct db_ctx {
     db::Bank bank[2];
     int cur;
     double4* xnext;      // double buffer of positions for the step kernel
+    double* vnext;       // double buffer of velocities (DPD: the step reads neighbour velocities)
     double4* xsave;      // state at block start (rollback)
     double* vsave;
     db::SweepBuf sw;

@@ -1,8 +1,9 @@
 // Per-step force pass: one thread per bead gathers its own force (Newton's third
 // law is not used for bonded terms: every bead evaluates each bond, angle and
 // dihedral it takes part in, as in the paper's directional-bond storage, section 2
-// and appendix), so nothing is accumulated across threads.  Pair forces: WCA over
-// the 27 surrounding cells of the bead's current position.  Bonded: harmonic
+// and appendix), so nothing is accumulated across threads.  Pair forces: WCA, or
+// the DPD conservative, dissipative and random forces (section 3), from the
+// Verlet list.  Bonded: harmonic
 // bonds with the type the bead stores, harmonic angles, cosine dihedrals
 // (section 3 potentials).  Then the Langevin force and the velocity-Verlet
 // update of the bead, written to a second position buffer.
@@ -124,10 +125,43 @@ __device__ __forceinline__ void pair_term(const Params& P, const Box& X, const d
     }
 }
 
+// DPD pair (i, j) as seen by bead i (section 3).  With d = x_j - x_i (minimum
+// image), r = |d|, e = -d / r (from j to i) and w = 1 - r / rc, bead i receives
+// (F^C + F^D + F^R) e with F^C = a w, F^D = -gamma w^2 (e . v_ij) and
+// F^R = sigma w xi / sqrt(dt); dsig = sigma / sqrt(dt).  Bead j forms the same
+// three terms from -d and -v_ij and the pair's single Gaussian, so the two forces
+// cancel exactly.  Without THERMO only the conservative part is formed.
+template <typename R, bool THERMO, bool ENERGY>
+__device__ __forceinline__ void dpd_pair(const Params& P, const Box& X, const double4& xi, const double4& xj,
+                                         R rx, R ry, R rz, R r2, double dvx, double dvy, double dvz, int64_t step,
+                                         double dsig, Acc<R>& a) {
+    const R r = r_sqrt<R>(r2);
+    const R ir = r_rcp<R>(r);
+    const R w = (R)1.0 - r * (R)P.inv_rc;
+    R f = (R)P.dpd_a * w;
+    if (ENERGY) {
+        a.e_pair += 0.25 * (double)((R)P.dpd_a * (R)P.rc * w * w);   // half of a rc w^2 / 2
+        a.vir += 0.5 * (double)(f * r);
+    }
+    if (THERMO) {
+        const R ev = -(((R)dvx * rx + (R)dvy * ry) + (R)dvz * rz) * ir;   // e . v_ij
+        R xg;
+        if constexpr (sizeof(R) == 4) xg = pair_gaussian_f(X, meta_gid(xi), meta_gid(xj), step);
+        else xg = pair_gaussian(X, meta_gid(xi), meta_gid(xj), step);
+        f += -(R)P.dpd_gamma * w * w * ev + (R)dsig * w * xg;
+    }
+    const R fi = f * ir;
+    a.fx -= (double)(fi * rx);
+    a.fy -= (double)(fi * ry);
+    a.fz -= (double)(fi * rz);
+}
+
+// pair forces over the 27 cells (energy evaluation); vi and dsig feed the DPD
+// thermostat terms when the DPD friction is not zero
 template <typename R, int MODE>
 __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const int* __restrict__ cstart,
                             const int* __restrict__ clist, int i, const double4& xi, int nb, int p0, int p1, int p2,
-                            int p3, Acc<R>& a) {
+                            int p3, double vix, double viy, double viz, int64_t step, double dsig, Acc<R>& a) {
     const int nc = X.nc;
     int cx = cell_coord(xi.x, X.cell_scale, nc);
     int cy = cell_coord(xi.y, X.cell_scale, nc);
@@ -164,7 +198,18 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
                     if (!(r2 < rc2)) continue;
                     if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) continue;
                     if (P.excl_depth >= 2 && two_bonds_apart(B, P.n, j, nb, p0, p1, p2, p3)) continue;
-                    pair_term<R, MODE>(P, X, xi, xj, a);
+                    if (P.pair_style == PAIR_DPD) {
+                        const int n = P.n;
+                        if (P.dpd_gamma != 0.0)
+                            dpd_pair<R, true, MODE == MODE_ENERGY>(P, X, xi, xj, rx, ry, rz, r2, vix - B.v[j],
+                                                                   viy - B.v[n + j], viz - B.v[2 * n + j], step,
+                                                                   dsig, a);
+                        else
+                            dpd_pair<R, false, MODE == MODE_ENERGY>(P, X, xi, xj, rx, ry, rz, r2, 0, 0, 0, 0, 0,
+                                                                    a);
+                    } else {
+                        pair_term<R, MODE>(P, X, xi, xj, a);
+                    }
                 }
             }
         }
@@ -241,6 +286,41 @@ __device__ __forceinline__ void list_pair_forces(const Params& P, const Box& X, 
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (k0 + q < m) pair_one<R>(P, X, xi, xj[q], rc2, a);
+    }
+}
+
+// DPD pair forces from the Verlet list; THERMO adds the dissipative and random
+// parts, which read the neighbours' velocities (from the step's input buffer)
+template <typename R, bool THERMO>
+__device__ __forceinline__ void list_pair_dpd(const Params& P, const Box& X, const Bank& B, const NList& NL, int i,
+                                              const double4& xi, double vix, double viy, double viz, int64_t step,
+                                              double dsig, Acc<R>& a) {
+    const int n = P.n;
+    const R rc2 = (R)P.rc2;
+    const int m = NL.cnt[i];
+    for (int k0 = 0; k0 < m; k0 += 4) {
+        int j[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) j[q] = (k0 + q < m) ? NL.nl[(k0 + q) * n + i] : i;
+        double4 xj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xj[q] = B.x[j[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const R rx = (R)near_image(xj[q].x - xi.x, X);
+            const R ry = (R)near_image(xj[q].y - xi.y, X);
+            const R rz = (R)near_image(xj[q].z - xi.z, X);
+            const R r2 = (rx * rx + ry * ry) + rz * rz;
+            if ((k0 + q < m) & (r2 < rc2)) {
+                if (THERMO) {
+                    const int jq = j[q];
+                    dpd_pair<R, true, false>(P, X, xi, xj[q], rx, ry, rz, r2, vix - B.v[jq], viy - B.v[n + jq],
+                                             viz - B.v[2 * n + jq], step, dsig, a);
+                } else {
+                    dpd_pair<R, false, false>(P, X, xi, xj[q], rx, ry, rz, r2, 0, 0, 0, 0, 0, a);
+                }
+            }
+        }
     }
 }
 
@@ -570,12 +650,15 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// pref: sqrt(24 gamma T / dt) of a single system (from the host); a batch
-// forms it per bead from the replica's temperature
-template <typename R, int MODE, bool BATCH>
+// pref: sqrt(24 gamma T / dt) of a single system (from the host), dsig: the DPD
+// sigma / sqrt(dt) = sqrt(2 T gamma_DPD) / sqrt(dt); a batch forms both per bead
+// from the replica's temperature.  PAIR selects the pair style at compile time.
+// The new velocities go to vout, which is B.v itself unless the DPD thermostat
+// reads the neighbours' input velocities.
+template <typename R, int MODE, bool BATCH, int PAIR>
 __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
-                                                    double4* __restrict__ xout, int64_t step, double pref,
-                                                    unsigned int* __restrict__ vmax2_slot,
+                                                    double4* __restrict__ xout, double* vout, int64_t step,
+                                                    double pref, double dsig, unsigned int* __restrict__ vmax2_slot,
                                                     double* __restrict__ fout, int* __restrict__ err,
                                                     double4* __restrict__ xsave, double* __restrict__ vsave) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
@@ -602,7 +685,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
             angle_terms<R, MODE_STEP>(P, X, C, B, i, B.na[i], a);
             dihedral_terms<R, MODE_STEP>(P, X, C, B, i, B.nd[i], a);
         }
-        if (P.have_pair) list_pair_forces<R>(P, X, B, NL, i, xi, a);
+        if (PAIR == PAIR_DPD) {
+            if (MODE == MODE_STEP && P.dpd_gamma != 0.0) {
+                if (BATCH) dsig = sqrt(2.0 * box_temperature(X, step) * P.dpd_gamma) / sqrt(P.dt);
+                list_pair_dpd<R, true>(P, X, B, NL, i, xi, B.v[i], B.v[n + i], B.v[2 * n + i], step, dsig, a);
+            } else {
+                list_pair_dpd<R, false>(P, X, B, NL, i, xi, 0, 0, 0, 0, 0, a);
+            }
+        } else if (P.have_pair) {
+            list_pair_forces<R>(P, X, B, NL, i, xi, a);
+        }
         if (MODE == MODE_FORCES) {
             int g = meta_gid(xi);
             fout[3 * (size_t)g] = a.fx;
@@ -644,9 +736,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
             bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
             if (bad) atomicOr(err, ERR_NONFINITE);
             xout[i] = xo;
-            B.v[i] = vx;
-            B.v[n + i] = vy;
-            B.v[2 * n + i] = vz;
+            vout[i] = vx;
+            vout[n + i] = vy;
+            vout[2 * n + i] = vz;
         }
     }
     if (MODE == MODE_STEP) {
@@ -686,11 +778,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ 
         int p1 = nb > 1 ? B.bp[n + i] : -1;
         int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
         int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
-        if (P.have_pair) pair_forces<R, MODE_ENERGY>(P, X, B, cstart, clist, i, xi, nb, p0, p1, p2, p3, a);
+        double vx = B.v[i], vy = B.v[n + i], vz = B.v[2 * n + i];
+        const double dsig = P.pair_style == PAIR_DPD && P.dpd_gamma != 0.0
+                                ? sqrt(2.0 * box_temperature(X, step) * P.dpd_gamma) / sqrt(P.dt)
+                                : 0.0;
+        if (P.have_pair)
+            pair_forces<R, MODE_ENERGY>(P, X, B, cstart, clist, i, xi, nb, p0, p1, p2, p3, vx, vy, vz, step, dsig,
+                                        a);
         bond_terms<R, MODE_ENERGY>(P, X, C, B, i, xi, nb, a);
         angle_terms<R, MODE_ENERGY>(P, X, C, B, i, B.na[i], a);
         dihedral_terms<R, MODE_ENERGY>(P, X, C, B, i, B.nd[i], a);
-        double vx = B.v[i], vy = B.v[n + i], vz = B.v[2 * n + i];
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
             double pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
@@ -750,53 +847,83 @@ void launch_build_nlist(db_ctx* c) {
                            c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d);
 }
 
-// sqrt(24 gamma T(step) / dt), the amplitude of the uniform Langevin noise of a single system
-static double langevin_prefactor(const Params& P, int64_t step) {
-    if (P.gamma == 0.0) return 0.0;
+// temperature of the single system's box at a step
+static double host_temperature(const Params& P, int64_t step) {
     const Box& X = P.box;
-    double T = X.T0;
-    if (X.ramp > 0) {
-        int64_t k = step < X.ramp ? step : X.ramp;
-        T = X.T0 + (X.T1 - X.T0) * (double)k / (double)X.ramp;
-    }
-    return sqrt(24.0 * P.gamma * T / P.dt);
+    if (X.ramp <= 0) return X.T0;
+    int64_t k = step < X.ramp ? step : X.ramp;
+    return X.T0 + (X.T1 - X.T0) * (double)k / (double)X.ramp;
 }
 
-template <typename R, int MODE, bool BATCH>
-static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, int64_t step, double pref, unsigned* vm,
-                               double* f, bool save) {
-    hipLaunchKernelGGL((k_step<R, MODE, BATCH>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
-                       c->nlist, c->halo, xout, step, pref, vm, f, c->err_d, save ? c->xsave : nullptr,
-                       save ? c->vsave : nullptr);
+// sqrt(24 gamma T / dt), the amplitude of the uniform Langevin noise of a single system
+static double langevin_prefactor(const Params& P, int64_t step) {
+    if (P.gamma == 0.0) return 0.0;
+    return sqrt(24.0 * P.gamma * host_temperature(P, step) / P.dt);
+}
+
+// sigma / sqrt(dt) = sqrt(2 T gamma_DPD) / sqrt(dt) of a single system
+static double dpd_sigma(const Params& P, int64_t step) {
+    if (P.pair_style != PAIR_DPD || P.dpd_gamma == 0.0) return 0.0;
+    return sqrt(2.0 * host_temperature(P, step) * P.dpd_gamma) / sqrt(P.dt);
+}
+
+// the DPD thermostat reads the neighbours' velocities: the step writes the new
+// ones to the second buffer
+static bool velocity_double_buffer(const db_ctx* c) {
+    return c->hp.have_pair && c->hp.pair_style == PAIR_DPD && c->hp.dpd_gamma != 0.0;
+}
+
+template <typename R, int MODE, bool BATCH, int PAIR>
+static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
+                               double dsig, unsigned* vm, double* f, bool save) {
+    hipLaunchKernelGGL((k_step<R, MODE, BATCH, PAIR>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                       B, c->nlist, c->halo, xout, vout, step, pref, dsig, vm, f, c->err_d,
+                       save ? c->xsave : nullptr, save ? c->vsave : nullptr);
+}
+
+template <int MODE, int PAIR>
+static void launch_step_pair(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
+                             double dsig, unsigned* vm, double* f, bool save) {
+    const bool batch = c->nrep > 0;
+    if (c->precision == DB_MIXED) {
+        if (batch) launch_step_kernel<float, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        else launch_step_kernel<float, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+    } else {
+        if (batch) launch_step_kernel<double, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        else launch_step_kernel<double, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+    }
 }
 
 template <int MODE>
-static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, int64_t step, double pref, unsigned* vm,
-                            double* f, bool save = false) {
-    const bool batch = c->nrep > 0;
-    if (c->precision == DB_MIXED) {
-        if (batch) launch_step_kernel<float, MODE, true>(c, B, xout, step, pref, vm, f, save);
-        else launch_step_kernel<float, MODE, false>(c, B, xout, step, pref, vm, f, save);
-    } else {
-        if (batch) launch_step_kernel<double, MODE, true>(c, B, xout, step, pref, vm, f, save);
-        else launch_step_kernel<double, MODE, false>(c, B, xout, step, pref, vm, f, save);
-    }
+static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
+                            double dsig, unsigned* vm, double* f, bool save = false) {
+    if (c->hp.have_pair && c->hp.pair_style == PAIR_DPD)
+        launch_step_pair<MODE, PAIR_DPD>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+    else
+        launch_step_pair<MODE, PAIR_WCA>(c, B, xout, vout, step, pref, dsig, vm, f, save);
 }
 
 void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
     if (c->n == 0) return;
     const double pref = langevin_prefactor(c->hp, step);
+    const double dsig = dpd_sigma(c->hp, step);
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
-    launch_step_any<MODE_STEP>(c, B, c->xnext, step, pref, vm, nullptr, save);
+    const bool vbuf = velocity_double_buffer(c);
+    launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;
+    if (vbuf) {
+        double* u = B.v;
+        B.v = c->vnext;
+        c->vnext = u;
+    }
 }
 
 void launch_forces(db_ctx* c, double* f) {
     if (c->n == 0) return;
-    launch_step_any<MODE_FORCES>(c, c->bank[c->cur], nullptr, 0, 0.0, nullptr, f);
+    launch_step_any<MODE_FORCES>(c, c->bank[c->cur], nullptr, nullptr, 0, 0.0, 0.0, nullptr, f);
 }
 
 template <typename R, bool BATCH>

@@ -24,8 +24,10 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-# bead types (section 3: A, T, C, G = 1..4); 5 = backbone bead of the 2-bead model
+# bead types (section 3: A, T, C, G = 1..4); 5 = backbone bead of the 2-bead model,
+# 6 = DPD solvent bead
 A, T, C, G, P = 1, 2, 3, 4, 5
+SOLVENT = 6
 COMPLEMENT = {A: T, T: A, C: G, G: C}
 # bond types
 H_BOND, BB_3P, BB_5P, PB_BOND, WEAK = 1, 2, 3, 4, 5
@@ -137,6 +139,16 @@ def ff_t2(T0=1.0, T1=1.0, ramp_steps=0, gamma=1.0, dt=0.005, weak=False) -> Forc
         ff.bonds[WEAK] = (10.0, 1.5)
     ff.angles = {1: (10.0, math.pi)}
     ff.dihedrals = {1: (5.0, 0.0)}
+    return ff
+
+
+def ff_dpd(T=1.0, gamma_dpd=100.0, dt=0.01, a=25.0) -> ForceField:
+    """The 2-bead model's bonded terms in the paper's DPD setting (section 3):
+    a = 25, rc = 1, pair interactions off below three bonds apart, dt = 0.01, the
+    DPD pair thermostat alone (no Langevin force); gamma_dpd = 100 is the
+    friction read from the paper's stated value (its units are the friction's)."""
+    ff = ff_t2(T0=T, T1=T, gamma=0.0, dt=dt)
+    ff.pair, ff.dpd_a, ff.dpd_gamma, ff.rc, ff.exclude_depth = "dpd", a, gamma_dpd, 1.0, 2
     return ff
 
 
@@ -392,6 +404,35 @@ def duplex_box(n_duplex, n_bp, rho, seed_w, seed_d, T=1.0) -> System:
     rng = np.random.default_rng(seed_w)
     b = pack_duplexes([n_bp] * n_duplex, L, rng)
     return _finish(b, L, np.random.default_rng(seed_d), T)
+
+
+def dpd_solution(n_duplex, n_bp, n_total, rho=3.0, seed_w=9, seed_d=19, T=1.0) -> System:
+    """Duplexes of the 2-bead model in explicit DPD solvent at number density rho
+    (the paper's DNA runs use 3): the duplexes are packed as in duplex_box, the
+    remaining n_total - 4 n_bp n_duplex beads are solvent (type 6, not reactive)
+    at uniform random positions (the DPD pair force is soft, so overlaps are
+    harmless)."""
+    n_dna = 4 * n_bp * n_duplex
+    if n_total < n_dna:
+        raise ValueError("n_total below the duplex beads")
+    L = (n_total / rho) ** (1.0 / 3.0)
+    rng = np.random.default_rng(seed_w)
+    b = pack_duplexes([n_bp] * n_duplex, L, rng) if n_duplex else _Builder()
+    for p in rng.uniform(0.0, L, size=(n_total - n_dna, 3)):
+        b.add(p, SOLVENT)
+    react = np.zeros(n_total, dtype=np.uint8)
+    react[:n_dna] = 1
+    return _finish(b, L, np.random.default_rng(seed_d), T, reactive=react)
+
+
+def dpd_c3(seed_w=23, seed_d=33) -> Workload:
+    """1,000,000 beads at density 3 (the paper's DPD solvent density): 2,500
+    hybridized 20-bp duplexes of the 2-bead model (200,000 beads) in 800,000
+    solvent beads; DPD a = 25, friction 100, T = 1, dt = 0.01; hybridization
+    sweep every 10 steps."""
+    s = dpd_solution(2500, 20, 1_000_000, 3.0, seed_w, seed_d)
+    return Workload("dpd: 2500 x 20-bp duplexes in DPD solvent, 1000000 beads, rho=3", s, ff_dpd(),
+                    rules_t2(p=0.5, every=10), 10000, seed_d)
 
 
 def c2(seed_w=2, seed_d=12) -> Workload:

@@ -89,13 +89,14 @@ def test_full_pair_force_conserves_momentum():
     assert np.abs(v.sum(axis=0)).max() < 1e-9
 
 
-@pytest.mark.parametrize("dt", [0.01, 0.005])
-def test_thermostat_holds_the_temperature(dt):
+@pytest.mark.parametrize("gamma,dt", [(4.5, 0.01), (4.5, 0.005), (100.0, 0.01)])
+def test_thermostat_holds_the_temperature(gamma, dt):
     """Fluctuation-dissipation: starting hot (T = 3), the fluid relaxes to the set
     T = 1; the mean kinetic energy per bead is 3T/2 within 3 % (dt = 0.01 is the
-    paper's step; halving it must not move the temperature)."""
+    paper's step; halving it must not move the temperature; friction 100 is the
+    paper's stated value)."""
     s = _fluid(T=3.0)
-    o = oracle.Oracle.from_system(s, _dpd_ff(dt=dt), synth.RuleSet(every=0), seed=11)
+    o = oracle.Oracle.from_system(s, _dpd_ff(gamma=gamma, dt=dt), synth.RuleSet(every=0), seed=11)
     o.step(int(round(8.0 / dt)))
     ke = []
     for _ in range(40):
