@@ -156,6 +156,31 @@ def run_batch(steps, warmup, precision=1):
             "speedup": seq_s / bat_s}
 
 
+def run_dpd(steps, warmup):
+    """The paper's own dynamics (section 3): DPD conservative, dissipative and
+    random pair forces at density 3 with the hybridization sweep, mixed and FP64."""
+    import synth
+
+    w = synth.dpd_c3()
+    mixed = run_gpu(w, 1, steps, warmup)
+    fp64 = run_gpu(w, 0, steps, warmup)
+    b, a, d = mixed["topology_per_bead"]
+    kernel_bytes, _ = algorithmic_bytes_per_bead_step(b, a, d, w.rules.every)
+    n = w.system.n
+
+    def frac(r):
+        return kernel_bytes * n / (r["step_kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS if r["step_kernel_us"] > 0 else None
+
+    return {"workload": "2500 x 20-bp duplexes (2-bead model, 200000 beads) in 800000 DPD solvent beads, "
+                        "1000000 beads, rho=3, a=25, gamma=100, T=1, dt=0.01, sweep every 10 steps",
+            "value": mixed["bead_steps_per_s"], "unit": "bead-steps/s", "ms_per_step": mixed["ms_per_step"],
+            "step_kernel_us": mixed["step_kernel_us"], "hbm_roofline_frac": frac(mixed),
+            "bytes_per_bead_step": kernel_bytes,
+            "fp64": {"value": fp64["bead_steps_per_s"], "ms_per_step": fp64["ms_per_step"],
+                     "step_kernel_us": fp64["step_kernel_us"], "hbm_roofline_frac": frac(fp64)},
+            "mixed_detail": mixed, "fp64_detail": fp64}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -262,6 +287,7 @@ def main():
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--permute-every", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the replica-ladder measurement")
+    ap.add_argument("--no-dpd", action="store_true", help="skip the DPD-solution measurement")
     ap.add_argument("--accuracy", action="store_true",
                     help="also report mixed-vs-FP64 accuracy: force error, hybridized-fraction ramp, NVE drift")
     ap.add_argument("--copy-probe", action="store_true",
@@ -323,6 +349,8 @@ def main():
         line["accuracy"] = run_accuracy()
     if not args.no_batch:
         line["batch"] = run_batch(max(100, args.steps // 4), min(args.warmup, 50))
+    if not args.no_dpd:
+        line["dpd"] = run_dpd(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -8,9 +8,13 @@
 // and then runs up to `rebuild_interval` fused step kernels without rebuilding.
 // Each step kernel records the largest speed; after the block the host bounds
 // the largest displacement by the sum of dt * max speed.  If that bound exceeds
-// the skin (cell edge minus pair cutoff) some pair could have been missed, so
-// the block's positions and velocities are restored and the block is re-run
-// with a fresh cell list at every step.  The interval adapts to the speeds seen.
+// half the skin (list cutoff minus pair cutoff) some pair could have been
+// missed, so the block's positions and velocities are restored and the block is
+// re-run with a fresh list at every step.  The interval adapts to the speeds
+// seen.  With DPD the pair friction decorrelates velocities within a few steps,
+// so the motion is diffusive and the speed bound far too cautious: there the
+// step kernels record the largest displacement from the block's first position
+// itself, which is the exact test, and the interval follows its growth.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -33,7 +37,7 @@ const double kSkinDefault = 0.55;
 struct Pinned {
     int err;
     int pad;
-    float vmax2[kMaxBlock];        // largest |v|^2 of each step of the block
+    float vmax2[kMaxBlock];        // largest |v|^2 (DPD: squared displacement) after each step of the block
     unsigned long long stats[8];
     double energy[6];
     int total[4];
@@ -978,7 +982,7 @@ static int run_sweep(db_ctx* c, int64_t step) {
     return DB_OK;
 }
 
-static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save) {
+static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save, bool ref) {
     if (c->profile) {
         if ((size_t)c->ev_used + 2 > c->ev_pool.size()) {
             for (int k = 0; k < 2 * kMaxBlock; ++k) {
@@ -988,11 +992,11 @@ static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save) {
             }
         }
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
-        launch_step(c, step, slot, save);
+        launch_step(c, step, slot, save, ref);
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     } else {
-        launch_step(c, step, slot, save);
+        launch_step(c, step, slot, save, ref);
     }
     return DB_OK;
 }
@@ -1017,6 +1021,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
     const double dt = c->hp.dt;
     const int every = c->hp.every;
     const double skin = skin_of(c);
+    const bool track = c->hp.have_pair && c->hp.pair_style == PAIR_DPD;   // displacement, not speed
     hipStream_t s = c->stream;
     while (nsteps > 0) {
         const int64_t k0 = c->step;
@@ -1036,7 +1041,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
         // the block's input state is kept for a re-run: by the reorder, or else by
         // the first step kernel of the block
         for (int64_t q = 0; q < len; ++q) {
-            rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0);
+            rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0, guard && q > 0);
             if (rc) return rc;
         }
         hipLaunchKernelGGL(k_report, dim3(1), dim3(kMaxBlock), 0, s, c->vmax2, (int)len, c->err_d, c->sw.stats,
@@ -1051,11 +1056,18 @@ int db_step(db_ctx* c, int64_t nsteps) {
         X.host_valid = false;
         rc = check_device_error(c);
         if (rc) return rc;
-        double bound = 0.0, vmax = 0.0;
+        // bound: how far any bead may be from where the list was built, at the
+        // input of the block's last step
+        double bound = 0.0, vmax = 0.0, dlast = 0.0;
         for (int64_t q = 0; q < len; ++q) {
             double v = std::sqrt((double)pin->vmax2[q]);
-            vmax = std::max(vmax, v);
-            if (q + 1 < len) bound += dt * v;
+            if (track) {
+                if (q + 1 < len) bound = std::max(bound, v);
+                dlast = v;
+            } else {
+                vmax = std::max(vmax, v);
+                if (q + 1 < len) bound += dt * v;
+            }
         }
         if (guard && bound > skin) {
             // some bead may have left the reach of the cell list: redo with a fresh list every step
@@ -1073,6 +1085,12 @@ int db_step(db_ctx* c, int64_t nsteps) {
             rc = check_device_error(c);
             if (rc) return rc;
             c->rebuild_interval = std::max<int>(1, (int)(len / 2));
+        } else if (track && std::isfinite(skin)) {
+            // extrapolate the largest displacement linearly in time from the block's
+            // end (exact for ballistic motion, cautious for diffusive motion, so the
+            // interval keeps growing while the test passes)
+            int want = dlast > 0 ? (int)std::floor(0.8 * skin * (double)len / dlast) + 1 : kMaxBlock;
+            c->rebuild_interval = std::max(1, std::min(kMaxBlock, want));
         } else if (std::isfinite(skin) && vmax > 0) {
             int want = (int)std::floor(0.8 * skin / (dt * vmax));
             c->rebuild_interval = std::max(1, std::min(kMaxBlock, want));

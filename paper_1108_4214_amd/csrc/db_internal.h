@@ -230,7 +230,9 @@ void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, 
 
 // kernels_force.hip
 void launch_build_nlist(db_ctx* c);                  // Verlet list from the current cell list
-void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save = false);   // save: keep the input x, v
+// save: keep the input x, v (the block's reference state); ref: that state is in
+// the rollback buffers (steps after the block's first)
+void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save = false, bool ref = false);
 void launch_forces(db_ctx* c, double* f_gid_order);
 void launch_energy(db_ctx* c, double* out6_device);
 

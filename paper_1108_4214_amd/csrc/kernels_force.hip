@@ -236,10 +236,28 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     const int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
     const int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
     const Box& X = box_of<BATCH>(P, meta_word(xi));
+    // the beads two bonds away (partners of partners), gathered once per bead, so
+    // that testing a candidate compares registers instead of re-reading the
+    // partners' tables; -1 marks an empty entry
+    static_assert(DB_MAXB == 4, "the exclusion test holds four partners");
+    const bool depth2 = P.excl_depth >= 2;
+    const int pp[DB_MAXB] = {p0, p1, p2, p3};
+    int two[DB_MAXB * DB_MAXB];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        const int nq = (depth2 && k < nb) ? B.nb[pp[k]] : 0;
+#pragma unroll
+        for (int m = 0; m < DB_MAXB; ++m) two[k * DB_MAXB + m] = m < nq ? B.bp[m * n + pp[k]] : -1;
+    }
     int cnt = 0;
     scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, float) {
         if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
-        if (P.excl_depth >= 2 && two_bonds_apart(B, n, j, nb, p0, p1, p2, p3)) return;
+        if (depth2 && nb > 0) {
+            bool ex = false;
+#pragma unroll
+            for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) ex |= two[k] == j;
+            if (ex) return;
+        }
         if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
         ++cnt;
     });
@@ -654,13 +672,17 @@ __device__ __forceinline__ double wave_max(double v) {
 // sigma / sqrt(dt) = sqrt(2 T gamma_DPD) / sqrt(dt); a batch forms both per bead
 // from the replica's temperature.  PAIR selects the pair style at compile time.
 // The new velocities go to vout, which is B.v itself unless the DPD thermostat
-// reads the neighbours' input velocities.
+// reads the neighbours' input velocities.  Each step reports the workgroup maxima
+// of |v|^2 (WCA) or, with DPD, of the squared displacement of the new position
+// from the block's reference position xref (the list build's; nullptr at the
+// block's first step, whose input is that position).
 template <typename R, int MODE, bool BATCH, int PAIR>
 __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
                                                     double4* __restrict__ xout, double* vout, int64_t step,
                                                     double pref, double dsig, unsigned int* __restrict__ vmax2_slot,
                                                     double* __restrict__ fout, int* __restrict__ err,
-                                                    double4* __restrict__ xsave, double* __restrict__ vsave) {
+                                                    double4* __restrict__ xsave, double* __restrict__ vsave,
+                                                    const double4* __restrict__ xref) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
     const Params& P = *Pp;
     const int n = P.n;
@@ -673,6 +695,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
     Acc<R> a;
     double4 xi = make_double4(0, 0, 0, 0);
     double vx = 0, vy = 0, vz = 0;
+    double m2 = 0.0;   // |v|^2, or the squared displacement from the reference
     if (active) {
         xi = B.x[i];
         const Box& X = box_of<BATCH>(P, meta_word(xi));
@@ -735,6 +758,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
             xo.w = xi.w;
             bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
             if (bad) atomicOr(err, ERR_NONFINITE);
+            if (PAIR == PAIR_DPD) {
+                const double4 r = xref ? xref[i] : xi;
+                const double ex = near_image(xo.x - r.x, X), ey = near_image(xo.y - r.y, X),
+                             ez = near_image(xo.z - r.z, X);
+                m2 = (ex * ex + ey * ey) + ez * ez;
+            } else {
+                m2 = (vx * vx + vy * vy) + vz * vz;
+            }
             xout[i] = xo;
             vout[i] = vx;
             vout[n + i] = vy;
@@ -745,8 +776,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         // largest speed of the workgroup; one atomic per workgroup, spread over
         // 64 words so that the workgroups of one step do not serialise on one address
         __shared__ float wmax[DB_BLOCK / 64];
-        double v2 = active ? (vx * vx + vy * vy) + vz * vz : 0.0;
-        v2 = wave_max(v2);
+        double v2 = wave_max(m2);
         if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = (float)v2 * 1.0001f;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -875,42 +905,44 @@ static bool velocity_double_buffer(const db_ctx* c) {
 
 template <typename R, int MODE, bool BATCH, int PAIR>
 static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
-                               double dsig, unsigned* vm, double* f, bool save) {
+                               double dsig, unsigned* vm, double* f, bool save, bool ref) {
     hipLaunchKernelGGL((k_step<R, MODE, BATCH, PAIR>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                        B, c->nlist, c->halo, xout, vout, step, pref, dsig, vm, f, c->err_d,
-                       save ? c->xsave : nullptr, save ? c->vsave : nullptr);
+                       save ? c->xsave : nullptr, save ? c->vsave : nullptr, ref ? c->xsave : nullptr);
 }
 
 template <int MODE, int PAIR>
 static void launch_step_pair(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
-                             double dsig, unsigned* vm, double* f, bool save) {
+                             double dsig, unsigned* vm, double* f, bool save, bool ref) {
     const bool batch = c->nrep > 0;
     if (c->precision == DB_MIXED) {
-        if (batch) launch_step_kernel<float, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
-        else launch_step_kernel<float, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        if (batch) launch_step_kernel<float, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+        else launch_step_kernel<float, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
     } else {
-        if (batch) launch_step_kernel<double, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
-        else launch_step_kernel<double, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        if (batch)
+            launch_step_kernel<double, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+        else
+            launch_step_kernel<double, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
     }
 }
 
 template <int MODE>
 static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
-                            double dsig, unsigned* vm, double* f, bool save = false) {
+                            double dsig, unsigned* vm, double* f, bool save = false, bool ref = false) {
     if (c->hp.have_pair && c->hp.pair_style == PAIR_DPD)
-        launch_step_pair<MODE, PAIR_DPD>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        launch_step_pair<MODE, PAIR_DPD>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
     else
-        launch_step_pair<MODE, PAIR_WCA>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        launch_step_pair<MODE, PAIR_WCA>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
 }
 
-void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
+void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save, bool ref) {
     if (c->n == 0) return;
     const double pref = langevin_prefactor(c->hp, step);
     const double dsig = dpd_sigma(c->hp, step);
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
     const bool vbuf = velocity_double_buffer(c);
-    launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save);
+    launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save, ref);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;
