@@ -48,6 +48,7 @@ def lib():
             "or_pair_wca": (C.c_int, [P, d, d, d, C.c_int]),
             "or_pair_dpd": (C.c_int, [P, d, d, d, C.c_int]),
             "or_bond_harmonic": (C.c_int, [P, i32, d, d]),
+            "or_bond_well": (C.c_int, [P, i32, d, d, d, d]),
             "or_angle_harmonic": (C.c_int, [P, i32, d, d]),
             "or_dihedral_cosine": (C.c_int, [P, i32, d, d]),
             "or_langevin": (C.c_int, [P, d, d, d]),
@@ -164,6 +165,8 @@ class Oracle:
             _chk(L.or_pair_wca(self._h, ff.eps, ff.sigma, ff.rc, ff.exclude_depth), "or_pair_wca")
         for t, (K, r0) in ff.bonds.items():
             _chk(L.or_bond_harmonic(self._h, t, K, r0), "or_bond_harmonic")
+        for t, (umin, rw, rz, rcut) in getattr(ff, "wells", {}).items():
+            _chk(L.or_bond_well(self._h, t, umin, rw, rz, rcut), "or_bond_well")
         for t, (K, th0) in ff.angles.items():
             _chk(L.or_angle_harmonic(self._h, t, K, th0), "or_angle_harmonic")
         for t, (K, p0) in ff.dihedrals.items():

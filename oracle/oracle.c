@@ -59,6 +59,8 @@ struct or_sys {
     int pair_style;                 /* 0: WCA, 1: DPD */
     double dpd_a, dpd_gamma;
     double bK[MAXT], bR0[MAXT]; int bset[MAXT];
+    int bstyle[MAXT];                              /* 0: harmonic, 1: well */
+    double bUmin[MAXT], bRw[MAXT], bRz[MAXT], bRcut[MAXT];
     double aK[MAXT], aT0[MAXT]; int aset[MAXT];
     double dK[MAXT], dP0[MAXT]; int dset[MAXT];
     double T0, T1, gamma, dt; int64_t ramp;
@@ -322,7 +324,18 @@ int or_pair_dpd(or_sys* s, double a, double gamma, double rc, int depth) {
 }
 int or_bond_harmonic(or_sys* s, int32_t t, double K, double r0) {
     if (t < 1 || t >= MAXT) return -1;
-    s->bK[t] = K; s->bR0[t] = r0; s->bset[t] = 1; return 0;
+    s->bK[t] = K; s->bR0[t] = r0; s->bset[t] = 1; s->bstyle[t] = 0; return 0;
+}
+/* bond well of the 1-bead DNA model, section 3, in the reading that makes the
+ * printed backbone and hybridization forms consistent: U = U_min [(r - r_w)^2 /
+ * (r_z - r_w)^2 - 1] for r < r_cut, 0 beyond; minimum -U_min at the well r_w,
+ * zero at r_z (r_cut = +inf: no cutoff) */
+int or_bond_well(or_sys* s, int32_t t, double umin, double rw, double rz, double rcut) {
+    if (t < 1 || t >= MAXT || !isfinite(umin) || !isfinite(rw) || !isfinite(rz) || rz == rw || !(rcut > 0))
+        return -1;
+    s->bUmin[t] = umin; s->bRw[t] = rw; s->bRz[t] = rz; s->bRcut[t] = rcut;
+    s->bset[t] = 1; s->bstyle[t] = 1;
+    return 0;
 }
 int or_angle_harmonic(or_sys* s, int32_t t, double K, double th0) {
     if (t < 1 || t >= MAXT) return -1;
@@ -611,6 +624,23 @@ static void dpd_thermostat_pair(or_sys* s, int i, int j, const double d[3], doub
     }
 }
 
+/* energy u and dU/dr of bond type t at length r, as the bead storing t feels it */
+static void bond_potential(const or_sys* s, int t, double r, double* u, double* du) {
+    if (s->bstyle[t] == 1) {
+        if (r < s->bRcut[t]) {
+            double w = s->bRz[t] - s->bRw[t];
+            *u = s->bUmin[t] * ((r - s->bRw[t]) * (r - s->bRw[t]) / (w * w) - 1.0);
+            *du = 2.0 * s->bUmin[t] * (r - s->bRw[t]) / (w * w);
+        } else {
+            *u = 0.0;
+            *du = 0.0;
+        }
+        return;
+    }
+    *u = s->bK[t] * (r - s->bR0[t]) * (r - s->bR0[t]);
+    *du = 2.0 * s->bK[t] * (r - s->bR0[t]);
+}
+
 static void bonded_forces(or_sys* s, force_ctx* c) {
     double* f = c->f;
     /* bonds: bead i feels the potential of the type it stores (t_ij), bead j that of t_ji */
@@ -619,11 +649,12 @@ static void bonded_forces(or_sys* s, force_ctx* c) {
         double d[3];
         double r = sqrt(sep(s, b->i, b->j, d));
         if (!(r > 0)) continue;
-        double Ki = s->bK[b->tij], ri = s->bR0[b->tij];
-        double Kj = s->bK[b->tji], rj = s->bR0[b->tji];
-        c->ubond += 0.5 * (Ki * (r - ri) * (r - ri) + Kj * (r - rj) * (r - rj));
-        double gi = 2.0 * Ki * (r - ri) / r;   /* F_i = gi * d (d points from i to j) */
-        double gj = 2.0 * Kj * (r - rj) / r;   /* F_j = -gj * d */
+        double ui, dui, uj, duj;
+        bond_potential(s, b->tij, r, &ui, &dui);
+        bond_potential(s, b->tji, r, &uj, &duj);
+        c->ubond += 0.5 * (ui + uj);
+        double gi = dui / r;   /* F_i = gi * d (d points from i to j) */
+        double gj = duj / r;   /* F_j = -gj * d */
         for (int q = 0; q < 3; ++q) {
             f[3 * b->i + q] += gi * d[q];
             f[3 * b->j + q] -= gj * d[q];

@@ -8,10 +8,12 @@
  *
  * What it computes (paper: Svaneborg, "LAMMPS framework for dynamic bonding and
  * an application modeling DNA"):
- *   - forces of the WCA pair potential, harmonic bonds with per-direction bond
- *     types (section 2, directional bonds), harmonic angles and cosine
- *     dihedrals (section 3 potentials);
- *   - velocity-Verlet time stepping with a Langevin thermostat;
+ *   - forces of the WCA pair potential or the DPD conservative force, harmonic
+ *     or well-shaped bonds with per-direction bond types (section 2,
+ *     directional bonds), harmonic angles and cosine dihedrals (section 3
+ *     potentials);
+ *   - velocity-Verlet time stepping with a Langevin thermostat and/or the DPD
+ *     dissipative and random pair forces (section 3);
  *   - the dynamic-bonding sweep (section 2 and the appendix "Implementation
  *     details", steps 2-9): creation and breakage nomination, mutual matching
  *     with stochastic acceptance, killbond, convertbond, removal of angles and
@@ -46,6 +48,7 @@ int or_generate_angles_dihedrals(or_sys* s);
 int or_pair_wca(or_sys* s, double eps, double sigma, double rc, int exclude_depth);
 int or_pair_dpd(or_sys* s, double a, double gamma, double rc, int exclude_depth);
 int or_bond_harmonic(or_sys* s, int32_t type, double K, double r0);
+int or_bond_well(or_sys* s, int32_t type, double umin, double r_well, double r_zero, double r_cut);
 int or_angle_harmonic(or_sys* s, int32_t type, double K, double theta0);
 int or_dihedral_cosine(or_sys* s, int32_t type, double K, double phi0);
 int or_langevin(or_sys* s, double T, double gamma, double dt);

@@ -70,6 +70,7 @@ class ForceField:
     dpd_a: float = 25.0
     dpd_gamma: float = 4.5
     bonds: dict = dataclasses.field(default_factory=dict)      # type -> (K, r0)
+    wells: dict = dataclasses.field(default_factory=dict)      # type -> (U_min, r_well, r_zero, r_cut)
     angles: dict = dataclasses.field(default_factory=dict)     # type -> (K, theta0)
     dihedrals: dict = dataclasses.field(default_factory=dict)  # type -> (K, phi0)
     T0: float = 1.0
