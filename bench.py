@@ -156,12 +156,8 @@ def run_batch(steps, warmup, precision=1):
             "speedup": seq_s / bat_s}
 
 
-def run_dpd(steps, warmup):
-    """The paper's own dynamics (section 3): DPD conservative, dissipative and
-    random pair forces at density 3 with the hybridization sweep, mixed and FP64."""
-    import synth
-
-    w = synth.dpd_c3()
+def run_leg(w, description, steps, warmup):
+    """One more workload, mixed and FP64, reported beside the headline."""
     mixed = run_gpu(w, 1, steps, warmup)
     fp64 = run_gpu(w, 0, steps, warmup)
     b, a, d = mixed["topology_per_bead"]
@@ -171,14 +167,31 @@ def run_dpd(steps, warmup):
     def frac(r):
         return kernel_bytes * n / (r["step_kernel_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS if r["step_kernel_us"] > 0 else None
 
-    return {"workload": "2500 x 20-bp duplexes (2-bead model, 200000 beads) in 800000 DPD solvent beads, "
-                        "1000000 beads, rho=3, a=25, gamma=100, T=1, dt=0.01, sweep every 10 steps",
-            "value": mixed["bead_steps_per_s"], "unit": "bead-steps/s", "ms_per_step": mixed["ms_per_step"],
-            "step_kernel_us": mixed["step_kernel_us"], "hbm_roofline_frac": frac(mixed),
-            "bytes_per_bead_step": kernel_bytes,
+    return {"workload": description, "value": mixed["bead_steps_per_s"], "unit": "bead-steps/s",
+            "ms_per_step": mixed["ms_per_step"], "step_kernel_us": mixed["step_kernel_us"],
+            "hbm_roofline_frac": frac(mixed), "bytes_per_bead_step": kernel_bytes,
             "fp64": {"value": fp64["bead_steps_per_s"], "ms_per_step": fp64["ms_per_step"],
                      "step_kernel_us": fp64["step_kernel_us"], "hbm_roofline_frac": frac(fp64)},
             "mixed_detail": mixed, "fp64_detail": fp64}
+
+
+def run_dpd(steps, warmup):
+    """The paper's own dynamics (section 3): DPD conservative, dissipative and
+    random pair forces at density 3 with the hybridization sweep."""
+    import synth
+
+    return run_leg(synth.dpd_c3(), "2500 x 20-bp duplexes (2-bead model, 200000 beads) in 800000 DPD solvent beads, "
+                   "1000000 beads, rho=3, a=25, gamma=100, T=1, dt=0.01, sweep every 10 steps", steps, warmup)
+
+
+def run_dna1(steps, warmup):
+    """The paper's 1-bead DNA model (section 3 wells, angles and stacking
+    dihedrals; Fig. 2 rule table, a sweep every step) in DPD solvent."""
+    import synth
+
+    return run_leg(synth.dna1_c3(), "5000 x 20-bp duplexes of the paper's 1-bead model (200000 beads) in 800000 "
+                   "DPD solvent beads, 1000000 beads, rho=3, Fig. 2 rules (sweep every step, paircheck14), "
+                   "section 3 wells, angles and dihedrals, DPD a=25, gamma=100, T=1, dt=0.01", steps, warmup)
 
 
 def log(msg):
@@ -288,6 +301,7 @@ def main():
     ap.add_argument("--permute-every", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the replica-ladder measurement")
     ap.add_argument("--no-dpd", action="store_true", help="skip the DPD-solution measurement")
+    ap.add_argument("--no-dna1", action="store_true", help="skip the 1-bead DNA model measurement")
     ap.add_argument("--accuracy", action="store_true",
                     help="also report mixed-vs-FP64 accuracy: force error, hybridized-fraction ramp, NVE drift")
     ap.add_argument("--copy-probe", action="store_true",
@@ -351,6 +365,8 @@ def main():
         line["batch"] = run_batch(max(100, args.steps // 4), min(args.warmup, 50))
     if not args.no_dpd:
         line["dpd"] = run_dpd(args.steps, args.warmup)
+    if not args.no_dna1:
+        line["dna1"] = run_dna1(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -126,6 +126,14 @@ int db_pair_wca(db_ctx* ctx, double eps, double sigma, double rc, int exclude_de
 int db_pair_dpd(db_ctx* ctx, double a, double gamma, double rc, int exclude_depth);
 /* U = K (r - r0)^2; a bead feels the potential of the type it stores */
 int db_bond_harmonic(db_ctx* ctx, int32_t type, double K, double r0);
+/* Bond well of the 1-bead DNA model (section 3: backbone U_min = 10, well 0.3,
+ * zero 0.6; hybridization U_min = 1, well 0.6, zero and cutoff 1.0), in the
+ * reading that makes the two printed forms consistent:
+ * U = U_min [(r - r_well)^2 / (r_zero - r_well)^2 - 1] for r < r_cut, 0 beyond
+ * (r_cut = +inf: no cutoff).  Replaces any harmonic setting of the type.
+ * EINVAL for a type outside 1..31, non-finite U_min / r_well / r_zero,
+ * r_zero == r_well or r_cut <= 0. */
+int db_bond_well(db_ctx* ctx, int32_t type, double U_min, double r_well, double r_zero, double r_cut);
 /* U = K (theta - theta0)^2 */
 int db_angle_harmonic(db_ctx* ctx, int32_t type, double K, double theta0);
 /* U = K [1 - cos(phi - phi0)], phi the signed dihedral with cis = 0 */
@@ -183,8 +191,9 @@ int db_get_stats(db_ctx* ctx, db_stats* out);
 /* current step counter; db_set_step also allows the sweep of that step again */
 int db_set_step(db_ctx* ctx, int64_t step);
 /* tuning knobs of the step scheduler: the neighbour-list skin (list cutoff minus
- * pair cutoff, > 0; default 0.55) and how many cell-list rebuilds pass between
- * reorderings of the per-bead state into cell order (>= 1; default 8) */
+ * pair cutoff, > 0; default 0.55 with WCA, 0.3 with DPD) and how many cell-list
+ * rebuilds pass between reorderings of the per-bead state into cell order (>= 1;
+ * default 8).  Once set here, the skin no longer follows the pair style. */
 int db_tune(db_ctx* ctx, double skin, int32_t permute_every);
 /* enable (1) / disable (0) HIP-event timing of every launch of the fused step
  * kernel on the handle's stream */
@@ -197,7 +206,8 @@ int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);
  * then bracketed by two potential-energy evaluations (costs about two force
  * passes per sweep) */
 int db_track_topology_energy(db_ctx* ctx, int enable);
-/* tries skin in {0.4, 0.5, 0.6, 0.8} x permute_every in {1, 2, 4, 8}, running
+/* tries skin in {0.4, 0.5, 0.6, 0.8} (DPD: {0.2, 0.25, 0.3, 0.4}) x
+ * permute_every in {1, 2, 4, 8}, running
  * steps_per_trial steps of the trajectory with each (the system advances by
  * 16 x steps_per_trial steps), and keeps the fastest; best_skin / best_permute
  * (either may be NULL) receive the choice */

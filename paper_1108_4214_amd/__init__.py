@@ -26,7 +26,8 @@ MAX_BONDS_PER_BEAD, MAX_ANGLES_PER_BEAD, MAX_DIHEDRALS_PER_BEAD = 4, 12, 16
 EXPORTS = [
     "db_create", "db_workspace_bytes", "db_bind_workspace", "db_destroy", "db_last_error",
     "db_set_state", "db_set_reactive", "db_set_bonds", "db_set_angles", "db_set_dihedrals",
-    "db_generate_angles_dihedrals", "db_pair_wca", "db_pair_dpd", "db_bond_harmonic", "db_angle_harmonic",
+    "db_generate_angles_dihedrals", "db_pair_wca", "db_pair_dpd", "db_bond_harmonic", "db_bond_well",
+    "db_angle_harmonic",
     "db_dihedral_cosine", "db_langevin", "db_temperature_ramp", "db_sweep_every", "db_bond_create",
     "db_bond_create_dir", "db_bond_break", "db_bond_kill", "db_bond_convert", "db_max_bonds",
     "db_angle_pattern", "db_dihedral_pattern", "db_step", "db_sweep_now", "db_forces", "db_energy",
@@ -78,6 +79,7 @@ _SIG = {
     "db_pair_wca": [_P, _d, _d, _d, _int],
     "db_pair_dpd": [_P, _d, _d, _d, _int],
     "db_bond_harmonic": [_P, _i32, _d, _d],
+    "db_bond_well": [_P, _i32, _d, _d, _d, _d],
     "db_angle_harmonic": [_P, _i32, _d, _d],
     "db_dihedral_cosine": [_P, _i32, _d, _d],
     "db_langevin": [_P, _d, _d, _d],
@@ -223,6 +225,10 @@ def db_pair_dpd(ctx, a, gamma, rc, exclude_depth):
 
 def db_bond_harmonic(ctx, t, K, r0):
     _check(ctx, _lib.db_bond_harmonic(ctx, int(t), K, r0))
+
+
+def db_bond_well(ctx, t, umin, r_well, r_zero, r_cut):
+    _check(ctx, _lib.db_bond_well(ctx, int(t), umin, r_well, r_zero, r_cut))
 
 
 def db_angle_harmonic(ctx, t, K, theta0):
@@ -426,6 +432,8 @@ class System:
                 db_pair_wca(c, ff.eps, ff.sigma, ff.rc, ff.exclude_depth)
             for t, (K, r0) in ff.bonds.items():
                 db_bond_harmonic(c, t, K, r0)
+            for t, (umin, rw, rz, rcut) in getattr(ff, "wells", {}).items():
+                db_bond_well(c, t, umin, rw, rz, rcut)
             for t, (K, th0) in ff.angles.items():
                 db_angle_harmonic(c, t, K, th0)
             for t, (K, p0) in ff.dihedrals.items():

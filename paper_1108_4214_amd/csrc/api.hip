@@ -32,6 +32,9 @@ namespace {
 
 const int kMaxBlock = 64;
 const double kSkinDefault = 0.55;
+// DPD at density 3 lists about five times the candidates of the WCA workloads, so
+// a thinner skin (more frequent list builds, shorter lists) costs less per step
+const double kSkinDefaultDPD = 0.3;
 
 // host memory the device writes its end-of-block report into (mapped, pinned)
 struct Pinned {
@@ -584,8 +587,10 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     P.box.T0 = P.box.T1 = 1.0;
     P.dt = 0.005;
     P.excl_depth = 1;
+    for (int t = 0; t < DB_MAXT; ++t) P.bRc2[t] = INFINITY;
     c->params_dirty = true;
     c->skin = kSkinDefault;
+    c->skin_tuned = false;
     c->swept_step = -1;
     c->rebuild_interval = 8;
     c->permute_every = 8;
@@ -771,6 +776,7 @@ int db_pair_wca(db_ctx* c, double eps, double sigma, double rc, int depth) {
     Params& P = c->hp;
     P.have_pair = 1;
     P.pair_style = PAIR_WCA;
+    if (!c->skin_tuned) c->skin = kSkinDefault;
     P.eps = eps;
     P.sig2 = sigma * sigma;
     P.rc2 = rc * rc;
@@ -788,6 +794,7 @@ int db_pair_dpd(db_ctx* c, double a, double gamma, double rc, int depth) {
     Params& P = c->hp;
     P.have_pair = 1;
     P.pair_style = PAIR_DPD;
+    if (!c->skin_tuned) c->skin = kSkinDefaultDPD;
     P.dpd_a = a;
     P.dpd_gamma = gamma;
     P.rc2 = rc * rc;
@@ -802,6 +809,22 @@ int db_bond_harmonic(db_ctx* c, int32_t t, double K, double r0) {
     if (!c || t < 1 || t >= DB_MAXT || !std::isfinite(K) || !std::isfinite(r0)) return DB_EINVAL;
     c->hp.bK[t] = K;
     c->hp.bR0[t] = r0;
+    c->hp.bE0[t] = 0.0;
+    c->hp.bRc2[t] = INFINITY;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+// the well is the harmonic bond K (r - r_w)^2 with K = U_min / (r_z - r_w)^2,
+// shifted by -U_min, and cut at r_cut
+int db_bond_well(db_ctx* c, int32_t t, double umin, double rw, double rz, double rcut) {
+    if (!c || t < 1 || t >= DB_MAXT || !std::isfinite(umin) || !std::isfinite(rw) || !std::isfinite(rz) || rz == rw ||
+        !(rcut > 0))
+        return DB_EINVAL;
+    c->hp.bK[t] = umin / ((rz - rw) * (rz - rw));
+    c->hp.bR0[t] = rw;
+    c->hp.bE0[t] = -umin;
+    c->hp.bRc2[t] = std::isfinite(rcut) ? rcut * rcut : INFINITY;
     c->params_dirty = true;
     return DB_OK;
 }
@@ -1256,6 +1279,7 @@ int db_set_step(db_ctx* c, int64_t step) {
 int db_tune(db_ctx* c, double skin, int32_t permute_every) {
     if (!c || !(skin > 0) || !std::isfinite(skin) || permute_every < 1) return DB_EINVAL;
     c->skin = skin;
+    c->skin_tuned = true;
     c->permute_every = permute_every;
     c->params_dirty = true;
     return DB_OK;
@@ -1263,7 +1287,11 @@ int db_tune(db_ctx* c, double skin, int32_t permute_every) {
 
 int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* best_permute) {
     if (!c || steps_per_trial < 1) return DB_EINVAL;
-    const double skins[4] = {0.4, 0.5, 0.6, 0.8};
+    // DPD at density 3 favours thinner skins than the WCA workloads
+    const bool dpd = c->hp.have_pair && c->hp.pair_style == PAIR_DPD;
+    const double wca_skins[4] = {0.4, 0.5, 0.6, 0.8}, dpd_skins[4] = {0.2, 0.25, 0.3, 0.4};
+    const double* skins_of = dpd ? dpd_skins : wca_skins;
+    const double skins[4] = {skins_of[0], skins_of[1], skins_of[2], skins_of[3]};
     const int perms[4] = {1, 2, 4, 8};
     double best_t = INFINITY, bs = c->skin;
     int bp = c->permute_every;
@@ -1299,7 +1327,8 @@ static bool same_physics(const Params& a, const Params& b) {
     if (a.have_pair != b.have_pair || a.excl_depth != b.excl_depth || a.pair_style != b.pair_style ||
         a.eps != b.eps || a.sig2 != b.sig2 || a.rc2 != b.rc2 || a.dpd_a != b.dpd_a || a.dpd_gamma != b.dpd_gamma)
         return false;
-    if (!eq(a.bK, b.bK, sizeof a.bK) || !eq(a.bR0, b.bR0, sizeof a.bR0) || !eq(a.aK, b.aK, sizeof a.aK) ||
+    if (!eq(a.bK, b.bK, sizeof a.bK) || !eq(a.bR0, b.bR0, sizeof a.bR0) || !eq(a.bE0, b.bE0, sizeof a.bE0) ||
+        !eq(a.bRc2, b.bRc2, sizeof a.bRc2) || !eq(a.aK, b.aK, sizeof a.aK) ||
         !eq(a.aT0, b.aT0, sizeof a.aT0) || !eq(a.dK, b.dK, sizeof a.dK) || !eq(a.dC0, b.dC0, sizeof a.dC0) ||
         !eq(a.dS0, b.dS0, sizeof a.dS0))
         return false;

@@ -75,6 +75,7 @@ struct Params {
     double rnl2;         // neighbour-list cutoff squared (pair cutoff + skin)
     // bonded
     double bK[DB_MAXT], bR0[DB_MAXT];
+    double bE0[DB_MAXT], bRc2[DB_MAXT];   // energy offset; squared cutoff (+inf: none)
     double aK[DB_MAXT], aT0[DB_MAXT], aPiMinusT0[DB_MAXT];
     double dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
     // thermostat / integration
@@ -209,6 +210,7 @@ struct db_ctx {
     int permute_every;        // permute the state every k-th rebuild
     int64_t rebuild_count;
     double skin;
+    bool skin_tuned;          // set by db_tune: the pair style no longer picks the default
     double vmax_est;
 
     // profiling

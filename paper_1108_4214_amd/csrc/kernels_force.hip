@@ -28,7 +28,7 @@ struct Acc {
 // and an LDS lookup costs far less than a second dependent global load.
 template <typename R>
 struct Coef {
-    R bK[DB_MAXT], bR0[DB_MAXT];
+    R bK[DB_MAXT], bR0[DB_MAXT], bRc2[DB_MAXT];   // bRc2: squared bond cutoff (+inf: none)
     R aK[DB_MAXT], aT0[DB_MAXT], aPm[DB_MAXT];   // aPm = pi - theta0
     R dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
 };
@@ -40,6 +40,7 @@ __device__ __forceinline__ void load_coef(const Params& P, Coef<R>& C) {
     if (t < DB_MAXT) {
         C.bK[t] = (R)P.bK[t];
         C.bR0[t] = (R)P.bR0[t];
+        C.bRc2[t] = (R)P.bRc2[t];
         C.aK[t] = (R)P.aK[t];
         C.aT0[t] = (R)P.aT0[t];
         C.aPm[t] = (R)P.aPiMinusT0[t];
@@ -366,7 +367,7 @@ __device__ __forceinline__ void bond_terms(const Params& P, const Box& X, const 
         double dz = near_image(xj.z - xi.z, X);
         R rx = (R)dx, ry = (R)dy, rz = (R)dz;
         R rr2 = (rx * rx + ry * ry) + rz * rz;
-        if (!(rr2 > (R)0)) continue;
+        if (!(rr2 > (R)0) || !(rr2 < C.bRc2[t])) continue;
         R ir = r_rsqrt<R>(rr2);
         R r = rr2 * ir;
         R K = C.bK[t], r0 = C.bR0[t];
@@ -375,7 +376,7 @@ __device__ __forceinline__ void bond_terms(const Params& P, const Box& X, const 
         a.fy += (double)(g * ry);
         a.fz += (double)(g * rz);
         if (MODE == MODE_ENERGY) {
-            a.e_bond += 0.5 * (double)(K * (r - r0) * (r - r0));
+            a.e_bond += 0.5 * ((double)(K * (r - r0) * (r - r0)) + P.bE0[t]);
             a.vir -= 0.5 * (double)(g * r * r);
         }
     }
@@ -620,7 +621,7 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         const int t = B.bt[k * n + i] & (DB_MAXT - 1);
         const R rx = hx[k], ry = hy[k], rz = hz[k];
         R rr2 = (rx * rx + ry * ry) + rz * rz;
-        if (!(rr2 > (R)0)) continue;
+        if (!(rr2 > (R)0) || !(rr2 < C.bRc2[t])) continue;
         R ir = r_rsqrt<R>(rr2);
         R r = rr2 * ir;
         R g = (R)2.0 * C.bK[t] * (r - C.bR0[t]) * ir;   // F_i = g * (x_j - x_i)

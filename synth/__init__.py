@@ -153,6 +153,46 @@ def ff_dpd(T=1.0, gamma_dpd=100.0, dt=0.01, a=25.0) -> ForceField:
     return ff
 
 
+def ff_dna1(T=1.0, gamma_dpd=100.0, dt=0.01) -> ForceField:
+    """The paper's 1-bead DNA force field (section 3) in DPD solvent: hybridization
+    well (U_min 1, well 0.6, zero and cutoff 1.0), backbone wells of both
+    directions (U_min 10, well 0.3, zero 0.6), straight backbone angles (K 20) and
+    backbone-hybridization right angles (K 1), stacking dihedrals K (1 + d cos phi)
+    with d = -1 (cis: types 1, 2) and d = +1 (trans: type 3), i.e. cosine
+    dihedrals at phi0 = 0 and pi; DPD as in ff_dpd."""
+    ff = ff_dpd(T=T, gamma_dpd=gamma_dpd, dt=dt)
+    ff.bonds = {}
+    ff.wells = {H_BOND: (1.0, 0.6, 1.0, 1.0), BB_3P: (10.0, 0.3, 0.6, math.inf), BB_5P: (10.0, 0.3, 0.6, math.inf)}
+    ff.angles = {1: (20.0, math.pi), 2: (1.0, 0.5 * math.pi)}
+    ff.dihedrals = {1: (1.0, 0.0), 2: (1.0, 0.0), 3: (1.0, math.pi)}
+    return ff
+
+
+def rules_fig2() -> RuleSet:
+    """The rule table of the paper's 1-bead DNA model (Fig. 2): hybridization of
+    complementary bases within 0.6 with p = 1, directional backbone ligation
+    between bead types 2 and 3 within 0.3 with p = 0.1, hybridization bonds killed
+    beyond 1.0, at most one bond of each type per bead, straight-backbone and
+    backbone-hybridization angles, three stacking dihedral patterns; a sweep every
+    step with paircheck14."""
+    any3, any4 = (ANY, ANY, ANY), (ANY, ANY, ANY, ANY)
+    return RuleSet(every=1, paircheck14=1, rules=[
+        ("create", H_BOND, A, T, 0.6, 1.0),
+        ("create", H_BOND, C, G, 0.6, 1.0),
+        ("createdir", BB_3P, BB_5P, T, C, 0.3, 0.1),
+        ("kill", H_BOND, 1.0),
+        ("maxbond", H_BOND, ANY, 1),
+        ("maxbond", BB_3P, ANY, 1),
+        ("maxbond", BB_5P, ANY, 1),
+        ("angle", 1, any3, (mask(BB_3P), mask(BB_5P))),
+        ("angle", 2, any3, (mask(H_BOND), mask(BB_3P, BB_5P))),
+        ("dihedral", 1, any4, (mask(H_BOND), mask(BB_3P, BB_5P), mask(H_BOND))),
+        ("dihedral", 2, any4, (mask(BB_3P), mask(H_BOND), mask(BB_5P))),
+        ("dihedral", 3, any4, (mask(BB_3P), mask(H_BOND), mask(BB_3P))),
+        ("dihedral", 3, any4, (mask(BB_5P), mask(H_BOND), mask(BB_5P))),
+    ])
+
+
 def parse_script(text: str) -> RuleSet:
     """Parse the rule syntax of the paper's Fig. 1 (one rule per line).
 
@@ -434,6 +474,54 @@ def dpd_c3(seed_w=23, seed_d=33) -> Workload:
     s = dpd_solution(2500, 20, 1_000_000, 3.0, seed_w, seed_d)
     return Workload("dpd: 2500 x 20-bp duplexes in DPD solvent, 1000000 beads, rho=3", s, ff_dpd(),
                     rules_t2(p=0.5, every=10), 10000, seed_d)
+
+
+def dna1_solution(n_duplex, n_bp, n_total, rho=3.0, seed_w=29, seed_d=39, T=1.0, bb=0.3, hyb=0.6) -> System:
+    """Duplexes of the paper's 1-bead model (ladders of ladder_1bead's layout:
+    backbone spacing bb, strands hyb apart, random sequences) in DPD solvent
+    (type 5, not reactive) at number density rho.  The flat ladders sit on a slot
+    lattice (pitch: length + 1 sigma along x, 1.6 sigma in y, 1 sigma in z) in
+    random slot order with random flips and jitter; solvent beads are uniform."""
+    n_dna = 2 * n_bp * n_duplex
+    if n_total < n_dna:
+        raise ValueError("n_total below the duplex beads")
+    L = (n_total / rho) ** (1.0 / 3.0)
+    rng = np.random.default_rng(seed_w)
+    px, py, pz = (n_bp - 1) * bb + 1.0, 1.6, 1.0
+    nx, ny, nz = int(L // px), int(L // py), int(L // pz)
+    if nx * ny * nz < n_duplex:
+        raise ValueError("duplexes do not fit in the box")
+    slots = rng.permutation(nx * ny * nz)[:n_duplex]
+    b = _Builder()
+    for sl in slots:
+        sl = int(sl)
+        org = np.array([(sl % nx) * px, ((sl // nx) % ny) * py, (sl // (nx * ny)) * pz]) + rng.uniform(-0.05, 0.05, 3)
+        seq = random_sequence(rng, n_bp)
+        k = np.arange(n_bp, dtype=np.float64)
+        if rng.integers(2):
+            k = (n_bp - 1) - k
+        y1, y2 = (0.0, hyb) if rng.integers(2) else (hyb, 0.0)
+        s1 = [b.add(org + [k[m] * bb, y1, 0.0], seq[m]) for m in range(n_bp)]
+        s2 = [b.add(org + [k[m] * bb, y2, 0.0], COMPLEMENT[seq[m]]) for m in range(n_bp)]
+        for m in range(n_bp - 1):
+            b.bonds.append((s1[m], s1[m + 1], BB_3P, BB_5P))   # strand 1: m+1 is 3' of m
+            b.bonds.append((s2[m], s2[m + 1], BB_5P, BB_3P))   # strand 2 antiparallel: m is 3' of m+1
+        for m in range(n_bp):
+            b.bonds.append((s1[m], s2[m], H_BOND, H_BOND))
+    for p in rng.uniform(0.0, L, size=(n_total - n_dna, 3)):
+        b.add(p, P)
+    react = np.zeros(n_total, dtype=np.uint8)
+    react[:n_dna] = 1
+    return _finish(b, L, np.random.default_rng(seed_d), T, reactive=react)
+
+
+def dna1_c3(seed_w=29, seed_d=39) -> Workload:
+    """1,000,000 beads at density 3: 5,000 hybridized 20-bp duplexes of the
+    paper's 1-bead model (200,000 beads) in 800,000 DPD solvent beads; the paper's
+    force field (ff_dna1) and Fig. 2 rule table (sweep every step)."""
+    s = dna1_solution(5000, 20, 1_000_000, 3.0, seed_w, seed_d)
+    return Workload("dna1: 5000 x 20-bp duplexes of the 1-bead model in DPD solvent, 1000000 beads, rho=3", s,
+                    ff_dna1(), rules_fig2(), 10000, seed_d)
 
 
 def c2(seed_w=2, seed_d=12) -> Workload:
