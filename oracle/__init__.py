@@ -49,6 +49,7 @@ def lib():
             "or_pair_dpd": (C.c_int, [P, d, d, d, C.c_int]),
             "or_bond_harmonic": (C.c_int, [P, i32, d, d]),
             "or_bond_well": (C.c_int, [P, i32, d, d, d, d]),
+            "or_external_force": (C.c_int, [P, i64, P, P]),
             "or_angle_harmonic": (C.c_int, [P, i32, d, d]),
             "or_dihedral_cosine": (C.c_int, [P, i32, d, d]),
             "or_langevin": (C.c_int, [P, d, d, d]),
@@ -153,6 +154,12 @@ class Oracle:
         a = _c(dih, np.int32).reshape(-1, 5)
         abcd = np.ascontiguousarray(a[:, 1:5]); t = np.ascontiguousarray(a[:, 0])
         _chk(lib().or_set_dihedrals(self._h, a.shape[0], _p(abcd), _p(t)), "or_set_dihedrals")
+
+    def set_external_force(self, ids, f):
+        """constant external force f[k] (3 components) on bead ids[k]; empty ids clears"""
+        i = _c(ids, np.int32).reshape(-1)
+        fv = _c(f, np.float64).reshape(-1, 3)
+        _chk(lib().or_external_force(self._h, i.shape[0], _p(i), _p(fv)), "or_external_force")
 
     def generate_angles_dihedrals(self):
         _chk(lib().or_generate_angles_dihedrals(self._h), "or_generate_angles_dihedrals")

@@ -43,6 +43,7 @@ struct or_sys {
     double L, hL;
     uint64_t seed;
     double *x, *v;      /* n*3 */
+    double *fext;       /* n*3 constant external force per bead, or NULL */
     int *type;
     uint8_t *reactive;
 
@@ -164,7 +165,7 @@ or_sys* or_create(int32_t n, double L, uint64_t seed) {
 
 void or_destroy(or_sys* s) {
     if (!s) return;
-    free(s->x); free(s->v); free(s->type); free(s->reactive);
+    free(s->x); free(s->v); free(s->fext); free(s->type); free(s->reactive);
     free(s->bond); free(s->ang); free(s->dih);
     free(s->aoff); free(s->anbr); free(s->atype); free(s->abond);
     free(s->nomC); free(s->nomK);
@@ -742,6 +743,25 @@ static void conservative(or_sys* s, force_ctx* c) {
     c->upair = c->ubond = c->uang = c->udih = c->vir = 0.0;
     if (s->have_pair) for_pairs(s, s->rc, 0, s->pair_style == 1 ? dpd_conservative_pair : wca_pair, c);
     bonded_forces(s, c);
+    if (s->fext)
+        for (int i = 0; i < 3 * s->n; ++i) c->f[i] += s->fext[i];
+}
+
+/* constant external forces (the unzipping experiments of section 3): bead ids[k]
+ * feels f[3k..3k+2] in every force evaluation; count = 0 removes them all; a
+ * bead listed twice keeps the sum */
+int or_external_force(or_sys* s, int64_t count, const int32_t* ids, const double* f) {
+    if (count < 0) return -1;
+    for (int64_t k = 0; k < count; ++k)
+        if (ids[k] < 0 || ids[k] >= s->n || !isfinite(f[3 * k]) || !isfinite(f[3 * k + 1]) || !isfinite(f[3 * k + 2]))
+            return -1;
+    free(s->fext);
+    s->fext = NULL;
+    if (count == 0) return 0;
+    s->fext = (double*)calloc(3 * (size_t)s->n, sizeof(double));
+    for (int64_t k = 0; k < count; ++k)
+        for (int q = 0; q < 3; ++q) s->fext[3 * (size_t)ids[k] + q] += f[3 * k + q];
+    return 0;
 }
 
 int or_forces(or_sys* s, double* f) {

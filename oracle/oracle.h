@@ -49,6 +49,7 @@ int or_pair_wca(or_sys* s, double eps, double sigma, double rc, int exclude_dept
 int or_pair_dpd(or_sys* s, double a, double gamma, double rc, int exclude_depth);
 int or_bond_harmonic(or_sys* s, int32_t type, double K, double r0);
 int or_bond_well(or_sys* s, int32_t type, double umin, double r_well, double r_zero, double r_cut);
+int or_external_force(or_sys* s, int64_t count, const int32_t* ids, const double* f);
 int or_angle_harmonic(or_sys* s, int32_t type, double K, double theta0);
 int or_dihedral_cosine(or_sys* s, int32_t type, double K, double phi0);
 int or_langevin(or_sys* s, double T, double gamma, double dt);
