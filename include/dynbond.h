@@ -124,7 +124,18 @@ int db_pair_wca(db_ctx* ctx, double eps, double sigma, double rc, int exclude_de
  * paper's DNA runs exclude beads fewer than three bonds apart: depth 2).
  * gamma >= 0; gamma = 0 gives the conservative force only.  Box edge > 2 rc. */
 int db_pair_dpd(db_ctx* ctx, double a, double gamma, double rc, int exclude_depth);
-/* U = K (r - r0)^2; a bead feels the potential of the type it stores */
+/* Constant external forces (the unzipping experiments of section 3, e.g. 28
+ * opposite forces on the end pair of a duplex): bead ids[k] feels f[3k..3k+2]
+ * in every force evaluation, db_forces included; a bead listed twice gets the
+ * sum; count = 0 removes them all.  Host pointers; the table is indexed by bead
+ * id, so it follows the beads through reorders.  No energy is attributed to it
+ * (its potential is not periodic).  EINVAL for an id outside 0..N-1 or a
+ * non-finite component; ESTATE on a batch, and db_batch_create refuses replicas
+ * that carry external forces. */
+int db_external_force(db_ctx* ctx, int64_t count, const int32_t* ids, const double* f);
+/* U = K (r - r0)^2; a bead feels the potential of the type it stores.  Directional
+ * types with different potentials (or K = 0 one way: a "half" bond) give a net
+ * force along the bond (section 2 remark on active matter). */
 int db_bond_harmonic(db_ctx* ctx, int32_t type, double K, double r0);
 /* Bond well of the 1-bead DNA model (section 3: backbone U_min = 10, well 0.3,
  * zero 0.6; hybridization U_min = 1, well 0.6, zero and cutoff 1.0), in the

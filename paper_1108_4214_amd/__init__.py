@@ -33,7 +33,7 @@ EXPORTS = [
     "db_angle_pattern", "db_dihedral_pattern", "db_step", "db_sweep_now", "db_forces", "db_energy",
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
-    "db_batch_create", "db_batch_get_state", "db_track_topology_energy",
+    "db_batch_create", "db_batch_get_state", "db_track_topology_energy", "db_external_force",
 ]
 
 STAT_FIELDS = [
@@ -80,6 +80,7 @@ _SIG = {
     "db_pair_dpd": [_P, _d, _d, _d, _int],
     "db_bond_harmonic": [_P, _i32, _d, _d],
     "db_bond_well": [_P, _i32, _d, _d, _d, _d],
+    "db_external_force": [_P, _i64, _P, _P],
     "db_angle_harmonic": [_P, _i32, _d, _d],
     "db_dihedral_cosine": [_P, _i32, _d, _d],
     "db_langevin": [_P, _d, _d, _d],
@@ -225,6 +226,14 @@ def db_pair_dpd(ctx, a, gamma, rc, exclude_depth):
 
 def db_bond_harmonic(ctx, t, K, r0):
     _check(ctx, _lib.db_bond_harmonic(ctx, int(t), K, r0))
+
+
+def db_external_force(ctx, ids, f):
+    i = np.ascontiguousarray(np.asarray(ids, dtype=np.int32).reshape(-1))
+    fv = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1, 3))
+    if fv.shape[0] != i.shape[0]:
+        raise ValueError("one force per id")
+    _check(ctx, _lib.db_external_force(ctx, i.shape[0], i.ctypes.data, fv.ctypes.data))
 
 
 def db_bond_well(ctx, t, umin, r_well, r_zero, r_cut):

@@ -153,6 +153,7 @@ static size_t layout(db_ctx* c, bool assign) {
     }
     put(c->xnext, 32 * n);
     put(c->vnext, 24 * n);
+    put(c->fext, 24 * n);
     put(c->xsave, 32 * n);
     put(c->vsave, 24 * n);
     SweepBuf& S = c->sw;
@@ -278,6 +279,7 @@ static int upload_params(db_ctx* c) {
     if (!c->params_dirty) return DB_OK;
     compute_grid(c);
     c->hp.n = c->n;
+    c->hp.fext = c->fext;
     c->hp.nrep = c->nrep;
     c->hp.rep = c->nrep > 0 ? c->rep_d : nullptr;
     if (c->nrep > 0)
@@ -801,6 +803,29 @@ int db_pair_dpd(db_ctx* c, double a, double gamma, double rc, int depth) {
     P.rc = rc;
     P.inv_rc = 1.0 / rc;
     P.excl_depth = depth;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
+int db_external_force(db_ctx* c, int64_t count, const int32_t* ids, const double* f) {
+    if (!c || count < 0 || (count > 0 && (!ids || !f))) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_ESTATE, "a batch takes no external forces");
+    std::vector<double> t(3 * (size_t)c->n, 0.0);
+    for (int64_t k = 0; k < count; ++k) {
+        const int i = ids[k];
+        if (i < 0 || i >= c->n) return fail(c, DB_EINVAL, "external force %lld on invalid bead %d", (long long)k, i);
+        for (int q = 0; q < 3; ++q) {
+            if (!std::isfinite(f[3 * k + q])) return fail(c, DB_EINVAL, "non-finite external force %lld", (long long)k);
+            t[3 * (size_t)i + q] += f[3 * k + q];
+        }
+    }
+    int rc = ensure_memory(c);
+    if (rc) return rc;
+    if (c->n > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->fext, t.data(), 24 * (size_t)c->n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->hp.has_ext = count > 0 ? 1 : 0;
     c->params_dirty = true;
     return DB_OK;
 }
@@ -1366,6 +1391,7 @@ int db_batch_create(db_ctx** out, db_ctx* const* reps, int32_t nrep, void* strea
         if (!q || !q->have_state || q->nrep > 0) return DB_EINVAL;
         if (q->precision != reps[0]->precision || q->step != reps[0]->step) return DB_EINVAL;
         if (!same_physics(q->hp, reps[0]->hp)) return DB_EINVAL;
+        if (q->hp.has_ext) return DB_EINVAL;   // external forces are tied to one system's bead ids
         db_host_ext& X = ext(q);
         if (X.dev_error) return DB_ESTATE;
         if (X.dev_valid && !X.host_valid) {

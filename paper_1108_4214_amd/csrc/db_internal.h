@@ -80,6 +80,9 @@ struct Params {
     double dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
     // thermostat / integration
     double gamma, dt;
+    // constant external forces, indexed by global bead id ([3n]; read only when has_ext)
+    int has_ext;
+    const double* fext;
     // rules, in call order
     int every, pc13, pc14;
     int nrule, nmax, narule, ndrule;
@@ -176,6 +179,7 @@ struct db_ctx {
     int cur;
     double4* xnext;      // double buffer of positions for the step kernel
     double* vnext;       // double buffer of velocities (DPD: the step reads neighbour velocities)
+    double* fext;        // [3n] external force by global bead id
     double4* xsave;      // state at block start (rollback)
     double* vsave;
     db::SweepBuf sw;

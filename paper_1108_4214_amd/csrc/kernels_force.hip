@@ -719,6 +719,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         } else if (P.have_pair) {
             list_pair_forces<R>(P, X, B, NL, i, xi, a);
         }
+        if (P.has_ext) {
+            const size_t g = (size_t)meta_gid(xi);
+            a.fx += P.fext[3 * g];
+            a.fy += P.fext[3 * g + 1];
+            a.fz += P.fext[3 * g + 2];
+        }
         if (MODE == MODE_FORCES) {
             int g = meta_gid(xi);
             fout[3 * (size_t)g] = a.fx;
@@ -819,6 +825,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ 
         bond_terms<R, MODE_ENERGY>(P, X, C, B, i, xi, nb, a);
         angle_terms<R, MODE_ENERGY>(P, X, C, B, i, B.na[i], a);
         dihedral_terms<R, MODE_ENERGY>(P, X, C, B, i, B.nd[i], a);
+        if (P.has_ext) {
+            const size_t g = (size_t)meta_gid(xi);
+            a.fx += P.fext[3 * g];
+            a.fy += P.fext[3 * g + 1];
+            a.fz += P.fext[3 * g + 2];
+        }
         double Fx = a.fx, Fy = a.fy, Fz = a.fz;
         if (P.gamma != 0.0) {
             double pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
