@@ -167,6 +167,8 @@ static size_t layout(db_ctx* c, bool assign) {
     put(S.conv, n);
     put(S.newp, 4 * n);
     put(S.stats, 8 * 8);
+    put(S.aoff, 4 * (n + 1));
+    put(S.act, 4 * n);
     put(c->nlist.nl, 4 * (size_t)DB_NLCAP * n);
     put(c->nlist.cnt, n);
     put(c->halo.nu, n);
@@ -569,7 +571,7 @@ extern "C" {
 int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, void* stream) {
     if (!out) return DB_EINVAL;
     *out = nullptr;
-    if (n < 0 || !(L > 0) || !std::isfinite(L)) return DB_EINVAL;
+    if (n < 0 || n > DB_MAX_BEADS || !(L > 0) || !std::isfinite(L)) return DB_EINVAL;
     if (precision != DB_FP64 && precision != DB_MIXED) return DB_EINVAL;
     db_ctx* c = new db_ctx();
     c->hx = new db_host_ext();

@@ -1,5 +1,6 @@
 // Neighbour scan over the cell list.  The cell sort also writes a float copy of
-// every position in list order (x, y, z and the slot), so the beads of the 27
+// every position in list order (x, y, z and a word holding the slot, the type and
+// the reactive flag), so the beads of the 27
 // cells around a bead are nine contiguous runs of that array (the three cells of
 // an x-row are adjacent unless the row wraps).  Runs are read four entries at a
 // time so that several loads are in flight per thread.  The float distance only
@@ -19,7 +20,8 @@ __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
     return d < -hL ? hi : r;
 }
 
-// f(j, r2f) for every j != i in the cells around xi with float r2 < cut2.
+// f(j, w) for every slot j != i in the cells around xi with float r2 < cut2; w is
+// the entry's word (slot, type, reactive flag: xs_slot / xs_type / xs_reactive).
 // With three or more cells per edge, the periodic image of a neighbour cell is
 // fixed by whether its index wrapped, so the bead's own coordinates are shifted
 // once per run and the candidates need no minimum-image test (the true nearest
@@ -90,11 +92,12 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
 #pragma unroll
                 for (int q = 0; q < DB_SCAN_W; ++q) {
                     // one branch per candidate: range, self and distance folded into one predicate
-                    const int j = __float_as_int(e[q].w);
+                    const int w = __float_as_int(e[q].w);
+                    const int j = xs_slot(w);
                     const float dx = e[q].x - (p + q < len0 ? px : qx1), dy = e[q].y - qy, dz = e[q].z - qz;
                     const float r2 = (dx * dx + dy * dy) + dz * dz;
                     const bool hit = (p + q < len) & (j != i) & (r2 < cut2);
-                    if (hit) f(j, r2);
+                    if (hit) f(j, w);
                 }
             }
         }
@@ -109,12 +112,13 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
                 const int s0 = cstart[c], s1 = cstart[c + 1];
                 for (int p = s0; p < s1; ++p) {
                     const float4 e = xs[p];
-                    const int j = __float_as_int(e.w);
+                    const int w = __float_as_int(e.w);
+                    const int j = xs_slot(w);
                     const float dx = fmin_image(e.x - px, Lf, hLf);
                     const float dy = fmin_image(e.y - py, Lf, hLf);
                     const float dz = fmin_image(e.z - pz, Lf, hLf);
                     const float r2 = (dx * dx + dy * dy) + dz * dz;
-                    if ((j != i) & (r2 < cut2)) f(j, r2);
+                    if ((j != i) & (r2 < cut2)) f(j, w);
                 }
             }
         }

@@ -107,6 +107,17 @@ __host__ __device__ inline double pack_meta(int gid, int type, int reactive, int
     return d;
 }
 
+// The word stored with each entry of the cell-ordered float position copy: the
+// slot, the bead type and the reactive flag, so that scans can reject candidates
+// by type before reading anything else of them.
+__device__ __forceinline__ float xs_word(int slot, int meta) {
+    return __int_as_float((int)((uint32_t)slot | ((uint32_t)meta_type(meta) << DB_SLOT_BITS) |
+                                ((uint32_t)meta_reactive(meta) << 31)));
+}
+__device__ __forceinline__ int xs_slot(int w) { return w & DB_MAX_BEADS; }
+__device__ __forceinline__ int xs_type(int w) { return (int)(((uint32_t)w >> DB_SLOT_BITS) & 31u); }
+__device__ __forceinline__ bool xs_reactive(int w) { return ((uint32_t)w >> 31) != 0u; }
+
 // The box of a bead: the system's own, or in a batch the replica's (BATCH is a
 // template flag of the kernels, so the single-system path reads uniform values).
 template <bool BATCH>

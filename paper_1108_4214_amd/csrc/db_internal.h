@@ -19,6 +19,8 @@
 #define DB_MAXU 8            // bonded halo entries per bead (codes hold 3-bit indices)
 #define DB_HALO_OVF 255      // halo marker: more than DB_MAXU distinct bonded partners
 #define DB_VMAX_SPREAD 64    // words per step over which the speed maxima are spread
+#define DB_SLOT_BITS 26      // the float position copy packs slot | type << 26 | reactive << 31
+#define DB_MAX_BEADS ((1 << DB_SLOT_BITS) - 1)
 
 namespace db {
 
@@ -123,6 +125,9 @@ struct SweepBuf {
     uint8_t* conv;    // bead takes part in an accepted conversion
     int* newp;        // partner slot of this bead's new (created or converted) bond, or -1
     unsigned long long* stats;   // [8] counters of the sweep
+    int* aoff;        // [n + 1] 0/1 flags of the beads that may nominate a creation partner,
+                      // then their exclusive prefix sums; aoff[n] = their number
+    int* act;         // [n] those beads in slot order
 };
 
 // Verlet neighbour list: entry k of bead s at nl[k * n + s] (slots), count in cnt
@@ -146,7 +151,7 @@ struct Cells {
     int* cnt;         // [ncell]
     int* start;       // [ncell + 1]
     int* list;        // [n] slots, cell by cell, ascending within a cell
-    float4* xs;       // [n] in list order: float x, y, z and the slot (bits) of each entry
+    float4* xs;       // [n] in list order: float x, y, z and (bits) slot | type << 26 | reactive << 31
     int* cellid;      // [n]
     int* rank;        // [n] place of the bead among the beads of its cell
     int* blocksum;    // scan scratch

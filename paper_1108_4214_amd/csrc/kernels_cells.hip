@@ -176,7 +176,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_cellsort(int ncell, const int* __r
     for (int a = s0; a < s1; ++a) {
         int j = list[a];
         double4 xj = x[j];
-        xs[a] = make_float4((float)xj.x, (float)xj.y, (float)xj.z, __int_as_float(j));
+        xs[a] = make_float4((float)xj.x, (float)xj.y, (float)xj.z, xs_word(j, meta_word(xj)));
     }
 }
 
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_permute(int n, Bank src, Bank dst,
         dst.dt[k * n + s] = src.dt[k * n + o];
     }
     list[s] = s;   // the cells now hold contiguous slot ranges
-    xs[s].w = __int_as_float(s);
+    xs[s].w = xs_word(s, meta_word(x));
 }
 
 void launch_permute(db_ctx* c, bool save) {

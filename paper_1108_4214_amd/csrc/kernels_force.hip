@@ -251,7 +251,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         for (int m = 0; m < DB_MAXB; ++m) two[k * DB_MAXB + m] = m < nq ? B.bp[m * n + pp[k]] : -1;
     }
     int cnt = 0;
-    scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, float) {
+    scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, int) {
         if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
         if (depth2 && nb > 0) {
             bool ex = false;

@@ -82,6 +82,19 @@ __device__ __forceinline__ void stat_add(unsigned long long* st, int k, unsigned
 // rules in call order (the last applicable one wins), maxbond on both beads and
 // the graph distance; the closest survivor (ties: lower id) is nominated.
 
+// bead types that some creation rule pairs with type ti (a superset of the
+// partners that can pass every test: distance and maxbond are not looked at)
+__device__ __forceinline__ uint32_t create_partner_types(const Params& P, int ti) {
+    uint32_t m = 0;
+    for (int q = 0; q < P.nrule; ++q) {
+        const Rule& r = P.rule[q];
+        if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
+        if (type_ok(r.b1, ti)) m |= r.b2 == 0 ? 0xFFFFFFFFu : 1u << r.b2;
+        if (type_ok(r.b2, ti)) m |= r.b1 == 0 ? 0xFFFFFFFFu : 1u << r.b1;
+    }
+    return m;
+}
+
 // some creation rule admits a bead of type ti holding table Ti in one of its two
 // roles (type and maxbond)
 __device__ __forceinline__ bool create_admits(const Params& P, int ti, const Tab& Ti) {
@@ -94,14 +107,32 @@ __device__ __forceinline__ bool create_admits(const Params& P, int ti, const Tab
     return false;
 }
 
+// The beads that may nominate a creation partner (reactive, of a type some
+// creation rule names, with room for one of its bond types under maxbond) are
+// flagged by the breakage nomination, which reads every bead's table anyway; the
+// flags are scanned and the beads listed in slot order, so that the creation scan
+// runs on full wavefronts.
+__global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
+    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int o = S.aoff[i];
+    if (S.aoff[i + 1] > o) S.act[o] = i;
+}
+
+// one thread per listed bead; the grid covers every bead, the workgroups past the
+// list's end return at once
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
                                                               const int* __restrict__ cstart,
                                                               const float4* __restrict__ xs, SweepBuf S) {
     const Params& P = *Pp;
     const int n = P.n;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
+    const int nl = S.aoff[n];
+    const int ntile = (nl + DB_BLOCK - 1) / DB_BLOCK;
+    if ((int)blockIdx.x >= ntile) return;
+    const int t = xcd_tile(blockIdx.x, ntile) * DB_BLOCK + threadIdx.x;   // listed range split per XCD
+    if (t >= nl) return;
+    const int i = S.act[t];
     const double4 xi = B.x[i];
     const int mi = meta_word(xi);
     const Box& X = box_of<BATCH>(P, mi);
@@ -109,15 +140,25 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
     const int gi = meta_gid(xi);
     int best = -1, best_rule = -1, best_bt = 0, best_g = 0;
     double best_r2 = 0.0;
-    bool can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
-    const Tab Ti = can ? load_tab(B, n, i) : Tab{0, -1, -1, -1, -1, 0, 0, 0, 0};
-    can = can && create_admits(P, ti, Ti);
-    if (can) {
+    const Tab Ti = load_tab(B, n, i);
+    {
         const float cut2 = (float)(P.rmax2_create * 1.0001);
-        scan_cells(X, cstart, xs, i, xi, cut2, [&](int j, float) {
+        // types and reactivity ride in the scan's words: most candidates are
+        // rejected before anything else of them is read
+        const uint32_t partner_types = create_partner_types(P, ti);
+        // the beads two bonds away, gathered once for the distance-3 test
+        int two[DB_MAXB * DB_MAXB];
+#pragma unroll
+        for (int a = 0; a < DB_MAXB; ++a) {
+            const int q = Ti.p(a);
+            const int nq = (!P.pc14 && a < Ti.n) ? B.nb[q] : 0;
+#pragma unroll
+            for (int b = 0; b < DB_MAXB; ++b) two[a * DB_MAXB + b] = b < nq ? B.bp[b * n + q] : -1;
+        }
+        scan_cells(X, cstart, xs, i, xi, cut2, [&](int j, int w) {
+            if (!xs_reactive(w) || !((partner_types >> xs_type(w)) & 1u)) return;
             const double4 xj = B.x[j];
             const int mj = meta_word(xj);
-            if (!meta_reactive(mj)) return;
             double dx, dy, dz;
             const double r2 = separation(X, xi, xj, dx, dy, dz);
             if (!(r2 < P.rmax2_create)) return;
@@ -154,11 +195,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
                 if (tab_has(Tj, Ti.p(a))) d2 = true;
             if (d2 && !P.pc13) return;
             if (!d2 && !P.pc14) {
-                for (int a = 0; a < Ti.n; ++a) {
-                    const Tab Tq = load_tab(B, n, Ti.p(a));
-                    for (int b = 0; b < Tj.n; ++b)
-                        if (tab_has(Tq, Tj.p(b))) return;
+                // distance 3: a partner of j is a partner of a partner of i
+                bool d3 = false;
+#pragma unroll
+                for (int b = 0; b < DB_MAXB; ++b) {
+                    const int pj = Tj.p(b);
+                    if (b < Tj.n) {
+#pragma unroll
+                        for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) d3 |= two[k] == pj;
+                    }
                 }
+                if (d3) return;
             }
             if (best < 0 || r2 < best_r2 || (r2 == best_r2 && gj < best_g)) {
                 best = j;
@@ -189,6 +236,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
     double best_r2 = 0.0;
     int rm = 0;
     unsigned long long killed_here = 0;
+    {
+        // creation: flag the bead for the creation scan's list; its nomination starts empty
+        const int ti = meta_type(mi);
+        bool can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
+        if (can) can = create_admits(P, ti, load_tab(B, n, i));
+        S.aoff[i] = can ? 1 : 0;
+        S.nomC[i] = -1;
+        S.ruleC[i] = -1;
+        S.btC[i] = 0;
+    }
     if (meta_reactive(mi) && (P.has_kill || P.has_break_class)) {
         Tab Ti = load_tab(B, n, i);
         int ti = meta_type(mi);
@@ -570,9 +627,11 @@ static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOC
 template <bool BATCH>
 static void sweep_kernels(db_ctx* c, const Bank& B, unsigned g, int64_t step) {
     hipStream_t s = c->stream;
+    hipLaunchKernelGGL(k_nominate_break<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
+    launch_exclusive_scan(c->sw.aoff, c->n, nullptr, c->cells.blocksum, s);
+    hipLaunchKernelGGL(k_create_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
     hipLaunchKernelGGL(k_nominate_create<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
                        c->cells.xs, c->sw);
-    hipLaunchKernelGGL(k_nominate_break<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
     hipLaunchKernelGGL(k_resolve<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step);
     hipLaunchKernelGGL(k_apply<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step, c->err_d);
 }
