@@ -73,6 +73,8 @@ typedef struct {
      * at fixed positions, and its sum over all sweeps; 0 while not tracked
      * (db_track_topology_energy) */
     double du_topo_last, du_topo_cum;
+    int64_t list_patches;    /* blocks that kept the Verlet list across their sweep and redid only the
+                                lists of the beads whose exclusions changed */
 } db_stats;
 
 /* ---- lifecycle ---------------------------------------------------------------- */

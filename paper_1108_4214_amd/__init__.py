@@ -46,10 +46,12 @@ STAT_FIELDS = [
 
 
 LEDGER_FIELDS = ["du_topo_last", "du_topo_cum"]
+TAIL_FIELDS = ["list_patches"]
 
 
 class db_stats(C.Structure):
-    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS] + [(f, C.c_double) for f in LEDGER_FIELDS]
+    _fields_ = ([(f, C.c_int64) for f in STAT_FIELDS] + [(f, C.c_double) for f in LEDGER_FIELDS] +
+                [(f, C.c_int64) for f in TAIL_FIELDS])
 
 
 class DynBondError(RuntimeError):
@@ -358,6 +360,7 @@ def db_get_stats(ctx):
     _check(ctx, _lib.db_get_stats(ctx, C.byref(s)))
     out = {f: int(getattr(s, f)) for f in STAT_FIELDS}
     out.update({f: float(getattr(s, f)) for f in LEDGER_FIELDS})
+    out.update({f: int(getattr(s, f)) for f in TAIL_FIELDS})
     return out
 
 

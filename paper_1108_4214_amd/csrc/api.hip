@@ -153,6 +153,7 @@ static size_t layout(db_ctx* c, bool assign) {
     }
     put(c->xnext, 32 * n);
     put(c->vnext, 24 * n);
+    put(c->xref, 32 * n);
     put(c->fext, 24 * n);
     put(c->xsave, 32 * n);
     put(c->vsave, 24 * n);
@@ -169,6 +170,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(S.stats, 8 * 8);
     put(S.aoff, 4 * (n + 1));
     put(S.act, 4 * n);
+    put(S.chg, n);
     put(c->nlist.nl, 4 * (size_t)DB_NLCAP * n);
     put(c->nlist.cnt, n);
     put(c->halo.nu, n);
@@ -289,6 +291,7 @@ static int upload_params(db_ctx* c) {
                                  c->stream));
     HIPCHK(c, hipMemcpyAsync(c->dp, &c->hp, sizeof(Params), hipMemcpyHostToDevice, c->stream));
     c->params_dirty = false;
+    c->list_valid = false;   // the grid or the cutoffs may have changed
     return DB_OK;
 }
 
@@ -378,6 +381,7 @@ static int upload_system(db_ctx* c) {
     X.dev_valid = true;
     X.dev_error = 0;
     c->halo_force = true;
+    c->list_valid = false;
     launch_fill_int(c->err_d, 0, 16, s);
     return DB_OK;
 }
@@ -595,6 +599,10 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->params_dirty = true;
     c->skin = kSkinDefault;
     c->skin_tuned = false;
+    c->list_valid = false;
+    c->list_disp = 0.0;
+    c->disp_rate = 0.0;
+    c->patches = 0;
     c->swept_step = -1;
     c->rebuild_interval = 8;
     c->permute_every = 8;
@@ -1032,7 +1040,7 @@ static int run_sweep(db_ctx* c, int64_t step) {
     return DB_OK;
 }
 
-static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save, bool ref) {
+static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save) {
     if (c->profile) {
         if ((size_t)c->ev_used + 2 > c->ev_pool.size()) {
             for (int k = 0; k < 2 * kMaxBlock; ++k) {
@@ -1042,11 +1050,11 @@ static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save, bool 
             }
         }
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
-        launch_step(c, step, slot, save, ref);
+        launch_step(c, step, slot, save);
         HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     } else {
-        launch_step(c, step, slot, save, ref);
+        launch_step(c, step, slot, save);
     }
     return DB_OK;
 }
@@ -1062,6 +1070,16 @@ static int harvest_events(db_ctx* c) {
     return DB_OK;
 }
 
+// The list can be kept across sweeps when pairs interact and every box has at
+// least five cells per edge (the patched lists scan two cell edges around a bead).
+static bool list_reuse_allowed(const db_ctx* c) {
+    if (!c->hp.have_pair || c->hp.every <= 0 || !std::isfinite(skin_of(c))) return false;
+    if (c->nrep == 0) return c->hp.box.nc >= 5;
+    for (const Box& X : c->reps)
+        if (X.nc < 5) return false;
+    return true;
+}
+
 int db_step(db_ctx* c, int64_t nsteps) {
     if (!c || nsteps < 0) return DB_EINVAL;
     int rc = ready(c);
@@ -1072,26 +1090,53 @@ int db_step(db_ctx* c, int64_t nsteps) {
     const int every = c->hp.every;
     const double skin = skin_of(c);
     const bool track = c->hp.have_pair && c->hp.pair_style == PAIR_DPD;   // displacement, not speed
+    const bool reuse_ok = list_reuse_allowed(c);
+    // widest cutoff of a redone list whose expected length, at the densest box's
+    // density, stays within half the list's capacity
+    double dens = (double)c->n / (c->L * c->L * c->L);
+    for (size_t r = 0; r < c->reps.size(); ++r)
+        dens = std::max(dens, (double)c->rep_n[r] / (c->reps[r].L * c->reps[r].L * c->reps[r].L));
+    const double reuse_cut_max = dens > 0 ? std::cbrt(0.5 * DB_NLCAP / (4.18879020478639 * dens)) : INFINITY;
     hipStream_t s = c->stream;
     while (nsteps > 0) {
         const int64_t k0 = c->step;
         const bool sweep_due = every > 0 && k0 % every == 0 && c->swept_step != k0;
         int64_t len = std::min<int64_t>(nsteps, std::min(c->rebuild_interval, kMaxBlock));
         if (every > 0) len = std::min<int64_t>(len, every - (k0 % every));
-        const bool permute = (c->rebuild_count++ % c->permute_every) == 0;
+        // A block cut short by its sweep keeps the Verlet list when the displacement
+        // bound since the list's full build, grown by this block, stays within half
+        // the skin: only the lists of beads whose exclusions the sweep changed are
+        // redone, with the cutoff widened by twice that bound (so that every list
+        // stays valid while the bound does).
+        const double grow = (track ? c->disp_rate : dt * c->vmax_est) * (double)len;
+        const double patch_cut = std::sqrt(c->hp.rc2) + c->skin + 2.0 * c->list_disp;
+        const bool reuse = reuse_ok && sweep_due && c->list_valid && c->list_disp + 1.25 * grow <= skin &&
+                           patch_cut <= reuse_cut_max;
+        const double d0 = reuse ? c->list_disp : 0.0;   // bound at the block's input
+        bool permute = false;
         const bool guard = std::isfinite(skin) && len > 1;
-        rebuild(c, permute, guard);
-        if (sweep_due) {
+        if (reuse) {
+            rebuild(c, false);   // current cells for the sweep and the patched lists
             rc = run_sweep(c, k0);
             if (rc) return rc;
             c->swept_step = k0;
+            launch_patch_nlist(c, patch_cut);
+            c->patches++;
+        } else {
+            permute = (c->rebuild_count++ % c->permute_every) == 0;
+            rebuild(c, permute, guard);
+            if (sweep_due) {
+                rc = run_sweep(c, k0);
+                if (rc) return rc;
+                c->swept_step = k0;
+            }
+            launch_build_nlist(c);   // after the sweep: exclusions follow the new bonds
         }
-        launch_build_nlist(c);   // after the sweep: exclusions follow the new bonds
         launch_fill_int((int*)c->vmax2, 0, (size_t)len * DB_VMAX_SPREAD, s);
         // the block's input state is kept for a re-run: by the reorder, or else by
         // the first step kernel of the block
         for (int64_t q = 0; q < len; ++q) {
-            rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0, guard && q > 0);
+            rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0);
             if (rc) return rc;
         }
         hipLaunchKernelGGL(k_report, dim3(1), dim3(kMaxBlock), 0, s, c->vmax2, (int)len, c->err_d, c->sw.stats,
@@ -1107,16 +1152,17 @@ int db_step(db_ctx* c, int64_t nsteps) {
         rc = check_device_error(c);
         if (rc) return rc;
         // bound: how far any bead may be from where the list was built, at the
-        // input of the block's last step
-        double bound = 0.0, vmax = 0.0, dlast = 0.0;
+        // input of the block's last step; dlast: the same at the block's output
+        double bound = d0, vmax = 0.0, dlast = d0;
         for (int64_t q = 0; q < len; ++q) {
             double v = std::sqrt((double)pin->vmax2[q]);
-            if (track) {
+            if (track) {   // measured from the full build's positions
                 if (q + 1 < len) bound = std::max(bound, v);
                 dlast = v;
             } else {
                 vmax = std::max(vmax, v);
                 if (q + 1 < len) bound += dt * v;
+                dlast += dt * v;
             }
         }
         if (guard && bound > skin) {
@@ -1135,6 +1181,11 @@ int db_step(db_ctx* c, int64_t nsteps) {
             rc = check_device_error(c);
             if (rc) return rc;
             c->rebuild_interval = std::max<int>(1, (int)(len / 2));
+            c->list_valid = false;
+        } else if (reuse) {
+            // the interval follows full builds only
+            c->list_disp = dlast;
+            c->disp_rate = std::max(0.0, dlast - d0) / (double)len;
         } else if (track && std::isfinite(skin)) {
             // extrapolate the largest displacement linearly in time from the block's
             // end (exact for ballistic motion, cautious for diffusive motion, so the
@@ -1146,6 +1197,11 @@ int db_step(db_ctx* c, int64_t nsteps) {
             c->rebuild_interval = std::max(1, std::min(kMaxBlock, want));
         } else if (!std::isfinite(skin)) {
             c->rebuild_interval = kMaxBlock;
+        }
+        if (!reuse && !(guard && bound > skin)) {
+            c->list_valid = true;
+            c->list_disp = dlast;
+            c->disp_rate = dlast / (double)len;
         }
         c->vmax_est = vmax;
         c->step += len;
@@ -1160,6 +1216,7 @@ int db_sweep_now(db_ctx* c) {
     if (rc) return rc;
     if (c->swept_step == c->step) return fail(c, DB_ESTATE, "the sweep of step %lld was already done", (long long)c->step);
     rebuild(c, (c->rebuild_count++ % c->permute_every) == 0);
+    c->list_valid = false;
     rc = run_sweep(c, c->step);
     if (rc) return rc;
     Pinned* pin = ext(c).pin;
@@ -1287,6 +1344,7 @@ int db_get_stats(db_ctx* c, db_stats* o) {
     o->rollbacks = c->rollbacks;
     o->du_topo_last = c->du_last;
     o->du_topo_cum = c->du_cum;
+    o->list_patches = c->patches;
     return DB_OK;
 }
 

@@ -125,4 +125,41 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
     }
 }
 
+// f(j, w) for every slot j != i with float r2 < cut2 in the 5 x 5 x 5 cells
+// around xi: a reach of two cell edges, for lists redone with a cutoff beyond one
+// edge.  Needs at least five cells per edge (no cell is visited twice).  Each
+// candidate takes the minimum image; this serves only the few beads whose lists
+// are redone after a sweep.
+template <class F>
+__device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, const float4* __restrict__ xs,
+                                int i, const double4& xi, float cut2, F&& f) {
+    const int nc = X.nc;
+    const int cx = cell_coord(xi.x, X.cell_scale, nc);
+    const int cy = cell_coord(xi.y, X.cell_scale, nc);
+    const int cz = cell_coord(xi.z, X.cell_scale, nc);
+    const float Lf = (float)X.L, hLf = (float)X.hL;
+    const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
+    cstart += X.cell_off;
+    for (int oz = -2; oz <= 2; ++oz) {
+        const int zz = wrap_cell(cz + oz, nc);
+        for (int oy = -2; oy <= 2; ++oy) {
+            const int row = (zz * nc + wrap_cell(cy + oy, nc)) * nc;
+            for (int ox = -2; ox <= 2; ++ox) {
+                const int c = row + wrap_cell(cx + ox, nc);
+                const int s0 = cstart[c], s1 = cstart[c + 1];
+                for (int p = s0; p < s1; ++p) {
+                    const float4 e = xs[p];
+                    const int w = __float_as_int(e.w);
+                    const int j = xs_slot(w);
+                    const float dx = fmin_image(e.x - px, Lf, hLf);
+                    const float dy = fmin_image(e.y - py, Lf, hLf);
+                    const float dz = fmin_image(e.z - pz, Lf, hLf);
+                    const float r2 = (dx * dx + dy * dy) + dz * dz;
+                    if ((j != i) & (r2 < cut2)) f(j, w);
+                }
+            }
+        }
+    }
+}
+
 }  // namespace db

@@ -126,8 +126,10 @@ struct SweepBuf {
     int* newp;        // partner slot of this bead's new (created or converted) bond, or -1
     unsigned long long* stats;   // [8] counters of the sweep
     int* aoff;        // [n + 1] 0/1 flags of the beads that may nominate a creation partner,
-                      // then their exclusive prefix sums; aoff[n] = their number
+                      // then their exclusive prefix sums; aoff[n] = their number (after the
+                      // sweep: the same for the beads whose Verlet list must be redone)
     int* act;         // [n] those beads in slot order
+    uint8_t* chg;     // the sweep created or removed (not converted) a bond of the bead
 };
 
 // Verlet neighbour list: entry k of bead s at nl[k * n + s] (slots), count in cnt
@@ -183,6 +185,7 @@ struct db_ctx {
     db::Bank bank[2];
     int cur;
     double4* xnext;      // double buffer of positions for the step kernel
+    double4* xref;       // positions at the last full Verlet-list build (slot order)
     double* vnext;       // double buffer of velocities (DPD: the step reads neighbour velocities)
     double* fext;        // [3n] external force by global bead id
     double4* xsave;      // state at block start (rollback)
@@ -193,6 +196,12 @@ struct db_ctx {
     db::Halo halo;
     bool halo_force;     // slots or tables changed: rebuild the halo
     bool halo_sweep;     // a sweep ran since the last halo build: rebuild it if the sweep changed bonds
+    // Verlet list kept across sweeps: valid for the current slots and topology, and
+    // list_disp bounds how far any bead has moved since its full build
+    bool list_valid;
+    double list_disp;
+    double disp_rate;    // growth of that bound per step seen lately
+    int64_t patches;     // blocks that kept the list and redid only the changed beads' lists
     // a batch of independent replicas (nrep > 0): one box per replica
     int nrep;
     std::vector<db::Box> reps;   // host copy; cell_off and gid_off fixed at creation
@@ -240,10 +249,13 @@ void launch_permute(db_ctx* c, bool save);           // reorder all per-bead sta
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s);
 
 // kernels_force.hip
-void launch_build_nlist(db_ctx* c);                  // Verlet list from the current cell list
-// save: keep the input x, v (the block's reference state); ref: that state is in
-// the rollback buffers (steps after the block's first)
-void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save = false, bool ref = false);
+void launch_halo(db_ctx* c);                         // bonded halo, if slots or tables changed
+void launch_build_nlist(db_ctx* c);                  // halo, then the Verlet list from the current cell list
+// Verlet lists of the beads whose exclusions the last sweep changed, with cutoff
+// cut (the list cutoff plus twice the displacement since the full build)
+void launch_patch_nlist(db_ctx* c, double cut);
+// save: keep the input x, v (the block's input state, for a re-run)
+void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save = false);
 void launch_forces(db_ctx* c, double* f_gid_order);
 void launch_energy(db_ctx* c, double* out6_device);
 

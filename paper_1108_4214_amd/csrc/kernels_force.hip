@@ -221,16 +221,33 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
 // skin) that is not excluded, from the 27 cells of the current cell list.  The
 // float prefilter carries a 1e-4 relative margin, so the list is a superset of
 // the pairs within the cutoff in double.
-template <bool BATCH>
+// The full build (list == nullptr: every bead, and its position is kept in xref
+// as the list's reference) or the patch after a sweep (list: the beads whose
+// exclusions changed, count at list_n; cut2 then exceeds the list cutoff by the
+// displacement margin and the wide stencil reaches it).
+template <bool BATCH, bool WIDE>
 __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restrict__ Pp, Bank B,
                                                           const int* __restrict__ cstart,
                                                           const float4* __restrict__ xs, NList NL,
-                                                          int* __restrict__ err) {
+                                                          int* __restrict__ err, double4* __restrict__ xref,
+                                                          const int* __restrict__ list,
+                                                          const int* __restrict__ list_n, float cut2) {
     const Params& P = *Pp;
     const int n = P.n;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
+    int i;
+    if (WIDE) {
+        const int nl = *list_n;
+        const int ntile = (nl + DB_BLOCK - 1) / DB_BLOCK;
+        if ((int)blockIdx.x >= ntile) return;
+        const int t = xcd_tile(blockIdx.x, ntile) * DB_BLOCK + threadIdx.x;
+        if (t >= nl) return;
+        i = list[t];
+    } else {
+        i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
+        if (i >= n) return;
+    }
     const double4 xi = B.x[i];
+    if (!WIDE) xref[i] = xi;
     const int nb = B.nb[i];
     const int p0 = nb > 0 ? B.bp[i] : -1;
     const int p1 = nb > 1 ? B.bp[n + i] : -1;
@@ -251,7 +268,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         for (int m = 0; m < DB_MAXB; ++m) two[k * DB_MAXB + m] = m < nq ? B.bp[m * n + pp[k]] : -1;
     }
     int cnt = 0;
-    scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), [&](int j, int) {
+    auto visit = [&](int j, int) {
         if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
         if (depth2 && nb > 0) {
             bool ex = false;
@@ -261,7 +278,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         }
         if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
         ++cnt;
-    });
+    };
+    if (WIDE) scan_cells_wide(X, cstart, xs, i, xi, cut2, visit);
+    else scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), visit);
     if (cnt > DB_NLCAP) {
         atomicOr(err, ERR_NLIST);
         cnt = DB_NLCAP;
@@ -675,8 +694,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // The new velocities go to vout, which is B.v itself unless the DPD thermostat
 // reads the neighbours' input velocities.  Each step reports the workgroup maxima
 // of |v|^2 (WCA) or, with DPD, of the squared displacement of the new position
-// from the block's reference position xref (the list build's; nullptr at the
-// block's first step, whose input is that position).
+// from xref, the position at the last full Verlet-list build.
 template <typename R, int MODE, bool BATCH, int PAIR>
 __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
                                                     double4* __restrict__ xout, double* vout, int64_t step,
@@ -766,7 +784,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
             bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
             if (bad) atomicOr(err, ERR_NONFINITE);
             if (PAIR == PAIR_DPD) {
-                const double4 r = xref ? xref[i] : xi;
+                const double4 r = xref[i];
                 const double ex = near_image(xo.x - r.x, X), ey = near_image(xo.y - r.y, X),
                              ez = near_image(xo.z - r.z, X);
                 m2 = (ex * ex + ey * ey) + ez * ez;
@@ -875,19 +893,66 @@ __global__ void k_energy_final(const double* __restrict__ epart, int nblocks, do
 
 static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK); }
 
-void launch_build_nlist(db_ctx* c) {
+void launch_halo(db_ctx* c) {
     if (c->n == 0) return;
     if (c->halo_force || c->halo_sweep)
         hipLaunchKernelGGL(k_halo, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
                            c->halo, c->halo_force ? (const unsigned long long*)nullptr : c->sw.stats);
     c->halo_force = false;
     c->halo_sweep = false;
+}
+
+void launch_build_nlist(db_ctx* c) {
+    if (c->n == 0) return;
+    launch_halo(c);
     if (c->nrep > 0)
-        hipLaunchKernelGGL(k_build_nlist<true>, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d);
+        hipLaunchKernelGGL((k_build_nlist<true, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, c->xref, nullptr,
+                           nullptr, 0.0f);
     else
-        hipLaunchKernelGGL(k_build_nlist<false>, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d);
+        hipLaunchKernelGGL((k_build_nlist<false, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, c->xref, nullptr,
+                           nullptr, 0.0f);
+}
+
+// beads whose exclusions the sweep changed: a changed bond table, or (exclusion
+// depth 2) a partner whose table changed
+__global__ __launch_bounds__(DB_BLOCK) void k_patch_flags(const Params* __restrict__ Pp, Bank B, SweepBuf S) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    bool d = S.chg[i] != 0;
+    if (!d && P.excl_depth >= 2) {
+        const int nb = B.nb[i];
+        for (int k = 0; k < nb; ++k) d |= S.chg[B.bp[k * n + i]] != 0;
+    }
+    S.aoff[i] = d ? 1 : 0;
+}
+
+__global__ __launch_bounds__(DB_BLOCK) void k_patch_list(int n, SweepBuf S) {
+    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int o = S.aoff[i];
+    if (S.aoff[i + 1] > o) S.act[o] = i;
+}
+
+void launch_patch_nlist(db_ctx* c, double cut) {
+    if (c->n == 0) return;
+    launch_halo(c);
+    hipStream_t s = c->stream;
+    const unsigned g = grid_for(c->n);
+    Bank& B = c->bank[c->cur];
+    hipLaunchKernelGGL(k_patch_flags, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
+    launch_exclusive_scan(c->sw.aoff, c->n, nullptr, c->cells.blocksum, s);
+    hipLaunchKernelGGL(k_patch_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
+    const float cut2 = (float)(cut * cut * 1.0001);
+    if (c->nrep > 0)
+        hipLaunchKernelGGL((k_build_nlist<true, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
+                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut2);
+    else
+        hipLaunchKernelGGL((k_build_nlist<false, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
+                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut2);
 }
 
 // temperature of the single system's box at a step
@@ -918,44 +983,44 @@ static bool velocity_double_buffer(const db_ctx* c) {
 
 template <typename R, int MODE, bool BATCH, int PAIR>
 static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
-                               double dsig, unsigned* vm, double* f, bool save, bool ref) {
+                               double dsig, unsigned* vm, double* f, bool save) {
     hipLaunchKernelGGL((k_step<R, MODE, BATCH, PAIR>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                        B, c->nlist, c->halo, xout, vout, step, pref, dsig, vm, f, c->err_d,
-                       save ? c->xsave : nullptr, save ? c->vsave : nullptr, ref ? c->xsave : nullptr);
+                       save ? c->xsave : nullptr, save ? c->vsave : nullptr, c->xref);
 }
 
 template <int MODE, int PAIR>
 static void launch_step_pair(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
-                             double dsig, unsigned* vm, double* f, bool save, bool ref) {
+                             double dsig, unsigned* vm, double* f, bool save) {
     const bool batch = c->nrep > 0;
     if (c->precision == DB_MIXED) {
-        if (batch) launch_step_kernel<float, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
-        else launch_step_kernel<float, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+        if (batch) launch_step_kernel<float, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
+        else launch_step_kernel<float, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
     } else {
         if (batch)
-            launch_step_kernel<double, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+            launch_step_kernel<double, MODE, true, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
         else
-            launch_step_kernel<double, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+            launch_step_kernel<double, MODE, false, PAIR>(c, B, xout, vout, step, pref, dsig, vm, f, save);
     }
 }
 
 template <int MODE>
 static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, double* vout, int64_t step, double pref,
-                            double dsig, unsigned* vm, double* f, bool save = false, bool ref = false) {
+                            double dsig, unsigned* vm, double* f, bool save = false) {
     if (c->hp.have_pair && c->hp.pair_style == PAIR_DPD)
-        launch_step_pair<MODE, PAIR_DPD>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+        launch_step_pair<MODE, PAIR_DPD>(c, B, xout, vout, step, pref, dsig, vm, f, save);
     else
-        launch_step_pair<MODE, PAIR_WCA>(c, B, xout, vout, step, pref, dsig, vm, f, save, ref);
+        launch_step_pair<MODE, PAIR_WCA>(c, B, xout, vout, step, pref, dsig, vm, f, save);
 }
 
-void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save, bool ref) {
+void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
     if (c->n == 0) return;
     const double pref = langevin_prefactor(c->hp, step);
     const double dsig = dpd_sigma(c->hp, step);
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
     const bool vbuf = velocity_double_buffer(c);
-    launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save, ref);
+    launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save);
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;

@@ -242,6 +242,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         bool can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
         if (can) can = create_admits(P, ti, load_tab(B, n, i));
         S.aoff[i] = can ? 1 : 0;
+        S.chg[i] = 0;
         S.nomC[i] = -1;
         S.ruleC[i] = -1;
         S.btC[i] = 0;
@@ -390,6 +391,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
     const int conv = S.conv[i];
     const int nb = B.nb[i];
     w = nb;
+    bool changed = false;   // the bead's bond graph changed (a conversion keeps it)
     if (rm > 0) {
         const int convp = conv ? S.newp[i] : -1;
         w = 0;
@@ -397,6 +399,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
             int j = B.bp[k * n + i];
             int t = B.bt[k * n + i];
             if (bond_removed(S, n, i, j)) {
+                changed |= j != convp;
                 if (j != convp) continue;
                 t = P.rule[S.ruleK[i]].bt2;   // converted: same partner, new type
             }
@@ -420,9 +423,11 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
                 ++w;
             }
             S.newp[i] = j;
+            changed = true;
             if (gi < gj) stat_add(S.stats, ST_CREATED, 1);
         }
     }
+    if (changed) S.chg[i] = 1;
     if (w != nb) B.nb[i] = (uint8_t)w;
     stat_add(S.stats, ST_ANG_DEL, ang_del);
     stat_add(S.stats, ST_DIH_DEL, dih_del);

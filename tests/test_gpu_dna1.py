@@ -142,3 +142,4 @@ def test_full_size_three_swept_steps(dna1_workload):
     o.step(3)
     assert same_topology(g, o), topo_diff(g, o)
     assert np.abs(_wrapped_diff(g.state()[0], o.state()[0], s.L)).max() < 1e-9
+
