@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--no-dna1", action="store_true", help="skip the 1-bead DNA model measurement")
     ap.add_argument("--accuracy", action="store_true",
                     help="also report mixed-vs-FP64 accuracy: force error, hybridized-fraction ramp, NVE drift")
+    ap.add_argument("--leg", choices=["dpd", "dna1", "batch"], default=None,
+                    help="run only this extra workload and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the traffic counters)")
     args = ap.parse_args()
@@ -317,10 +319,17 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.leg is not None:
+        legs = {"dpd": lambda: run_dpd(args.steps, args.warmup), "dna1": lambda: run_dna1(args.steps, args.warmup),
+                "batch": lambda: run_batch(max(100, args.steps // 4), min(args.warmup, 50))}
+        print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
+        return
     w = synth.c3()
     every = w.rules.every
     mixed = run_gpu(w, 1, args.steps, args.warmup, args.skin, args.permute_every)
+    log(f"bench: mixed {mixed['ms_per_step']:.4f} ms/step")
     fp64 = run_gpu(w, 0, args.steps, args.warmup, args.skin, args.permute_every)
+    log(f"bench: fp64 {fp64['ms_per_step']:.4f} ms/step")
     b, a, d = mixed["topology_per_bead"]
     kernel_bytes, step_bytes = algorithmic_bytes_per_bead_step(b, a, d, every)
     n = w.system.n
@@ -363,12 +372,16 @@ def main():
         line["accuracy"] = run_accuracy()
     if not args.no_batch:
         line["batch"] = run_batch(max(100, args.steps // 4), min(args.warmup, 50))
+        log("bench: replica ladder done")
     if not args.no_dpd:
         line["dpd"] = run_dpd(args.steps, args.warmup)
+        log("bench: DPD solution done")
     if not args.no_dna1:
         line["dna1"] = run_dna1(args.steps, args.warmup)
+        log("bench: 1-bead model done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        log("bench: CPU oracle done")
     print(json.dumps(line), flush=True)
 
 

@@ -221,8 +221,8 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
 // skin) that is not excluded, from the 27 cells of the current cell list.  The
 // float prefilter carries a 1e-4 relative margin, so the list is a superset of
 // the pairs within the cutoff in double.
-// The full build (list == nullptr: every bead, and its position is kept in xref
-// as the list's reference) or the patch after a sweep (list: the beads whose
+// The full build (list == nullptr: every bead, and with DPD its position is kept
+// in xref, from which the step kernels measure displacements) or the patch after a sweep (list: the beads whose
 // exclusions changed, count at list_n; cut2 then exceeds the list cutoff by the
 // displacement margin and the wide stencil reaches it).
 template <bool BATCH, bool WIDE>
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         if (i >= n) return;
     }
     const double4 xi = B.x[i];
-    if (!WIDE) xref[i] = xi;
+    if (!WIDE && xref) xref[i] = xi;
     const int nb = B.nb[i];
     const int p0 = nb > 0 ? B.bp[i] : -1;
     const int p1 = nb > 1 ? B.bp[n + i] : -1;
@@ -905,13 +905,14 @@ void launch_halo(db_ctx* c) {
 void launch_build_nlist(db_ctx* c) {
     if (c->n == 0) return;
     launch_halo(c);
+    double4* xref = c->hp.have_pair && c->hp.pair_style == PAIR_DPD ? c->xref : nullptr;
     if (c->nrep > 0)
         hipLaunchKernelGGL((k_build_nlist<true, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, c->xref, nullptr,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
                            nullptr, 0.0f);
     else
         hipLaunchKernelGGL((k_build_nlist<false, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, c->xref, nullptr,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
                            nullptr, 0.0f);
 }
 
