@@ -79,10 +79,10 @@ typedef struct {
 
 /* ---- lifecycle ---------------------------------------------------------------- */
 
-/* Create a handle for n_beads beads in a periodic cube of edge box_L.  seed keys
- * every random number (Langevin noise and bond acceptance).  precision: DB_FP64
- * or DB_MIXED.  hip_stream: a hipStream_t (NULL = the null stream).  Allocates no
- * device memory yet. */
+/* Create a handle for n_beads beads (0 .. 2^26 - 1) in a periodic cube of edge
+ * box_L.  seed keys every random number (Langevin noise and bond acceptance).
+ * precision: DB_FP64 or DB_MIXED.  hip_stream: a hipStream_t (NULL = the null
+ * stream).  Allocates no device memory yet. */
 int db_create(db_ctx** out, int32_t n_beads, double box_L, uint64_t seed, int precision, void* hip_stream);
 /* Device bytes the handle needs; db_bind_workspace may hand it a caller-owned
  * buffer (>= that size, 256-byte aligned) before db_set_state; otherwise the
