@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_EVERY = 7
 
 # HBM traffic of the step kernel from hardware counters (rocprofv3 --pmc FETCH_SIZE,
 # then WRITE_SIZE), recorded with a hash of the kernel sources it was taken on
@@ -91,7 +92,9 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
     g.step(warmup)
     torch.cuda.synchronize()
     pk.db_step_kernel_time(g.ctx)          # reset the tally
-    pk.db_profile(g.ctx, 1)
+    # events around every 7th step launch: each event pair idles the GPU for a few
+    # microseconds, and 7 is prime to the usual block lengths
+    pk.db_profile(g.ctx, PROFILE_EVERY)
     st0 = g.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -208,9 +208,11 @@ int db_set_step(db_ctx* ctx, int64_t step);
  * rebuilds pass between reorderings of the per-bead state into cell order (>= 1;
  * default 8).  Once set here, the skin no longer follows the pair style. */
 int db_tune(db_ctx* ctx, double skin, int32_t permute_every);
-/* enable (1) / disable (0) HIP-event timing of every launch of the fused step
- * kernel on the handle's stream */
-int db_profile(db_ctx* ctx, int enable);
+/* HIP-event timing of the fused step kernel on the handle's stream: every
+ * `every`-th launch is bracketed by two events (1 = every launch; 0 = off).
+ * Each event pair leaves the GPU idle for a few microseconds between launches,
+ * so sampling keeps the timed run close to an untimed one.  EINVAL if every < 0. */
+int db_profile(db_ctx* ctx, int every);
 /* mean GPU time per launch (microseconds) of the fused step kernel over the
  * launches timed since the last call, and their number; resets the tally */
 int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);

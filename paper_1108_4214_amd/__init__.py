@@ -372,8 +372,8 @@ def db_tune(ctx, skin, permute_every):
     _check(ctx, _lib.db_tune(ctx, float(skin), int(permute_every)))
 
 
-def db_profile(ctx, enable):
-    _check(ctx, _lib.db_profile(ctx, int(enable)))
+def db_profile(ctx, every):
+    _check(ctx, _lib.db_profile(ctx, int(every)))
 
 
 def db_step_kernel_time(ctx):

@@ -47,12 +47,16 @@ struct Pinned {
     double ledger[12];             // energies before and after the sweep of the block
 };
 
-__global__ void k_report(const float* __restrict__ vmax2, int len, const int* __restrict__ err,
+// the block's maxima go to the host and their words are cleared for the next block
+__global__ void k_report(float* __restrict__ vmax2, int len, const int* __restrict__ err,
                          const unsigned long long* __restrict__ stats, int with_stats, Pinned* __restrict__ out) {
     int q = threadIdx.x;
     if (q < len) {
         float m = 0.0f;
-        for (int w = 0; w < DB_VMAX_SPREAD; ++w) m = fmaxf(m, vmax2[q * DB_VMAX_SPREAD + w]);
+        for (int w = 0; w < DB_VMAX_SPREAD; ++w) {
+            m = fmaxf(m, vmax2[q * DB_VMAX_SPREAD + w]);
+            vmax2[q * DB_VMAX_SPREAD + w] = 0.0f;
+        }
         out->vmax2[q] = m;
     }
     if (q == 0) out->err = *err;
@@ -220,6 +224,8 @@ static int ensure_memory(db_ctx* c) {
     // zero the counters that kernels assume start at zero
     launch_fill_int(c->cells.cnt, 0, (size_t)ncell_cap(c), c->stream);
     launch_fill_int(c->err_d, 0, 16, c->stream);
+    launch_fill_int((int*)c->vmax2, 0, (size_t)kMaxBlock * DB_VMAX_SPREAD, c->stream);
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_report, hipEventDisableTiming));
     c->allocated = true;
     HIPCHK(c, hipGetLastError());
     return DB_OK;
@@ -536,8 +542,9 @@ static int check_device_error(db_ctx* c) {
                 (e & ERR_NONFINITE) ? "non-finite or escaping position" : "");
 }
 
-static void rebuild(db_ctx* c, bool permute, bool save = false) {
-    launch_build_cells(c);
+// cells_ready: the cell list was already built for the current positions
+static void rebuild(db_ctx* c, bool permute, bool save = false, bool cells_ready = false) {
+    if (!cells_ready) launch_build_cells(c);
     if (permute) launch_permute(c, save);
     c->rebuilds++;
 }
@@ -599,6 +606,10 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->params_dirty = true;
     c->skin = kSkinDefault;
     c->skin_tuned = false;
+    c->profile = false;
+    c->ev_report = nullptr;
+    c->profile_every = 1;
+    c->profile_count = 0;
     c->list_valid = false;
     c->list_disp = 0.0;
     c->disp_rate = 0.0;
@@ -639,6 +650,7 @@ int db_destroy(db_ctx* c) {
     db_host_ext& X = ext(c);
     if (c->allocated) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->ev_report) (void)hipEventDestroy(c->ev_report);
     if (c->arena_owned && c->arena) (void)hipFree(c->arena);
     if (X.pin) (void)hipHostFree(X.pin);
     delete c->hx;
@@ -1041,7 +1053,7 @@ static int run_sweep(db_ctx* c, int64_t step) {
 }
 
 static int launch_timed_step(db_ctx* c, int64_t step, int slot, bool save) {
-    if (c->profile) {
+    if (c->profile && (c->profile_count++ % c->profile_every) == 0) {
         if ((size_t)c->ev_used + 2 > c->ev_pool.size()) {
             for (int k = 0; k < 2 * kMaxBlock; ++k) {
                 hipEvent_t e;
@@ -1098,6 +1110,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
         dens = std::max(dens, (double)c->rep_n[r] / (c->reps[r].L * c->reps[r].L * c->reps[r].L));
     const double reuse_cut_max = dens > 0 ? std::cbrt(0.5 * DB_NLCAP / (4.18879020478639 * dens)) : INFINITY;
     hipStream_t s = c->stream;
+    bool cells_ready = false;   // built after the previous block's report, while the host waited
     while (nsteps > 0) {
         const int64_t k0 = c->step;
         const bool sweep_due = every > 0 && k0 % every == 0 && c->swept_step != k0;
@@ -1116,7 +1129,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
         bool permute = false;
         const bool guard = std::isfinite(skin) && len > 1;
         if (reuse) {
-            rebuild(c, false);   // current cells for the sweep and the patched lists
+            rebuild(c, false, false, cells_ready);   // current cells for the sweep and the patched lists
             rc = run_sweep(c, k0);
             if (rc) return rc;
             c->swept_step = k0;
@@ -1124,7 +1137,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
             c->patches++;
         } else {
             permute = (c->rebuild_count++ % c->permute_every) == 0;
-            rebuild(c, permute, guard);
+            rebuild(c, permute, guard, cells_ready);
             if (sweep_due) {
                 rc = run_sweep(c, k0);
                 if (rc) return rc;
@@ -1132,7 +1145,6 @@ int db_step(db_ctx* c, int64_t nsteps) {
             }
             launch_build_nlist(c);   // after the sweep: exclusions follow the new bonds
         }
-        launch_fill_int((int*)c->vmax2, 0, (size_t)len * DB_VMAX_SPREAD, s);
         // the block's input state is kept for a re-run: by the reorder, or else by
         // the first step kernel of the block
         for (int64_t q = 0; q < len; ++q) {
@@ -1141,7 +1153,12 @@ int db_step(db_ctx* c, int64_t nsteps) {
         }
         hipLaunchKernelGGL(k_report, dim3(1), dim3(kMaxBlock), 0, s, c->vmax2, (int)len, c->err_d, c->sw.stats,
                            sweep_due ? 1 : 0, X.pin_dev);
-        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, hipEventRecord(c->ev_report, s));
+        // the next block's cell list (it needs only this block's positions) is built
+        // while the host waits for the report; a re-run of this block discards it
+        cells_ready = nsteps > len;
+        if (cells_ready) launch_build_cells(c);
+        HIPCHK(c, hipEventSynchronize(c->ev_report));
         HIPCHK(c, hipGetLastError());
         if (c->profile) {
             rc = harvest_events(c);
@@ -1169,6 +1186,7 @@ int db_step(db_ctx* c, int64_t nsteps) {
             // some bead may have left the reach of the cell list: redo with a fresh list every step
             c->rollbacks++;
             Bank& Bc = c->bank[c->cur];
+            cells_ready = false;
             HIPCHK(c, hipMemcpyAsync(Bc.x, c->xsave, 32 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
             HIPCHK(c, hipMemcpyAsync(Bc.v, c->vsave, 24 * (size_t)c->n, hipMemcpyDeviceToDevice, s));
             for (int64_t q = 0; q < len; ++q) {
@@ -1176,6 +1194,8 @@ int db_step(db_ctx* c, int64_t nsteps) {
                 launch_build_nlist(c);
                 launch_step(c, k0 + q, 0);
             }
+            // the re-run steps wrote their maxima into the first word row: clear it
+            launch_fill_int((int*)c->vmax2, 0, DB_VMAX_SPREAD, s);
             HIPCHK(c, hipMemcpyAsync(&pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             rc = check_device_error(c);
@@ -1543,9 +1563,11 @@ int db_batch_get_state(db_ctx* c, int32_t r, double* x, double* v, int on_device
     return DB_OK;
 }
 
-int db_profile(db_ctx* c, int enable) {
-    if (!c) return DB_EINVAL;
-    c->profile = enable != 0;
+int db_profile(db_ctx* c, int every) {
+    if (!c || every < 0) return DB_EINVAL;
+    c->profile = every > 0;
+    c->profile_every = every > 0 ? every : 1;
+    c->profile_count = 0;
     return DB_OK;
 }
 

@@ -125,10 +125,10 @@ struct SweepBuf {
     uint8_t* conv;    // bead takes part in an accepted conversion
     int* newp;        // partner slot of this bead's new (created or converted) bond, or -1
     unsigned long long* stats;   // [8] counters of the sweep
-    int* aoff;        // [n + 1] 0/1 flags of the beads that may nominate a creation partner,
-                      // then their exclusive prefix sums; aoff[n] = their number (after the
-                      // sweep: the same for the beads whose Verlet list must be redone)
-    int* act;         // [n] those beads in slot order
+    int* aoff;        // [n + 1] exclusive prefix sums of the 0/1 flags of the beads that may
+                      // nominate a creation partner, aoff[n] = their number (after the sweep:
+                      // the same for the beads whose Verlet list must be redone)
+    int* act;         // [n] the flags, then those beads in slot order
     uint8_t* chg;     // the sweep created or removed (not converted) a bond of the bead
 };
 
@@ -233,6 +233,9 @@ struct db_ctx {
 
     // profiling
     bool profile;
+    hipEvent_t ev_report;     // recorded after each block's report
+    int profile_every;        // time every profile_every-th step launch
+    int64_t profile_count;
     std::vector<hipEvent_t> ev_pool;
     int ev_used;
     double prof_ms;
@@ -247,6 +250,8 @@ void launch_build_cells(db_ctx* c);                  // bin + scan + scatter + i
 void launch_permute(db_ctx* c, bool save);           // reorder all per-bead state by the cell list
                                                      // (save: also copy x, v to the rollback buffers)
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s);
+// out[0..count) = exclusive prefix sums of in (in != out), out[count] = the total
+void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStream_t s);
 
 // kernels_force.hip
 void launch_halo(db_ctx* c);                         // bonded halo, if slots or tables changed

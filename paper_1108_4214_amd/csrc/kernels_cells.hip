@@ -70,9 +70,10 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
     return v;
 }
 
-// in[0..count) -> out[0..count) exclusive; per-tile totals to blocksum
+// in[0..count) -> out[0..count) exclusive; per-tile totals to blocksum; total (when
+// not null and a single tile covers count) receives the sum of all
 __global__ __launch_bounds__(DB_BLOCK) void k_scan_tiles(const int* __restrict__ in, int* __restrict__ out, int count,
-                                                         int* __restrict__ blocksum) {
+                                                         int* __restrict__ blocksum, int* __restrict__ total) {
     __shared__ int wsum[DB_BLOCK / 64];
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int v[SCAN_ITEMS];
@@ -96,17 +97,27 @@ __global__ __launch_bounds__(DB_BLOCK) void k_scan_tiles(const int* __restrict__
         if (idx < count) out[idx] = run;
         run += v[k];
     }
-    if (threadIdx.x == DB_BLOCK - 1) blocksum[blockIdx.x] = run;
+    if (threadIdx.x == DB_BLOCK - 1) {
+        blocksum[blockIdx.x] = run;
+        if (total) *total = run;
+    }
 }
 
+// adds the tile offsets; the thread holding the last item writes the total (in is
+// the unchanged input of an out-of-place scan, read only for that item)
 __global__ __launch_bounds__(DB_BLOCK) void k_scan_add(int* __restrict__ out, int count,
-                                                       const int* __restrict__ offsets) {
+                                                       const int* __restrict__ offsets, const int* __restrict__ in,
+                                                       int* __restrict__ total) {
     int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int off = offsets[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         int idx = base + k;
-        if (idx < count) out[idx] += off;
+        if (idx < count) {
+            const int o = out[idx] + off;
+            out[idx] = o;
+            if (total && idx == count - 1) *total = o + in[idx];
+        }
     }
 }
 
@@ -122,14 +133,23 @@ __global__ void k_scan_total(const int* __restrict__ last_in, int* __restrict__ 
 // Exclusive scan of in[0..count) into out[0..count) (in == out allowed: each tile
 // reads its items before any of them is written).  blocksum must hold the tile
 // totals of every level: ceil(count/1024) + ceil(count/1024^2) + ... ints.
-static void scan_into(const int* in, int* out, int count, int* blocksum, hipStream_t s) {
+// total (optional, out-of-place scans only: in != out) receives the sum of all.
+static void scan_into(const int* in, int* out, int count, int* blocksum, hipStream_t s, int* total = nullptr) {
     int tiles = (count + SCAN_TILE - 1) / SCAN_TILE;
-    if (tiles == 0) return;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(DB_BLOCK), 0, s, in, out, count, blocksum);
+    if (tiles == 0) {
+        if (total) hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, total, 0, (size_t)1);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(DB_BLOCK), 0, s, in, out, count, blocksum,
+                       tiles == 1 ? total : nullptr);
     if (tiles > 1) {
         scan_into(blocksum, blocksum, tiles, blocksum + tiles, s);
-        hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(DB_BLOCK), 0, s, out, count, blocksum);
+        hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(DB_BLOCK), 0, s, out, count, blocksum, in, total);
     }
+}
+
+void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStream_t s) {
+    scan_into(in, out, count, blocksum, s, out + count);
 }
 
 // data[0..count) -> exclusive prefix sums in place, and the total in data[count]
@@ -147,8 +167,10 @@ void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, 
 // every cell clears the count for the next build (the scan has consumed it)
 __global__ __launch_bounds__(DB_BLOCK) void k_scatter(int n, const int* __restrict__ cellid,
                                                        const int* __restrict__ rank, const int* __restrict__ start,
-                                                       int* __restrict__ cnt, int* __restrict__ list) {
+                                                       int* __restrict__ cnt, int* __restrict__ list,
+                                                       unsigned long long* __restrict__ stats) {
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i < 8) stats[i] = 0ull;   // the counters of the sweep that follows this build
     if (i >= n) return;
     const int c = cellid[i], k = rank[i];
     list[start[c] + k] = i;
@@ -194,12 +216,11 @@ void launch_build_cells(db_ctx* c) {
             hipLaunchKernelGGL(k_bin<false>, dim3(nb), dim3(DB_BLOCK), 0, s, c->dp, B.x, c->cells.cellid,
                                c->cells.rank, c->cells.cnt);
     }
-    // start = exclusive scan of cnt; start[ncell] = n
-    scan_into(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, c->cells.start + ncell, n, (size_t)1);
+    // start = exclusive scan of cnt; start[ncell] = their total, n
+    scan_into(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s, c->cells.start + ncell);
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.cellid, c->cells.rank,
-                           c->cells.start, c->cells.cnt, c->cells.list);
+                           c->cells.start, c->cells.cnt, c->cells.list, c->sw.stats);
         unsigned cb = (unsigned)((ncell + DB_BLOCK - 1) / DB_BLOCK);
         hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(DB_BLOCK), 0, s, ncell, c->cells.start, c->cells.list, B.x,
                            c->cells.xs);

@@ -928,7 +928,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_patch_flags(const Params* __restri
         const int nb = B.nb[i];
         for (int k = 0; k < nb; ++k) d |= S.chg[B.bp[k * n + i]] != 0;
     }
-    S.aoff[i] = d ? 1 : 0;
+    S.act[i] = d ? 1 : 0;
 }
 
 __global__ __launch_bounds__(DB_BLOCK) void k_patch_list(int n, SweepBuf S) {
@@ -945,7 +945,7 @@ void launch_patch_nlist(db_ctx* c, double cut) {
     const unsigned g = grid_for(c->n);
     Bank& B = c->bank[c->cur];
     hipLaunchKernelGGL(k_patch_flags, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
-    launch_exclusive_scan(c->sw.aoff, c->n, nullptr, c->cells.blocksum, s);
+    launch_scan_total(c->sw.act, c->sw.aoff, c->n, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_patch_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
     const float cut2 = (float)(cut * cut * 1.0001);
     if (c->nrep > 0)

@@ -109,9 +109,9 @@ __device__ __forceinline__ bool create_admits(const Params& P, int ti, const Tab
 
 // The beads that may nominate a creation partner (reactive, of a type some
 // creation rule names, with room for one of its bond types under maxbond) are
-// flagged by the breakage nomination, which reads every bead's table anyway; the
-// flags are scanned and the beads listed in slot order, so that the creation scan
-// runs on full wavefronts.
+// flagged by the breakage nomination (in S.act), which reads every bead's table
+// anyway; the flags are scanned into S.aoff and the beads listed in slot order
+// (over the flags), so that the creation scan runs on full wavefronts.
 __global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
     const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i >= n) return;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         const int ti = meta_type(mi);
         bool can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
         if (can) can = create_admits(P, ti, load_tab(B, n, i));
-        S.aoff[i] = can ? 1 : 0;
+        S.act[i] = can ? 1 : 0;
         S.chg[i] = 0;
         S.nomC[i] = -1;
         S.ruleC[i] = -1;
@@ -633,7 +633,7 @@ template <bool BATCH>
 static void sweep_kernels(db_ctx* c, const Bank& B, unsigned g, int64_t step) {
     hipStream_t s = c->stream;
     hipLaunchKernelGGL(k_nominate_break<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
-    launch_exclusive_scan(c->sw.aoff, c->n, nullptr, c->cells.blocksum, s);
+    launch_scan_total(c->sw.act, c->sw.aoff, c->n, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_create_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
     hipLaunchKernelGGL(k_nominate_create<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
                        c->cells.xs, c->sw);
@@ -650,7 +650,6 @@ void launch_sweep(db_ctx* c, int64_t step) {
     hipStream_t s = c->stream;
     Bank& B = c->bank[c->cur];
     unsigned g = grid_for(c->n);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, c->sw.stats, 8);
     if (c->nrep > 0) sweep_kernels<true>(c, B, g, step);
     else sweep_kernels<false>(c, B, g, step);
     hipLaunchKernelGGL(k_generate<false>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
