@@ -614,11 +614,6 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     (void)gi;
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int count) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0ull;
-}
-
 __global__ void k_clear_angles(int n, uint8_t* na, uint8_t* nd) {
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i < n) {
