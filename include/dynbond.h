@@ -204,7 +204,7 @@ int db_get_stats(db_ctx* ctx, db_stats* out);
 /* current step counter; db_set_step also allows the sweep of that step again */
 int db_set_step(db_ctx* ctx, int64_t step);
 /* tuning knobs of the step scheduler: the neighbour-list skin (list cutoff minus
- * pair cutoff, > 0; default 0.55 with WCA, 0.3 with DPD) and how many cell-list
+ * pair cutoff, > 0; default 0.55 with WCA, 0.02 with DPD) and how many cell-list
  * rebuilds pass between reorderings of the per-bead state into cell order (>= 1;
  * default 8).  Once set here, the skin no longer follows the pair style. */
 int db_tune(db_ctx* ctx, double skin, int32_t permute_every);
@@ -221,7 +221,7 @@ int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);
  * then bracketed by two potential-energy evaluations (costs about two force
  * passes per sweep) */
 int db_track_topology_energy(db_ctx* ctx, int enable);
-/* tries skin in {0.4, 0.5, 0.6, 0.8} (DPD: {0.2, 0.25, 0.3, 0.4}) x
+/* tries skin in {0.4, 0.5, 0.6, 0.8} (DPD: {0.02, 0.05, 0.1, 0.3}) x
  * permute_every in {1, 2, 4, 8}, running
  * steps_per_trial steps of the trajectory with each (the system advances by
  * 16 x steps_per_trial steps), and keeps the fastest; best_skin / best_permute

@@ -32,9 +32,10 @@ namespace {
 
 const int kMaxBlock = 64;
 const double kSkinDefault = 0.55;
-// DPD at density 3 lists about five times the candidates of the WCA workloads, so
-// a thinner skin (more frequent list builds, shorter lists) costs less per step
-const double kSkinDefaultDPD = 0.3;
+// DPD at density 3 with the pair friction of the paper moves some bead far enough
+// to need a new list after about every step whatever the skin, so the thinnest
+// skin (shortest lists, cells of edge r_c) costs least per step
+const double kSkinDefaultDPD = 0.02;
 
 // host memory the device writes its end-of-block report into (mapped, pinned)
 struct Pinned {
@@ -260,9 +261,25 @@ static void compute_grid(db_ctx* c) {
     double rcr = std::sqrt(std::max(P.rmax2_create, 0.0));
     double rnl = P.have_pair ? rc + c->skin : 0.0;
     P.rnl2 = rnl * rnl;
-    const double amin = std::max(rnl, rcr);
+    // Cells no narrower than the list cutoff and the creation distance; when the
+    // creation distance is the larger one and the box holds five cells of at least
+    // half that distance per edge, the cells follow the list cutoff instead and the
+    // creation scan reaches two cells (the list build, run every few steps, then
+    // scans far fewer candidates).
+    auto grid = [&](Box& X, int cap) {
+        box_grid(X, std::max(rnl, rcr), cap);
+        X.wide_create = 0;
+        if (rcr > rnl) {
+            Box W = X;
+            box_grid(W, std::max(rnl, 0.5 * rcr), cap);
+            if (W.nc >= 5 && W.nc > X.nc) {
+                X = W;
+                X.wide_create = X.L / X.nc < rcr ? 1 : 0;
+            }
+        }
+    };
     if (c->nrep == 0) {
-        box_grid(P.box, amin, ncell_cap(c));
+        grid(P.box, ncell_cap(c));
         P.box.cell_off = 0;
         P.ncell = P.box.nc * P.box.nc * P.box.nc;
         return;
@@ -270,7 +287,7 @@ static void compute_grid(db_ctx* c) {
     int off = 0;
     for (int r = 0; r < c->nrep; ++r) {
         Box& X = c->reps[r];
-        box_grid(X, amin, 2 * c->rep_n[r] + 64);
+        grid(X, 2 * c->rep_n[r] + 64);
         X.cell_off = off;
         off += X.nc * X.nc * X.nc;
     }
@@ -1394,7 +1411,7 @@ int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* 
     if (!c || steps_per_trial < 1) return DB_EINVAL;
     // DPD at density 3 favours thinner skins than the WCA workloads
     const bool dpd = c->hp.have_pair && c->hp.pair_style == PAIR_DPD;
-    const double wca_skins[4] = {0.4, 0.5, 0.6, 0.8}, dpd_skins[4] = {0.2, 0.25, 0.3, 0.4};
+    const double wca_skins[4] = {0.4, 0.5, 0.6, 0.8}, dpd_skins[4] = {0.02, 0.05, 0.1, 0.3};
     const double* skins_of = dpd ? dpd_skins : wca_skins;
     const double skins[4] = {skins_of[0], skins_of[1], skins_of[2], skins_of[3]};
     const int perms[4] = {1, 2, 4, 8};

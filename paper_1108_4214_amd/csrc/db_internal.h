@@ -55,6 +55,7 @@ struct Box {
     double cell_scale;   // nc / L
     int nc, noff;        // nc^3 cells of edge L/nc; neighbour offsets per dimension
     int off[3];
+    int wide_create;     // the creation distance exceeds one cell edge: creation scans reach two cells
     int cell_off;        // first cell of the box in the shared cell arrays
     int gid_off;         // first global bead id of the box
     uint32_t seed_lo, seed_hi;

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
 #pragma unroll
             for (int b = 0; b < DB_MAXB; ++b) two[a * DB_MAXB + b] = b < nq ? B.bp[b * n + q] : -1;
         }
-        scan_cells(X, cstart, xs, i, xi, cut2, [&](int j, int w) {
+        auto visit = [&](int j, int w) {
             if (!xs_reactive(w) || !((partner_types >> xs_type(w)) & 1u)) return;
             const double4 xj = B.x[j];
             const int mj = meta_word(xj);
@@ -214,7 +214,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
                 best_rule = rule;
                 best_bt = bti;
             }
-        });
+        };
+        if (X.wide_create) scan_cells_wide(X, cstart, xs, i, xi, cut2, visit);
+        else scan_cells(X, cstart, xs, i, xi, cut2, visit);
     }
     S.nomC[i] = best;
     S.ruleC[i] = (int8_t)best_rule;
