@@ -176,6 +176,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(S.aoff, 4 * (n + 1));
     put(S.act, 4 * n);
     put(S.chg, n);
+    put(S.tchg, n);
     put(c->nlist.nl, 4 * (size_t)DB_NLCAP * n);
     put(c->nlist.cnt, n);
     put(c->halo.nu, n);

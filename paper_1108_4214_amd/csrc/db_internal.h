@@ -131,6 +131,7 @@ struct SweepBuf {
                       // the same for the beads whose Verlet list must be redone)
     int* act;         // [n] the flags, then those beads in slot order
     uint8_t* chg;     // the sweep created or removed (not converted) a bond of the bead
+    uint8_t* tchg;    // the sweep changed the bead's own bond, angle or dihedral table
 };
 
 // Verlet neighbour list: entry k of bead s at nl[k * n + s] (slots), count in cnt

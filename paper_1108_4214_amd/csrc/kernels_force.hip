@@ -543,15 +543,14 @@ __device__ __forceinline__ void dihedral_terms(const Params& P, const Box& X, co
 //   dcode: role (2 bits) | others 1..3 << 2, 5, 8 (3 bits each) | type << 11
 // sweep_stats: the counters of a sweep that ran since the last build, which is
 // then repeated only if that sweep changed a bond (NULL: rebuild regardless)
+// only == nullptr: every bead; else only the beads flagged there (those whose own
+// tables the last sweep changed: a bead's halo depends on its own tables alone)
 __global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp, Bank B, Halo H,
-                                                   const unsigned long long* __restrict__ sweep_stats) {
+                                                   const uint8_t* __restrict__ only) {
     const Params& P = *Pp;
     const int n = P.n;
     const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    if (sweep_stats &&
-        (sweep_stats[ST_CREATED] | sweep_stats[ST_BROKEN] | sweep_stats[ST_KILLED] | sweep_stats[ST_CONVERTED]) == 0)
-        return;
+    if (i >= n || (only && !only[i])) return;
     int u[DB_MAXU];
     const int nb = B.nb[i];
 #pragma unroll
@@ -893,11 +892,13 @@ __global__ void k_energy_final(const double* __restrict__ epart, int nblocks, do
 
 static unsigned grid_for(int n) { return (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK); }
 
+// the halo of every bead after slots or tables changed wholesale; after a sweep only
+// of the beads whose own tables it changed
 void launch_halo(db_ctx* c) {
     if (c->n == 0) return;
     if (c->halo_force || c->halo_sweep)
         hipLaunchKernelGGL(k_halo, dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
-                           c->halo, c->halo_force ? (const unsigned long long*)nullptr : c->sw.stats);
+                           c->halo, c->halo_force ? (const uint8_t*)nullptr : c->sw.tchg);
     c->halo_force = false;
     c->halo_sweep = false;
 }

@@ -245,6 +245,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         if (can) can = create_admits(P, ti, load_tab(B, n, i));
         S.act[i] = can ? 1 : 0;
         S.chg[i] = 0;
+        S.tchg[i] = 0;
         S.nomC[i] = -1;
         S.ruleC[i] = -1;
         S.btC[i] = 0;
@@ -359,6 +360,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
     // none (the common case at low reaction density) no table needs editing
     const bool any_removed = (S.stats[ST_BROKEN] | S.stats[ST_KILLED] | S.stats[ST_CONVERTED]) != 0;
     int w = 0;
+    bool purged = false;
     // step 6: angles and dihedrals crossing a removed bond (judged on the old graph)
     if (any_removed) {
     int na = B.na[i];
@@ -371,6 +373,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
         if (w != k) B.ang[w * n + i] = e;
         ++w;
     }
+    purged |= w != na;
     B.na[i] = (uint8_t)w;
     int nd = B.nd[i];
     w = 0;
@@ -386,6 +389,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
         }
         ++w;
     }
+    purged |= w != nd;
     B.nd[i] = (uint8_t)w;
     }
     // step 7: own bond entries (a conversion is listed among the removed entries)
@@ -430,6 +434,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
         }
     }
     if (changed) S.chg[i] = 1;
+    if (changed || purged) S.tchg[i] = 1;
     if (w != nb) B.nb[i] = (uint8_t)w;
     stat_add(S.stats, ST_ANG_DEL, ang_del);
     stat_add(S.stats, ST_DIH_DEL, dih_del);
@@ -504,6 +509,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     Gen g{P, B, S, n, ALL};
     const int gi = g.gid_of(i), ti = g.type_of(i);
     int na = B.na[i], nd = B.nd[i];
+    const int na0 = na, nd0 = nd;
     unsigned long long ang_new = 0, dih_new = 0;
     bool overflow_a = false, overflow_d = false;
     auto push_angle = [&](int a, int b, int c, int type) {
@@ -605,6 +611,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
             }
         }
     }
+    // the counters above count an entry at its centre only; the halo follows any
+    // entry appended to this bead's tables, whatever its role
+    if (!ALL && (na != na0 || nd != nd0)) S.tchg[i] = 1;
     B.na[i] = (uint8_t)na;
     B.nd[i] = (uint8_t)nd;
     if (overflow_a) atomicOr(err, ERR_ANGLE_CAP);

@@ -4,6 +4,7 @@ within rounding), with per-replica box edge, seed and temperature."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from gpu_common import perturbed
 
@@ -127,3 +128,38 @@ def test_ladder_replicas_batch_forces_and_sweep():
         xb, _ = b.replica_state(r)
         xg, _ = g.state()
         assert np.max(np.abs(xb - xg)) < 1e-4   # mixed precision, 25 steps
+
+
+def test_batch_every_step_sweeps_keep_the_list():
+    """A sweep every step in a batch: the lists are kept across sweeps and the
+    changed beads' lists redone (per replica box), the bonded halo rebuilt for the
+    beads whose tables changed (new angles and dihedrals in any role), and every
+    replica still follows its standalone run and the oracle."""
+    import paper_1108_4214_amd as pk
+    reps, edges, systems = [], [], []
+    for r, (nd, nbp, rho, T) in enumerate(((12, 8, 0.3, 0.8), (8, 6, 0.2, 1.0), (20, 8, 0.3, 1.2))):
+        s = perturbed(synth.duplex_box(nd, nbp, rho, 70 + r, 80 + r, T=T), 0.05, 70 + r)
+        ff = synth.ff_t2(T0=T, T1=T)
+        g = pk.System(s.n, s.L, 90 + r).configure(s, ff, synth.rules_t2(p=0.7, every=1, r_kill=1.35))
+        pk.db_set_reactive(g.ctx, s.reactive)
+        reps.append(g)
+        edges.append(s.L)
+        systems.append((s, ff))
+    b = pk.Batch(reps)
+    b.step(30)
+    for r, g in enumerate(reps):
+        g.step(30)
+        xb, vb = b.replica_state(r)
+        xg, vg = g.state()
+        d = xb - xg
+        d -= edges[r] * np.round(d / edges[r])   # a bead at the boundary may sit at either end
+        assert np.max(np.abs(d)) < 1e-9
+        assert np.max(np.abs(vb - vg)) < 1e-7
+    assert b.stats()["list_patches"] > 0
+    assert b.counts()[0] == sum(g.counts()[0] for g in reps)
+    s, ff = systems[0]
+    o = oracle.Oracle.from_system(s, ff, synth.rules_t2(p=0.7, every=1, r_kill=1.35), seed=90)
+    o.step(30)
+    d = b.replica_state(0)[0] - o.state()[0]
+    d -= edges[0] * np.round(d / edges[0])
+    assert np.max(np.abs(d)) < 1e-9
