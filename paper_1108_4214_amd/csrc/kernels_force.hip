@@ -308,52 +308,82 @@ __device__ __forceinline__ void pair_one(const Params& P, const Box& X, const do
     }
 }
 
+// entries of the Verlet list requested together: eight in the FP64 WCA kernel
+// (its occupancy is set by its LDS, so registers are free), four in the FP32
+// kernel and with DPD (which also requests the partners' velocities)
+template <typename R, int PAIR>
+constexpr int pair_batch() { return (sizeof(R) == 8 && PAIR != PAIR_DPD) ? 8 : 4; }
+
+// m and jpre (the first batch of entries, read whether occupied or not) are
+// loaded by the caller ahead of the bonded terms, so that their latency overlaps
+// them.
 template <typename R>
 __device__ __forceinline__ void list_pair_forces(const Params& P, const Box& X, const Bank& B, const NList& NL, int i,
-                                                 const double4& xi, Acc<R>& a) {
+                                                 const double4& xi, int m, const int (&jpre)[pair_batch<R, PAIR_WCA>()],
+                                                 Acc<R>& a) {
+    constexpr int Q = pair_batch<R, PAIR_WCA>();
     const int n = P.n;
     const R rc2 = (R)P.rc2;
-    const int m = NL.cnt[i];
-    for (int k0 = 0; k0 < m; k0 += 4) {
-        int j[4];
+    for (int k0 = 0; k0 < m; k0 += Q) {
+        int j[Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) j[q] = (k0 + q < m) ? NL.nl[(k0 + q) * n + i] : i;
-        double4 xj[4];
+        for (int q = 0; q < Q; ++q)
+            j[q] = (k0 + q < m) ? (k0 == 0 ? jpre[q] : NL.nl[(k0 + q) * n + i]) : i;
+        double4 xj[Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) xj[q] = B.x[j[q]];
+        for (int q = 0; q < Q; ++q) xj[q] = B.x[j[q]];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < Q; ++q)
             if (k0 + q < m) pair_one<R>(P, X, xi, xj[q], rc2, a);
     }
 }
 
 // DPD pair forces from the Verlet list; THERMO adds the dissipative and random
-// parts, which read the neighbours' velocities (from the step's input buffer)
+// parts, which read the neighbours' velocities (from the step's input buffer).
+// The FP64 kernel requests the velocities of a batch with its positions, whether
+// or not the pair turns out to lie within the cutoff; the FP32 kernel reads them
+// per interacting pair, which keeps its registers within five waves per SIMD.
+// m and jpre as for the WCA list.
 template <typename R, bool THERMO>
 __device__ __forceinline__ void list_pair_dpd(const Params& P, const Box& X, const Bank& B, const NList& NL, int i,
                                               const double4& xi, double vix, double viy, double viz, int64_t step,
-                                              double dsig, Acc<R>& a) {
+                                              double dsig, int m, const int (&jpre)[pair_batch<R, PAIR_DPD>()],
+                                              Acc<R>& a) {
+    constexpr int Q = pair_batch<R, PAIR_DPD>();
     const int n = P.n;
     const R rc2 = (R)P.rc2;
-    const int m = NL.cnt[i];
-    for (int k0 = 0; k0 < m; k0 += 4) {
-        int j[4];
+    for (int k0 = 0; k0 < m; k0 += Q) {
+        int j[Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) j[q] = (k0 + q < m) ? NL.nl[(k0 + q) * n + i] : i;
-        double4 xj[4];
+        for (int q = 0; q < Q; ++q)
+            j[q] = (k0 + q < m) ? (k0 == 0 ? jpre[q] : NL.nl[(k0 + q) * n + i]) : i;
+        double4 xj[Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) xj[q] = B.x[j[q]];
+        for (int q = 0; q < Q; ++q) xj[q] = B.x[j[q]];
+        constexpr bool vbatch = THERMO && sizeof(R) == 8;
+        double vjx[Q], vjy[Q], vjz[Q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < Q; ++q) {
+            vjx[q] = vbatch ? B.v[j[q]] : 0.0;
+            vjy[q] = vbatch ? B.v[n + j[q]] : 0.0;
+            vjz[q] = vbatch ? B.v[2 * n + j[q]] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
             const R rx = (R)near_image(xj[q].x - xi.x, X);
             const R ry = (R)near_image(xj[q].y - xi.y, X);
             const R rz = (R)near_image(xj[q].z - xi.z, X);
             const R r2 = (rx * rx + ry * ry) + rz * rz;
             if ((k0 + q < m) & (r2 < rc2)) {
                 if (THERMO) {
-                    const int jq = j[q];
-                    dpd_pair<R, true, false>(P, X, xi, xj[q], rx, ry, rz, r2, vix - B.v[jq], viy - B.v[n + jq],
-                                             viz - B.v[2 * n + jq], step, dsig, a);
+                    if (!vbatch) {
+                        const int jq = j[q];
+                        vjx[q] = B.v[jq];
+                        vjy[q] = B.v[n + jq];
+                        vjz[q] = B.v[2 * n + jq];
+                    }
+                    dpd_pair<R, true, false>(P, X, xi, xj[q], rx, ry, rz, r2, vix - vjx[q], viy - vjy[q],
+                                             viz - vjz[q], step, dsig, a);
                 } else {
                     dpd_pair<R, false, false>(P, X, xi, xj[q], rx, ry, rz, r2, 0, 0, 0, 0, 0, a);
                 }
@@ -612,17 +642,36 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
     const int tid = threadIdx.x;
     __shared__ R hs[3][DB_MAXU][DB_BLOCK];
     R hx[DB_MAXU], hy[DB_MAXU], hz[DB_MAXU];
-    // separations x_k - x_i, four at a time
+    // Every per-bead word used below is requested before the first of them is
+    // waited for, so that they share one memory latency instead of one each.
+    // Rows exist for every bead: unused rows are read and then ignored.  The FP64
+    // kernel, whose occupancy its LDS already limits, also takes the first angle
+    // and dihedral codes early and gathers all halo positions at once; the FP32
+    // kernel keeps within the registers of six waves per SIMD.
+    constexpr bool wide = sizeof(R) == 8;
+    constexpr int G = wide ? DB_MAXU : 4;
+    int su[DB_MAXU];
 #pragma unroll
-    for (int k0 = 0; k0 < DB_MAXU; k0 += 4) {
-        int s[4];
+    for (int q = 0; q < DB_MAXU; ++q) su[q] = H.u[q * n + i];
+    int btk[DB_MAXB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] = k0 + q < nu ? H.u[(k0 + q) * n + i] : i;
-        double4 xk[4];
+    for (int k = 0; k < DB_MAXB; ++k) btk[k] = B.bt[k * n + i];
+    const int nb = B.nb[i];
+    const int na = B.na[i];
+    const int nd = B.nd[i];
+    const uint32_t acode0 = wide ? H.acode[i] : 0u;
+    const uint32_t dcode0 = wide ? H.dcode[i] : 0u;
+    // separations x_k - x_i, G at a time
 #pragma unroll
-        for (int q = 0; q < 4; ++q) xk[q] = B.x[s[q]];
+    for (int k0 = 0; k0 < DB_MAXU; k0 += G) {
+        int s[G];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < G; ++q) s[q] = k0 + q < nu ? su[k0 + q] : i;
+        double4 xk[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) xk[q] = B.x[s[q]];
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
             hx[k0 + q] = (R)near_image(xk[q].x - xi.x, X);
             hy[k0 + q] = (R)near_image(xk[q].y - xi.y, X);
             hz[k0 + q] = (R)near_image(xk[q].z - xi.z, X);
@@ -632,11 +681,10 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         }
     }
     // bonds: the first nb halo entries are the partners in table order
-    const int nb = B.nb[i];
 #pragma unroll
     for (int k = 0; k < DB_MAXB; ++k) {
         if (k >= nb) continue;
-        const int t = B.bt[k * n + i] & (DB_MAXT - 1);
+        const int t = btk[k] & (DB_MAXT - 1);
         const R rx = hx[k], ry = hy[k], rz = hz[k];
         R rr2 = (rx * rx + ry * ry) + rz * rz;
         if (!(rr2 > (R)0) || !(rr2 < C.bRc2[t])) continue;
@@ -647,9 +695,8 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         a.fy += (double)(g * ry);
         a.fz += (double)(g * rz);
     }
-    const int na = B.na[i];
     for (int k = 0; k < na; ++k) {
-        const uint32_t code = H.acode[k * n + i];
+        const uint32_t code = (wide && k == 0) ? acode0 : H.acode[k * n + i];
         const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, t = (code >> 8) & (DB_MAXT - 1);
         const R s1x = hs[0][k1][tid], s1y = hs[1][k1][tid], s1z = hs[2][k1][tid];
         const R s2x = hs[0][k2][tid], s2y = hs[1][k2][tid], s2z = hs[2][k2][tid];
@@ -661,9 +708,8 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         const R pcx = role == 2 ? z : s2x, pcy = role == 2 ? z : s2y, pcz = role == 2 ? z : s2z;
         angle_core<R, MODE_STEP>(C, role, t, pax - pbx, pay - pby, paz - pbz, pcx - pbx, pcy - pby, pcz - pbz, a);
     }
-    const int nd = B.nd[i];
     for (int k = 0; k < nd; ++k) {
-        const uint32_t code = H.dcode[k * n + i];
+        const uint32_t code = (wide && k == 0) ? dcode0 : H.dcode[k * n + i];
         const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, k3 = (code >> 8) & 7;
         const int t = (code >> 11) & (DB_MAXT - 1);
         const R s1x = hs[0][k1][tid], s1y = hs[1][k1][tid], s1z = hs[2][k1][tid];
@@ -718,6 +764,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
         xi = B.x[i];
         const Box& X = box_of<BATCH>(P, meta_word(xi));
         const int nu = H.nu[i];
+        // the list's count and first entries are requested ahead of the bonded terms
+        constexpr int PQ = pair_batch<R, PAIR>();
+        int m_pair = 0;
+        int jpre[PQ];
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) jpre[q] = i;
+        if (P.have_pair) {
+            m_pair = NL.cnt[i];
+#pragma unroll
+            for (int q = 0; q < PQ; ++q) jpre[q] = NL.nl[q * n + i];
+        }
         if (nu <= DB_MAXU) {
             halo_bonded<R>(P, X, C, B, H, i, xi, nu, a);
         } else {
@@ -726,15 +783,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp
             angle_terms<R, MODE_STEP>(P, X, C, B, i, B.na[i], a);
             dihedral_terms<R, MODE_STEP>(P, X, C, B, i, B.nd[i], a);
         }
-        if (PAIR == PAIR_DPD) {
+        if constexpr (PAIR == PAIR_DPD) {
             if (MODE == MODE_STEP && P.dpd_gamma != 0.0) {
                 if (BATCH) dsig = sqrt(2.0 * box_temperature(X, step) * P.dpd_gamma) / sqrt(P.dt);
-                list_pair_dpd<R, true>(P, X, B, NL, i, xi, B.v[i], B.v[n + i], B.v[2 * n + i], step, dsig, a);
+                list_pair_dpd<R, true>(P, X, B, NL, i, xi, B.v[i], B.v[n + i], B.v[2 * n + i], step, dsig, m_pair,
+                                       jpre, a);
             } else {
-                list_pair_dpd<R, false>(P, X, B, NL, i, xi, 0, 0, 0, 0, 0, a);
+                list_pair_dpd<R, false>(P, X, B, NL, i, xi, 0, 0, 0, 0, 0, m_pair, jpre, a);
             }
-        } else if (P.have_pair) {
-            list_pair_forces<R>(P, X, B, NL, i, xi, a);
+        } else {
+            if (P.have_pair) list_pair_forces<R>(P, X, B, NL, i, xi, m_pair, jpre, a);
         }
         if (P.has_ext) {
             const size_t g = (size_t)meta_gid(xi);
