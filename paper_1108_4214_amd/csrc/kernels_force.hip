@@ -248,11 +248,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     }
     const double4 xi = B.x[i];
     if (!WIDE && xref) xref[i] = xi;
+    // the bond rows exist for every bead: all are requested at once with the count
+    // and the unused ones ignored, and likewise for the partners' rows, so that the
+    // exclusion set costs two memory latencies before the scan
     const int nb = B.nb[i];
-    const int p0 = nb > 0 ? B.bp[i] : -1;
-    const int p1 = nb > 1 ? B.bp[n + i] : -1;
-    const int p2 = nb > 2 ? B.bp[2 * n + i] : -1;
-    const int p3 = nb > 3 ? B.bp[3 * n + i] : -1;
+    int pr[DB_MAXB];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) pr[k] = B.bp[k * n + i];
+    const int p0 = nb > 0 ? pr[0] : -1;
+    const int p1 = nb > 1 ? pr[1] : -1;
+    const int p2 = nb > 2 ? pr[2] : -1;
+    const int p3 = nb > 3 ? pr[3] : -1;
     const Box& X = box_of<BATCH>(P, meta_word(xi));
     // the beads two bonds away (partners of partners), gathered once per bead, so
     // that testing a candidate compares registers instead of re-reading the
@@ -262,11 +268,30 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     const int pp[DB_MAXB] = {p0, p1, p2, p3};
     int two[DB_MAXB * DB_MAXB];
 #pragma unroll
-    for (int k = 0; k < DB_MAXB; ++k) {
-        const int nq = (depth2 && k < nb) ? B.nb[pp[k]] : 0;
+    for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) two[k] = -1;
+    if (depth2) {
+        int nq[DB_MAXB];
 #pragma unroll
-        for (int m = 0; m < DB_MAXB; ++m) two[k * DB_MAXB + m] = m < nq ? B.bp[m * n + pp[k]] : -1;
+        for (int k = 0; k < DB_MAXB; ++k) {
+            const int q = k < nb ? pp[k] : i;
+            nq[k] = k < nb ? B.nb[q] : 0;
+#pragma unroll
+            for (int m = 0; m < DB_MAXB; ++m) two[k * DB_MAXB + m] = B.bp[m * n + q];
+        }
+#pragma unroll
+        for (int k = 0; k < DB_MAXB; ++k)
+#pragma unroll
+            for (int m = 0; m < DB_MAXB; ++m)
+                if (m >= nq[k]) two[k * DB_MAXB + m] = -1;
     }
+    // The first NL_STAGE entries of the full build go to the thread's own LDS
+    // column and are written out afterwards one row at a time, so that a store
+    // covers consecutive beads of one row; entries beyond go straight to memory.
+    // (Written as they are found, the lanes of a wave store into rows that differ
+    // by their counts, and each store scatters over as many rows.)
+    constexpr int NL_STAGE = WIDE ? 1 : 20;
+    __shared__ int stage[NL_STAGE][DB_BLOCK];
+    const int tid = threadIdx.x;
     int cnt = 0;
     auto visit = [&](int j, int) {
         if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
@@ -276,11 +301,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
             for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) ex |= two[k] == j;
             if (ex) return;
         }
-        if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
+        if (!WIDE && cnt < NL_STAGE) stage[cnt][tid] = j;
+        else if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
         ++cnt;
     };
     if (WIDE) scan_cells_wide(X, cstart, xs, i, xi, cut2, visit);
     else scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), visit);
+    if (!WIDE) {
+        const int ns = min(cnt, NL_STAGE);
+        for (int k = 0; k < ns; ++k) NL.nl[k * n + i] = stage[k][tid];
+    }
     if (cnt > DB_NLCAP) {
         atomicOr(err, ERR_NLIST);
         cnt = DB_NLCAP;
