@@ -177,6 +177,8 @@ static size_t layout(db_ctx* c, bool assign) {
     put(S.act, 4 * n);
     put(S.chg, n);
     put(S.tchg, n);
+    put(S.npurge, n);
+    put(S.ngen, n);
     put(c->nlist.nl, 4 * (size_t)DB_NLCAP * n);
     put(c->nlist.cnt, n);
     put(c->halo.nu, n);

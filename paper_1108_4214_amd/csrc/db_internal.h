@@ -132,6 +132,8 @@ struct SweepBuf {
     int* act;         // [n] the flags, then those beads in slot order
     uint8_t* chg;     // the sweep created or removed (not converted) a bond of the bead
     uint8_t* tchg;    // the sweep changed the bead's own bond, angle or dihedral table
+    uint8_t* npurge;  // the bead lies within two bonds (old tables) of a bond the sweep removes
+    uint8_t* ngen;    // the bead lies within two bonds (new tables) of a bond the sweep created or converted
 };
 
 // Verlet neighbour list: entry k of bead s at nl[k * n + s] (slots), count in cnt

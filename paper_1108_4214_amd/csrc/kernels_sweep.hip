@@ -246,6 +246,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         S.act[i] = can ? 1 : 0;
         S.chg[i] = 0;
         S.tchg[i] = 0;
+        S.npurge[i] = 0;
+        S.ngen[i] = 0;
         S.nomC[i] = -1;
         S.ruleC[i] = -1;
         S.btC[i] = 0;
@@ -304,6 +306,19 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
     stat_add(S.stats, ST_KILLED, killed_here);
 }
 
+// flag bead s, its bond partners and theirs (in the current tables); several
+// beads may flag one bead, all with the same value
+__device__ __forceinline__ void mark_two_bonds(const Bank& B, int n, int s, uint8_t* __restrict__ f) {
+    f[s] = 1;
+    const int nb = B.nb[s];
+    for (int k = 0; k < nb; ++k) {
+        const int q = B.bp[k * n + s];
+        f[q] = 1;
+        const int nq = B.nb[q];
+        for (int m = 0; m < nq; ++m) f[B.bp[m * n + q]] = 1;
+    }
+}
+
 // ---- step 5: mutual breakage nominations ----------------------------------------
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_resolve(const Params* __restrict__ Pp, Bank B, SweepBuf S,
@@ -338,6 +353,11 @@ __global__ __launch_bounds__(DB_BLOCK) void k_resolve(const Params* __restrict__
     }
     S.conv[i] = (uint8_t)conv;
     S.newp[i] = newp;
+    // every member of an angle or dihedral through a removed bond lies within two
+    // bonds of one of that bond's ends, and both ends list the removal: they flag
+    // those beads (the tables still hold the old graph), the only ones whose
+    // tables the purge must read
+    if (S.rmcnt[i] > 0) mark_two_bonds(B, n, i, S.npurge);
 }
 
 __device__ __forceinline__ bool bond_removed(const SweepBuf& S, int n, int u, int v) {
@@ -362,7 +382,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
     int w = 0;
     bool purged = false;
     // step 6: angles and dihedrals crossing a removed bond (judged on the old graph)
-    if (any_removed) {
+    if (any_removed && S.npurge[i]) {
     int na = B.na[i];
     for (int k = 0; k < na; ++k) {
         int4 e = B.ang[k * n + i];
@@ -493,19 +513,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     if (P.narule == 0 && P.ndrule == 0) return;
     // no bond was created or converted in this sweep: nothing to generate
     if (!ALL && (S.stats[ST_CREATED] | S.stats[ST_CONVERTED]) == 0) return;
+    // only beads within two bonds of a new bond can lie on a qualifying path
+    // (flagged by k_mark_new)
+    if (!ALL && !S.ngen[i]) return;
     Tab Ti = load_tab(B, n, i);
-    if (!ALL) {
-        // only beads within two bonds of a new bond can lie on a qualifying path
-        bool dirty = S.newp[i] >= 0;
-        for (int a = 0; a < Ti.n && !dirty; ++a) {
-            int q = Ti.p(a);
-            if (S.newp[q] >= 0) dirty = true;
-            int nq = B.nb[q];
-            for (int m = 0; m < nq && !dirty; ++m)
-                if (S.newp[B.bp[m * n + q]] >= 0) dirty = true;
-        }
-        if (!dirty) return;
-    }
     Gen g{P, B, S, n, ALL};
     const int gi = g.gid_of(i), ti = g.type_of(i);
     int na = B.na[i], nd = B.nd[i];
@@ -625,6 +636,15 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     (void)gi;
 }
 
+// the beads within two bonds of a bond this sweep created or converted, from the
+// new tables (both ends hold it); nothing when the sweep made no bond
+__global__ __launch_bounds__(DB_BLOCK) void k_mark_new(int n, Bank B, SweepBuf S) {
+    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    if ((S.stats[ST_CREATED] | S.stats[ST_CONVERTED]) == 0) return;
+    if (S.newp[i] >= 0) mark_two_bonds(B, n, i, S.ngen);
+}
+
 __global__ void k_clear_angles(int n, uint8_t* na, uint8_t* nd) {
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i < n) {
@@ -658,7 +678,10 @@ void launch_sweep(db_ctx* c, int64_t step) {
     unsigned g = grid_for(c->n);
     if (c->nrep > 0) sweep_kernels<true>(c, B, g, step);
     else sweep_kernels<false>(c, B, g, step);
-    hipLaunchKernelGGL(k_generate<false>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
+    if (c->hp.narule || c->hp.ndrule) {
+        hipLaunchKernelGGL(k_mark_new, dim3(g), dim3(DB_BLOCK), 0, s, c->n, B, c->sw);
+        hipLaunchKernelGGL(k_generate<false>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, c->err_d);
+    }
 }
 
 void launch_generate_all(db_ctx* c) {
