@@ -346,7 +346,8 @@ constexpr int pair_batch() { return (sizeof(R) == 8 && PAIR != PAIR_DPD) ? 8 : 4
 
 // m and jpre (the first batch of entries, read whether occupied or not) are
 // loaded by the caller ahead of the bonded terms, so that their latency overlaps
-// them.
+// them; each later batch of entries is requested before the previous batch's
+// pairs are evaluated.
 template <typename R>
 __device__ __forceinline__ void list_pair_forces(const Params& P, const Box& X, const Bank& B, const NList& NL, int i,
                                                  const double4& xi, int m, const int (&jpre)[pair_batch<R, PAIR_WCA>()],
@@ -354,14 +355,17 @@ __device__ __forceinline__ void list_pair_forces(const Params& P, const Box& X, 
     constexpr int Q = pair_batch<R, PAIR_WCA>();
     const int n = P.n;
     const R rc2 = (R)P.rc2;
-    for (int k0 = 0; k0 < m; k0 += Q) {
-        int j[Q];
+    int j[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-            j[q] = (k0 + q < m) ? (k0 == 0 ? jpre[q] : NL.nl[(k0 + q) * n + i]) : i;
+    for (int q = 0; q < Q; ++q) j[q] = q < m ? jpre[q] : i;
+    for (int k0 = 0; k0 < m; k0 += Q) {
         double4 xj[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) xj[q] = B.x[j[q]];
+        // the next batch's entries are requested before this batch is evaluated
+        const int k1 = k0 + Q;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) j[q] = k1 + q < m ? NL.nl[(k1 + q) * n + i] : i;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (k0 + q < m) pair_one<R>(P, X, xi, xj[q], rc2, a);
@@ -675,9 +679,8 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
     // Every per-bead word used below is requested before the first of them is
     // waited for, so that they share one memory latency instead of one each.
     // Rows exist for every bead: unused rows are read and then ignored.  The FP64
-    // kernel, whose occupancy its LDS already limits, also takes the first angle
-    // and dihedral codes early and gathers all halo positions at once; the FP32
-    // kernel keeps within the registers of six waves per SIMD.
+    // kernel, whose occupancy its LDS already limits, also gathers all halo
+    // positions at once; the FP32 kernel takes them four at a time.
     constexpr bool wide = sizeof(R) == 8;
     constexpr int G = wide ? DB_MAXU : 4;
     int su[DB_MAXU];
@@ -689,8 +692,8 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
     const int nb = B.nb[i];
     const int na = B.na[i];
     const int nd = B.nd[i];
-    const uint32_t acode0 = wide ? H.acode[i] : 0u;
-    const uint32_t dcode0 = wide ? H.dcode[i] : 0u;
+    const uint32_t acode0 = H.acode[i];
+    const uint32_t dcode0 = H.dcode[i];
     // separations x_k - x_i, G at a time
 #pragma unroll
     for (int k0 = 0; k0 < DB_MAXU; k0 += G) {
@@ -726,7 +729,7 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         a.fz += (double)(g * rz);
     }
     for (int k = 0; k < na; ++k) {
-        const uint32_t code = (wide && k == 0) ? acode0 : H.acode[k * n + i];
+        const uint32_t code = k == 0 ? acode0 : H.acode[k * n + i];
         const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, t = (code >> 8) & (DB_MAXT - 1);
         const R s1x = hs[0][k1][tid], s1y = hs[1][k1][tid], s1z = hs[2][k1][tid];
         const R s2x = hs[0][k2][tid], s2y = hs[1][k2][tid], s2z = hs[2][k2][tid];
@@ -739,7 +742,7 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         angle_core<R, MODE_STEP>(C, role, t, pax - pbx, pay - pby, paz - pbz, pcx - pbx, pcy - pby, pcz - pbz, a);
     }
     for (int k = 0; k < nd; ++k) {
-        const uint32_t code = (wide && k == 0) ? dcode0 : H.dcode[k * n + i];
+        const uint32_t code = k == 0 ? dcode0 : H.dcode[k * n + i];
         const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, k3 = (code >> 8) & 7;
         const int t = (code >> 11) & (DB_MAXT - 1);
         const R s1x = hs[0][k1][tid], s1y = hs[1][k1][tid], s1z = hs[2][k1][tid];
@@ -770,13 +773,15 @@ __device__ __forceinline__ double wave_max(double v) {
 // reads the neighbours' input velocities.  Each step reports the workgroup maxima
 // of |v|^2 (WCA) or, with DPD, of the squared displacement of the new position
 // from xref, the position at the last full Verlet-list build.
+// The FP32 WCA step of a single box is held to the registers of six waves per
+// SIMD (its LDS allows six), which the compiler otherwise gives up for a few
+// registers.
 template <typename R, int MODE, bool BATCH, int PAIR>
-__global__ __launch_bounds__(DB_BLOCK) void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
-                                                    double4* __restrict__ xout, double* vout, int64_t step,
-                                                    double pref, double dsig, unsigned int* __restrict__ vmax2_slot,
-                                                    double* __restrict__ fout, int* __restrict__ err,
-                                                    double4* __restrict__ xsave, double* __restrict__ vsave,
-                                                    const double4* __restrict__ xref) {
+__global__ __launch_bounds__(DB_BLOCK, (sizeof(R) == 4 && PAIR == PAIR_WCA && !BATCH && MODE == MODE_STEP) ? 6 : 1)
+void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H, double4* __restrict__ xout, double* vout,
+            int64_t step, double pref, double dsig, unsigned int* __restrict__ vmax2_slot, double* __restrict__ fout,
+            int* __restrict__ err, double4* __restrict__ xsave, double* __restrict__ vsave,
+            const double4* __restrict__ xref) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
     const Params& P = *Pp;
     const int n = P.n;
