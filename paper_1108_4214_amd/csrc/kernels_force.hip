@@ -637,28 +637,50 @@ __global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp
             if (q == nu) u[q] = m;
         return nu++;
     };
+    // entries are read four at a time (an entry past the count re-reads the
+    // batch's first), so that the loads of a batch are in flight together; they
+    // are then coded in table order
     const int na = B.na[i];
-    for (int k = 0; k < na; ++k) {
-        const int4 e = B.ang[k * n + i];
-        const int role = e.x == i ? 0 : (e.z == i ? 2 : 1);
-        const int m1 = role == 0 ? e.y : e.x;
-        const int m2 = role == 2 ? e.y : e.z;
-        const int c1 = code_of(m1);
-        const int c2 = code_of(m2);
-        H.acode[k * n + i] = (uint32_t)(role | c1 << 2 | c2 << 5 | (e.w & (DB_MAXT - 1)) << 8);
+    for (int k0 = 0; k0 < na; k0 += 4) {
+        int4 e4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e4[q] = B.ang[(k0 + q < na ? k0 + q : k0) * n + i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (k0 + q >= na) continue;
+            const int4 e = e4[q];
+            const int role = e.x == i ? 0 : (e.z == i ? 2 : 1);
+            const int m1 = role == 0 ? e.y : e.x;
+            const int m2 = role == 2 ? e.y : e.z;
+            const int c1 = code_of(m1);
+            const int c2 = code_of(m2);
+            H.acode[(k0 + q) * n + i] = (uint32_t)(role | c1 << 2 | c2 << 5 | (e.w & (DB_MAXT - 1)) << 8);
+        }
     }
     const int nd = B.nd[i];
-    for (int k = 0; k < nd; ++k) {
-        const int4 e = B.dih[k * n + i];
-        const int t = B.dt[k * n + i] & (DB_MAXT - 1);
-        const int role = e.x == i ? 0 : (e.w == i ? 3 : (e.y == i ? 1 : 2));
-        const int o1 = role == 0 ? e.y : e.x;
-        const int o2 = role <= 1 ? e.z : e.y;
-        const int o3 = role <= 2 ? e.w : e.z;
-        const int c1 = code_of(o1);
-        const int c2 = code_of(o2);
-        const int c3 = code_of(o3);
-        H.dcode[k * n + i] = (uint32_t)(role | c1 << 2 | c2 << 5 | c3 << 8 | t << 11);
+    for (int k0 = 0; k0 < nd; k0 += 4) {
+        int4 e4[4];
+        int t4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + q < nd ? k0 + q : k0;
+            e4[q] = B.dih[k * n + i];
+            t4[q] = B.dt[k * n + i] & (DB_MAXT - 1);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (k0 + q >= nd) continue;
+            const int4 e = e4[q];
+            const int t = t4[q];
+            const int role = e.x == i ? 0 : (e.w == i ? 3 : (e.y == i ? 1 : 2));
+            const int o1 = role == 0 ? e.y : e.x;
+            const int o2 = role <= 1 ? e.z : e.y;
+            const int o3 = role <= 2 ? e.w : e.z;
+            const int c1 = code_of(o1);
+            const int c2 = code_of(o2);
+            const int c3 = code_of(o3);
+            H.dcode[(k0 + q) * n + i] = (uint32_t)(role | c1 << 2 | c2 << 5 | c3 << 8 | t << 11);
+        }
     }
 #pragma unroll
     for (int q = 0; q < DB_MAXU; ++q)

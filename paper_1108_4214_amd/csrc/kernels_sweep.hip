@@ -44,6 +44,48 @@ __device__ __forceinline__ Tab load_tab(const Bank& B, int n, int s) {
     return T;
 }
 
+// the same with every row requested together with the count (rows exist for
+// every bead): one memory latency instead of two, for the latency-bound paths
+// that read few tables; streaming passes over all beads keep load_tab, which
+// reads only the occupied rows
+__device__ __forceinline__ Tab load_tab_all(const Bank& B, int n, int s) {
+    Tab T;
+    T.n = B.nb[s];
+    const int p0 = B.bp[s], p1 = B.bp[n + s], p2 = B.bp[2 * n + s], p3 = B.bp[3 * n + s];
+    const int t0 = B.bt[s], t1 = B.bt[n + s], t2 = B.bt[2 * n + s], t3 = B.bt[3 * n + s];
+    T.p0 = T.n > 0 ? p0 : -1;
+    T.p1 = T.n > 1 ? p1 : -1;
+    T.p2 = T.n > 2 ? p2 : -1;
+    T.p3 = T.n > 3 ? p3 : -1;
+    T.t0 = T.n > 0 ? t0 : 0;
+    T.t1 = T.n > 1 ? t1 : 0;
+    T.t2 = T.n > 2 ? t2 : 0;
+    T.t3 = T.n > 3 ? t3 : 0;
+    return T;
+}
+
+// the tables of a bead's four partners, selected by a run-time index field by
+// field (a select of whole tables would go through scratch memory)
+__device__ __forceinline__ int sel4(int k, int x0, int x1, int x2, int x3) {
+    return k == 0 ? x0 : (k == 1 ? x1 : (k == 2 ? x2 : x3));
+}
+struct Tab4 {
+    Tab a, b, c, d;
+    __device__ Tab get(int k) const {
+        Tab T;
+        T.n = sel4(k, a.n, b.n, c.n, d.n);
+        T.p0 = sel4(k, a.p0, b.p0, c.p0, d.p0);
+        T.p1 = sel4(k, a.p1, b.p1, c.p1, d.p1);
+        T.p2 = sel4(k, a.p2, b.p2, c.p2, d.p2);
+        T.p3 = sel4(k, a.p3, b.p3, c.p3, d.p3);
+        T.t0 = sel4(k, a.t0, b.t0, c.t0, d.t0);
+        T.t1 = sel4(k, a.t1, b.t1, c.t1, d.t1);
+        T.t2 = sel4(k, a.t2, b.t2, c.t2, d.t2);
+        T.t3 = sel4(k, a.t3, b.t3, c.t3, d.t3);
+        return T;
+    }
+};
+
 __device__ __forceinline__ int tab_type_of(const Tab& T, int v) {
     for (int k = 0; k < T.n; ++k)
         if (T.p(k) == v) return T.t(k);
@@ -140,7 +182,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
     const int gi = meta_gid(xi);
     int best = -1, best_rule = -1, best_bt = 0, best_g = 0;
     double best_r2 = 0.0;
-    const Tab Ti = load_tab(B, n, i);
+    const Tab Ti = load_tab_all(B, n, i);
     {
         const float cut2 = (float)(P.rmax2_create * 1.0001);
         // types and reactivity ride in the scan's words: most candidates are
@@ -180,7 +222,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
                 if (!(r2 < r.r2)) continue;
                 if (!max_ok(P, ti, Ti, si)) continue;
                 if (!have_tj) {
-                    Tj = load_tab(B, n, j);
+                    Tj = load_tab_all(B, n, j);
                     have_tj = true;
                 }
                 if (!max_ok(P, tj, Tj, sj)) continue;
@@ -367,6 +409,13 @@ __device__ __forceinline__ bool bond_removed(const SweepBuf& S, int n, int u, in
     return false;
 }
 
+// the same with u's removal count already read
+__device__ __forceinline__ bool listed_removed(const SweepBuf& S, int n, int u, int rm, int v) {
+    for (int k = 0; k < rm; ++k)
+        if (S.rmlist[k * n + u] == v) return true;
+    return false;
+}
+
 // ---- steps 6-8: purge, remove / convert, create ---------------------------------
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ Pp, Bank B, SweepBuf S, int64_t step,
@@ -383,34 +432,72 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
     bool purged = false;
     // step 6: angles and dihedrals crossing a removed bond (judged on the old graph)
     if (any_removed && S.npurge[i]) {
-    int na = B.na[i];
-    for (int k = 0; k < na; ++k) {
-        int4 e = B.ang[k * n + i];
-        if (bond_removed(S, n, e.x, e.y) || bond_removed(S, n, e.y, e.z)) {
-            if (e.y == i) ++ang_del;
-            continue;
+        // first which entries cross a removed bond: four entries and the removal
+        // counts of their members are read together, before any row is moved
+        static_assert(DB_MAXA <= 32 && DB_MAXD <= 32, "one bit per entry");
+        const int na = B.na[i];
+        uint32_t drop = 0;
+        for (int k0 = 0; k0 < na; k0 += 4) {
+            int4 e4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e4[q] = B.ang[(k0 + q < na ? k0 + q : k0) * n + i];
+            int rx[4], ry[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rx[q] = S.rmcnt[e4[q].x];
+                ry[q] = S.rmcnt[e4[q].y];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int4 e = e4[q];
+                if (k0 + q < na && (listed_removed(S, n, e.x, rx[q], e.y) || listed_removed(S, n, e.y, ry[q], e.z))) {
+                    drop |= 1u << (k0 + q);
+                    if (e.y == i) ++ang_del;
+                }
+            }
         }
-        if (w != k) B.ang[w * n + i] = e;
-        ++w;
-    }
-    purged |= w != na;
-    B.na[i] = (uint8_t)w;
-    int nd = B.nd[i];
-    w = 0;
-    for (int k = 0; k < nd; ++k) {
-        int4 e = B.dih[k * n + i];
-        if (bond_removed(S, n, e.x, e.y) || bond_removed(S, n, e.y, e.z) || bond_removed(S, n, e.z, e.w)) {
-            if (e.y == i) ++dih_del;
-            continue;
+        // then the kept entries close up in order
+        for (int k = 0; k < na; ++k) {
+            if ((drop >> k) & 1u) continue;
+            if (w != k) B.ang[w * n + i] = B.ang[k * n + i];
+            ++w;
         }
-        if (w != k) {
-            B.dih[w * n + i] = e;
-            B.dt[w * n + i] = B.dt[k * n + i];
+        purged |= w != na;
+        B.na[i] = (uint8_t)w;
+        const int nd = B.nd[i];
+        drop = 0;
+        for (int k0 = 0; k0 < nd; k0 += 4) {
+            int4 e4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e4[q] = B.dih[(k0 + q < nd ? k0 + q : k0) * n + i];
+            int rx[4], ry[4], rz[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rx[q] = S.rmcnt[e4[q].x];
+                ry[q] = S.rmcnt[e4[q].y];
+                rz[q] = S.rmcnt[e4[q].z];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int4 e = e4[q];
+                if (k0 + q < nd && (listed_removed(S, n, e.x, rx[q], e.y) || listed_removed(S, n, e.y, ry[q], e.z) ||
+                                    listed_removed(S, n, e.z, rz[q], e.w))) {
+                    drop |= 1u << (k0 + q);
+                    if (e.y == i) ++dih_del;
+                }
+            }
         }
-        ++w;
-    }
-    purged |= w != nd;
-    B.nd[i] = (uint8_t)w;
+        w = 0;
+        for (int k = 0; k < nd; ++k) {
+            if ((drop >> k) & 1u) continue;
+            if (w != k) {
+                B.dih[w * n + i] = B.dih[k * n + i];
+                B.dt[w * n + i] = B.dt[k * n + i];
+            }
+            ++w;
+        }
+        purged |= w != nd;
+        B.nd[i] = (uint8_t)w;
     }
     // step 7: own bond entries (a conversion is listed among the removed entries)
     const int rm = S.rmcnt[i];
@@ -516,9 +603,19 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     // only beads within two bonds of a new bond can lie on a qualifying path
     // (flagged by k_mark_new)
     if (!ALL && !S.ngen[i]) return;
-    Tab Ti = load_tab(B, n, i);
+    const Tab Ti = load_tab_all(B, n, i);
     Gen g{P, B, S, n, ALL};
     const int gi = g.gid_of(i), ti = g.type_of(i);
+    // the partners' tables and types, requested together once (a missing
+    // partner reads bead i's own, unused)
+    Tab4 Tp;
+    Tp.a = load_tab_all(B, n, Ti.n > 0 ? Ti.p0 : i);
+    Tp.b = load_tab_all(B, n, Ti.n > 1 ? Ti.p1 : i);
+    Tp.c = load_tab_all(B, n, Ti.n > 2 ? Ti.p2 : i);
+    Tp.d = load_tab_all(B, n, Ti.n > 3 ? Ti.p3 : i);
+    const int ty0 = g.type_of(Ti.n > 0 ? Ti.p0 : i), ty1 = g.type_of(Ti.n > 1 ? Ti.p1 : i);
+    const int ty2 = g.type_of(Ti.n > 2 ? Ti.p2 : i), ty3 = g.type_of(Ti.n > 3 ? Ti.p3 : i);
+    auto ptype = [&](int k) { return k == 0 ? ty0 : (k == 1 ? ty1 : (k == 2 ? ty2 : ty3)); };
     int na = B.na[i], nd = B.nd[i];
     const int na0 = na, nd0 = nd;
     unsigned long long ang_new = 0, dih_new = 0;
@@ -558,7 +655,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
                 int a = Ti.p(k1), c = Ti.p(k2);
                 if (a == c) continue;
                 if (!(g.is_new(i, a) || g.is_new(i, c))) continue;
-                int t = match_angle(P, g.type_of(a), ti, g.type_of(c), Ti.t(k1), Ti.t(k2));
+                int t = match_angle(P, ptype(k1), ti, ptype(k2), Ti.t(k1), Ti.t(k2));
                 if (t) {
                     push_angle(a, i, c, t);
                     ++ang_new;
@@ -567,9 +664,9 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
         // angles with i at an end: i - b - c
         for (int k = 0; k < Ti.n; ++k) {
             int b = Ti.p(k);
-            Tab Tb = load_tab(B, n, b);
+            const Tab Tb = Tp.get(k);
             int t_bi = tab_type_of(Tb, i);
-            int tb = g.type_of(b);
+            int tb = ptype(k);
             for (int m = 0; m < Tb.n; ++m) {
                 int c = Tb.p(m);
                 if (c == i) continue;
@@ -583,13 +680,13 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
         // dihedrals with i at an end: i - b - c - d
         for (int k = 0; k < Ti.n; ++k) {
             int b = Ti.p(k);
-            Tab Tb = load_tab(B, n, b);
+            const Tab Tb = Tp.get(k);
             int t_bi = tab_type_of(Tb, i);
-            int tb = g.type_of(b);
+            int tb = ptype(k);
             for (int m = 0; m < Tb.n; ++m) {
                 int c = Tb.p(m);
                 if (c == i) continue;
-                Tab Tc = load_tab(B, n, c);
+                const Tab Tc = load_tab_all(B, n, c);
                 int t_cb = tab_type_of(Tc, b);
                 int tc = g.type_of(c);
                 for (int q = 0; q < Tc.n; ++q) {
@@ -604,14 +701,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
         // dihedrals with i second: a - i - c - d
         for (int k1 = 0; k1 < Ti.n; ++k1) {
             int a = Ti.p(k1);
-            int ta = g.type_of(a);
+            int ta = ptype(k1);
             for (int k2 = 0; k2 < Ti.n; ++k2) {
                 if (k2 == k1) continue;
                 int c = Ti.p(k2);
                 if (c == a) continue;
-                Tab Tc = load_tab(B, n, c);
+                const Tab Tc = Tp.get(k2);
                 int t_ci = tab_type_of(Tc, i);
-                int tc = g.type_of(c);
+                int tc = ptype(k2);
                 for (int q = 0; q < Tc.n; ++q) {
                     int d = Tc.p(q);
                     if (d == i || d == a) continue;
