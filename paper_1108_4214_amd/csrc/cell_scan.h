@@ -29,10 +29,14 @@ __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
 // four entries at a time.  Smaller grids visit every cell once and take the
 // per-candidate minimum image.  The visitor has a single call site per grid
 // case, which keeps it inlined once.
-template <class F>
+// PARTS > 1 splits one bead's scan over PARTS threads: the thread with the given
+// part takes the rows (or, on small grids, the cells) whose index is part modulo
+// PARTS; together the threads visit every candidate once.
+template <int PARTS = 1, class F>
 __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__ cstart,
                                            const float4* __restrict__ xs, int i, const double4& xi, float cut2,
-                                           F&& f) {
+                                           F&& f, int part = 0) {
+    static_assert(PARTS >= 1 && PARTS <= 9, "at most one thread per row");
     const int nc = X.nc;
     const int cx = cell_coord(xi.x, X.cell_scale, nc);
     const int cy = cell_coord(xi.y, X.cell_scale, nc);
@@ -68,15 +72,16 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
         auto row_of = [&](int r) {
             return (wrap_cell(cz + r / 3 - 1, nc) * nc + wrap_cell(cy + r % 3 - 1, nc)) * nc;
         };
-        int row = row_of(0);
+        const int r0 = PARTS == 1 ? 0 : part;
+        int row = row_of(r0);
         int s0 = cstart[row + a0], s1 = cstart[row + a1];
         int t0 = wrapx ? cstart[row + b0] : 0, t1 = wrapx ? cstart[row + b1] : 0;
-        for (int r = 0; r < 9; ++r) {
+        for (int r = r0; r < 9; r += PARTS) {
             const float qz = pz - shift(cz + r / 3 - 1), qy = py - shift(cy + r % 3 - 1);
             const int c0 = s0, d0 = t0;
             const int len0 = s1 - s0, len = len0 + (t1 - t0);
-            if (r < 8) {
-                row = row_of(r + 1);
+            if (r + PARTS < 9) {
+                row = row_of(r + PARTS);
                 s0 = cstart[row + a0];
                 s1 = cstart[row + a1];
                 t0 = wrapx ? cstart[row + b0] : 0;
@@ -103,11 +108,13 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
         }
         return;
     }
+    int cell_no = 0;
     for (int oz = 0; oz < X.noff; ++oz) {
         const int zz = wrap_cell(cz + X.off[oz], nc);
         for (int oy = 0; oy < X.noff; ++oy) {
             const int row = (zz * nc + wrap_cell(cy + X.off[oy], nc)) * nc;
             for (int ox = 0; ox < X.noff; ++ox) {
+                if (PARTS > 1 && cell_no++ % PARTS != part) continue;
                 const int c = row + wrap_cell(cx + X.off[ox], nc);
                 const int s0 = cstart[c], s1 = cstart[c + 1];
                 for (int p = s0; p < s1; ++p) {
@@ -129,10 +136,10 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
 // around xi: a reach of two cell edges, for lists redone with a cutoff beyond one
 // edge.  Needs at least five cells per edge (no cell is visited twice).  Each
 // candidate takes the minimum image; this serves only the few beads whose lists
-// are redone after a sweep.
-template <class F>
+// are redone after a sweep.  PARTS and part split the 25 rows as in scan_cells.
+template <int PARTS = 1, class F>
 __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, const float4* __restrict__ xs,
-                                int i, const double4& xi, float cut2, F&& f) {
+                                int i, const double4& xi, float cut2, F&& f, int part = 0) {
     const int nc = X.nc;
     const int cx = cell_coord(xi.x, X.cell_scale, nc);
     const int cy = cell_coord(xi.y, X.cell_scale, nc);
@@ -143,6 +150,7 @@ __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, co
     for (int oz = -2; oz <= 2; ++oz) {
         const int zz = wrap_cell(cz + oz, nc);
         for (int oy = -2; oy <= 2; ++oy) {
+            if (PARTS > 1 && ((oz + 2) * 5 + (oy + 2)) % PARTS != part) continue;
             const int row = (zz * nc + wrap_cell(cy + oy, nc)) * nc;
             for (int ox = -2; ox <= 2; ++ox) {
                 const int c = row + wrap_cell(cx + ox, nc);

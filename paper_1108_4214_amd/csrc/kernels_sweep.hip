@@ -161,20 +161,17 @@ __global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
     if (S.aoff[i + 1] > o) S.act[o] = i;
 }
 
-// one thread per listed bead; the grid covers every bead, the workgroups past the
-// list's end return at once
+// CREATE_LANES threads per listed bead, each scanning a share of the cell rows;
+// the group's nominee is the least (r^2, id) of its members' nominees, which is
+// what one thread scanning every row in any order would find.  The listed range
+// is split per XCD; the workgroups step over the tiles of the list, so that a
+// list longer than the grid's share is covered too.
+constexpr int CREATE_LANES = 8;
+
 template <bool BATCH>
-__global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
-                                                              const int* __restrict__ cstart,
-                                                              const float4* __restrict__ xs, SweepBuf S) {
-    const Params& P = *Pp;
-    const int n = P.n;
-    const int nl = S.aoff[n];
-    const int ntile = (nl + DB_BLOCK - 1) / DB_BLOCK;
-    if ((int)blockIdx.x >= ntile) return;
-    const int t = xcd_tile(blockIdx.x, ntile) * DB_BLOCK + threadIdx.x;   // listed range split per XCD
-    if (t >= nl) return;
-    const int i = S.act[t];
+__device__ __forceinline__ void nominate_create_one(const Params& P, const int n, const Bank& B,
+                                                    const int* __restrict__ cstart, const float4* __restrict__ xs,
+                                                    const SweepBuf& S, const int i, const int lane) {
     const double4 xi = B.x[i];
     const int mi = meta_word(xi);
     const Box& X = box_of<BATCH>(P, mi);
@@ -257,12 +254,48 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
                 best_bt = bti;
             }
         };
-        if (X.wide_create) scan_cells_wide(X, cstart, xs, i, xi, cut2, visit);
-        else scan_cells(X, cstart, xs, i, xi, cut2, visit);
+        if (X.wide_create) scan_cells_wide<CREATE_LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
+        else scan_cells<CREATE_LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
     }
-    S.nomC[i] = best;
-    S.ruleC[i] = (int8_t)best_rule;
-    S.btC[i] = (int8_t)best_bt;
+    // the group's least (r^2, id), exchanged within the aligned group of lanes
+#pragma unroll
+    for (int o = 1; o < CREATE_LANES; o <<= 1) {
+        const double r2o = __shfl_xor(best_r2, o, 64);
+        const int go = __shfl_xor(best_g, o, 64);
+        const int jo = __shfl_xor(best, o, 64);
+        const int ro = __shfl_xor(best_rule, o, 64);
+        const int bo = __shfl_xor(best_bt, o, 64);
+        if (jo >= 0 && (best < 0 || r2o < best_r2 || (r2o == best_r2 && go < best_g))) {
+            best = jo;
+            best_r2 = r2o;
+            best_g = go;
+            best_rule = ro;
+            best_bt = bo;
+        }
+    }
+    if (lane == 0) {
+        S.nomC[i] = best;
+        S.ruleC[i] = (int8_t)best_rule;
+        S.btC[i] = (int8_t)best_bt;
+    }
+}
+
+template <bool BATCH>
+__global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
+                                                              const int* __restrict__ cstart,
+                                                              const float4* __restrict__ xs, SweepBuf S) {
+    static_assert(64 % CREATE_LANES == 0 && DB_BLOCK % 64 == 0, "groups lie within a wavefront");
+    const Params& P = *Pp;
+    const int n = P.n;
+    const int nl = S.aoff[n];
+    const int ntile = (int)(((long long)nl * CREATE_LANES + DB_BLOCK - 1) / DB_BLOCK);
+    for (int tb = blockIdx.x; tb < ntile; tb += gridDim.x) {
+        const long long pos = (long long)xcd_tile(tb, ntile) * DB_BLOCK + threadIdx.x;
+        const int t = (int)(pos / CREATE_LANES);
+        const int lane = (int)(pos % CREATE_LANES);
+        // the lanes of a group share t: they take this branch together
+        if (t < nl) nominate_create_one<BATCH>(P, n, B, cstart, xs, S, S.act[t], lane);
+    }
 }
 
 // ---- steps 3 and 5: breakage nomination and killbond marks ----------------------
