@@ -136,6 +136,21 @@ def test_sweep_isolated_pairs(p):
     assert _stats_equal(g, o)
 
 
+@pytest.mark.parametrize("L,n", [(3.0, 30), (4.2, 60)])
+def test_sweep_small_grid(L, n):
+    """Boxes of one and two cells per edge, where the scan visits every cell once
+    (and the creation scan splits the cells over its lanes): a sweep against the
+    oracle, with creations, breaks and maxbond."""
+    s = synth.random_gas(n, L, seed=5, n_types=2)
+    s.bonds = np.array([(0, 1, 1, 1), (2, 3, 1, 1)], dtype=np.int32)
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 0.8), ("break", 1, 1.2, 0.6),
+                                          ("maxbond", 1, 0, 2)])
+    g, o = _sweep_both(s, synth.ForceField(), rules, step=11)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+    assert o.counts()[0] > 2
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_sweep_dense_gas_with_bonds(seed):
     s = synth.random_gas(2500, 14.0, seed=seed, n_types=4)
