@@ -605,8 +605,6 @@ __device__ __forceinline__ void dihedral_terms(const Params& P, const Box& X, co
 // bead i, instead of once per entry that names it.
 //   acode: role (2 bits) | other member 1 << 2 | other member 2 << 5 | type << 8
 //   dcode: role (2 bits) | others 1..3 << 2, 5, 8 (3 bits each) | type << 11
-// sweep_stats: the counters of a sweep that ran since the last build, which is
-// then repeated only if that sweep changed a bond (NULL: rebuild regardless)
 // only == nullptr: every bead; else only the beads flagged there (those whose own
 // tables the last sweep changed: a bead's halo depends on its own tables alone)
 __global__ __launch_bounds__(DB_BLOCK) void k_halo(const Params* __restrict__ Pp, Bank B, Halo H,
