@@ -233,47 +233,81 @@ __global__ __launch_bounds__(DB_BLOCK) void k_newslot(int n, const int* __restri
     if (s < n) newslot[list[s]] = s;
 }
 
+// 1 for the beads (in cell order) that hold a bond, which are the ones with bonded terms
+__global__ __launch_bounds__(DB_BLOCK) void k_bonded_flags(int n, const int* __restrict__ list,
+                                                           const uint8_t* __restrict__ nb, int* __restrict__ flag) {
+    int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (s < n) flag[s] = nb[list[s]] > 0 ? 1 : 0;
+}
+
+// Slots in cell order, except that within each XCD's share of the slots (the
+// contiguous tile range xcd_tile gives it; the tail is a share of its own) the
+// bonded beads come first.  A wavefront then holds bonded beads only or none, so
+// that solvent waves skip the bonded terms instead of waiting on the one bonded
+// bead among them, and each XCD keeps its share of both kinds.  off: exclusive
+// prefix sums of the flags in cell order, off[n] their total.
+__global__ __launch_bounds__(DB_BLOCK) void k_newslot_bonded_first(int n, const int* __restrict__ list,
+                                                                   const int* __restrict__ off,
+                                                                   int* __restrict__ newslot) {
+    int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (s >= n) return;
+    const int per = ((n + DB_BLOCK - 1) / DB_BLOCK) >> 3;
+    const int share = per * DB_BLOCK;
+    int st, en;
+    if (share > 0 && s < 8 * share) {
+        st = (s / share) * share;
+        en = min(st + share, n);   // the last tile may be partial: the eighth share can end short
+    } else {
+        st = 8 * share;
+        en = n;
+    }
+    const int before = off[s] - off[st];   // bonded beads of the share ahead of s
+    const int bonded = off[en] - off[st];
+    newslot[list[s]] = off[s + 1] > off[s] ? st + before : st + bonded + (s - st - before);
+}
+
 __global__ __launch_bounds__(DB_BLOCK) void k_permute(int n, Bank src, Bank dst, int* __restrict__ list,
                                                        const int* __restrict__ newslot, int* __restrict__ slot_of_gid,
                                                        double4* __restrict__ xsave, double* __restrict__ vsave,
                                                        float4* __restrict__ xs) {
-    int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    int s = blockIdx.x * DB_BLOCK + threadIdx.x;   // position in cell order
     if (s >= n) return;
     int o = list[s];
+    const int d = newslot[o];   // the bead's new slot
     double4 x = src.x[o];
     double vx = src.v[o], vy = src.v[n + o], vz = src.v[2 * n + o];
-    dst.x[s] = x;
-    dst.v[s] = vx;
-    dst.v[n + s] = vy;
-    dst.v[2 * n + s] = vz;
+    dst.x[d] = x;
+    dst.v[d] = vx;
+    dst.v[n + d] = vy;
+    dst.v[2 * n + d] = vz;
     if (xsave) {   // copy kept for re-running the block
-        xsave[s] = x;
-        vsave[s] = vx;
-        vsave[n + s] = vy;
-        vsave[2 * n + s] = vz;
+        xsave[d] = x;
+        vsave[d] = vx;
+        vsave[n + d] = vy;
+        vsave[2 * n + d] = vz;
     }
-    slot_of_gid[meta_gid(x)] = s;
+    slot_of_gid[meta_gid(x)] = d;
     int nb = src.nb[o];
-    dst.nb[s] = (uint8_t)nb;
+    dst.nb[d] = (uint8_t)nb;
     for (int k = 0; k < nb; ++k) {
-        dst.bp[k * n + s] = newslot[src.bp[k * n + o]];
-        dst.bt[k * n + s] = src.bt[k * n + o];
+        dst.bp[k * n + d] = newslot[src.bp[k * n + o]];
+        dst.bt[k * n + d] = src.bt[k * n + o];
     }
     int na = src.na[o];
-    dst.na[s] = (uint8_t)na;
+    dst.na[d] = (uint8_t)na;
     for (int k = 0; k < na; ++k) {
         int4 e = src.ang[k * n + o];
-        dst.ang[k * n + s] = make_int4(newslot[e.x], newslot[e.y], newslot[e.z], e.w);
+        dst.ang[k * n + d] = make_int4(newslot[e.x], newslot[e.y], newslot[e.z], e.w);
     }
     int nd = src.nd[o];
-    dst.nd[s] = (uint8_t)nd;
+    dst.nd[d] = (uint8_t)nd;
     for (int k = 0; k < nd; ++k) {
         int4 e = src.dih[k * n + o];
-        dst.dih[k * n + s] = make_int4(newslot[e.x], newslot[e.y], newslot[e.z], newslot[e.w]);
-        dst.dt[k * n + s] = src.dt[k * n + o];
+        dst.dih[k * n + d] = make_int4(newslot[e.x], newslot[e.y], newslot[e.z], newslot[e.w]);
+        dst.dt[k * n + d] = src.dt[k * n + o];
     }
-    list[s] = s;   // the cells now hold contiguous slot ranges
-    xs[s].w = xs_word(s, meta_word(x));
+    list[s] = d;   // the cell list now names the new slots
+    xs[s].w = xs_word(d, meta_word(x));
 }
 
 void launch_permute(db_ctx* c, bool save) {
@@ -282,7 +316,17 @@ void launch_permute(db_ctx* c, bool save) {
     hipStream_t s = c->stream;
     unsigned nb = (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK);
     int* newslot = c->cells.cellid;   // the bin ids are no longer needed
-    hipLaunchKernelGGL(k_newslot, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, newslot);
+    if (c->nrep == 0) {
+        // bonded beads first within each XCD's share; the sweep's flag and offset
+        // arrays are free while the cells are reordered
+        hipLaunchKernelGGL(k_bonded_flags, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, c->bank[c->cur].nb,
+                           c->sw.act);
+        launch_scan_total(c->sw.act, c->sw.aoff, n, c->cells.blocksum, s);
+        hipLaunchKernelGGL(k_newslot_bonded_first, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, c->sw.aoff,
+                           newslot);
+    } else {
+        hipLaunchKernelGGL(k_newslot, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, newslot);
+    }
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->bank[c->cur], c->bank[1 - c->cur],
                        c->cells.list, newslot, c->slot_of_gid, save ? c->xsave : (double4*)nullptr,
                        save ? c->vsave : (double*)nullptr, c->cells.xs);
