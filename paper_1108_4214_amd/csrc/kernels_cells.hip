@@ -227,7 +227,7 @@ void launch_build_cells(db_ctx* c) {
     }
 }
 
-// ---- permutation of the whole per-bead state into cell order -------------------
+// ---- permutation of the whole per-bead state into the new slot order ----------
 __global__ __launch_bounds__(DB_BLOCK) void k_newslot(int n, const int* __restrict__ list, int* __restrict__ newslot) {
     int s = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (s < n) newslot[list[s]] = s;
