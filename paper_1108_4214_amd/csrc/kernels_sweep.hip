@@ -585,9 +585,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
 // Angle ABC: bead types match and t(B->A) in S1, t(B->C) in S2; else CBA.
 // Dihedral ABCD: bead types match, t(B->A) in S1, t(C->B) or t(B->C) in S2,
 // t(C->D) in S3; else DCBA.  The first rule in table order that matches wins.
-__device__ int match_angle(const Params& P, int ta, int tb, int tc, int t_ba, int t_bc) {
-    for (int q = 0; q < P.narule; ++q) {
-        const AngRule& r = P.arule[q];
+// (nrule rules of the table at rules, which the generation pass keeps in LDS)
+__device__ int match_angle(int nrule, const AngRule* rules, int ta, int tb, int tc, int t_ba, int t_bc) {
+    for (int q = 0; q < nrule; ++q) {
+        const AngRule& r = rules[q];
         if (type_ok(r.b[0], ta) && type_ok(r.b[1], tb) && type_ok(r.b[2], tc) && in_mask(r.m[0], t_ba) &&
             in_mask(r.m[1], t_bc))
             return r.type;
@@ -598,10 +599,10 @@ __device__ int match_angle(const Params& P, int ta, int tb, int tc, int t_ba, in
     return 0;
 }
 
-__device__ int match_dihedral(const Params& P, int ta, int tb, int tc, int td, int t_ba, int t_bc, int t_cb,
-                              int t_cd) {
-    for (int q = 0; q < P.ndrule; ++q) {
-        const DihRule& r = P.drule[q];
+__device__ int match_dihedral(int nrule, const DihRule* rules, int ta, int tb, int tc, int td, int t_ba, int t_bc,
+                              int t_cb, int t_cd) {
+    for (int q = 0; q < nrule; ++q) {
+        const DihRule& r = rules[q];
         if (type_ok(r.b[0], ta) && type_ok(r.b[1], tb) && type_ok(r.b[2], tc) && type_ok(r.b[3], td) &&
             in_mask(r.m[0], t_ba) && (in_mask(r.m[1], t_cb) || in_mask(r.m[1], t_bc)) && in_mask(r.m[2], t_cd))
             return r.type;
@@ -629,13 +630,23 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
     const Params& P = *Pp;
     const int n = P.n;
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
     if (P.narule == 0 && P.ndrule == 0) return;
     // no bond was created or converted in this sweep: nothing to generate
     if (!ALL && (S.stats[ST_CREATED] | S.stats[ST_CONVERTED]) == 0) return;
     // only beads within two bonds of a new bond can lie on a qualifying path
     // (flagged by k_mark_new)
-    if (!ALL && !S.ngen[i]) return;
+    const bool mine = i < n && (ALL || S.ngen[i]);
+    // The pattern rules are matched from LDS: a workgroup holding a bead to work
+    // on copies them once.  After a sweep few wavefronts run this pass, and read
+    // from memory one rule at a time the rules cost a cache miss each.
+    __shared__ AngRule sar[DB_MAXRULES];
+    __shared__ DihRule sdr[DB_MAXRULES];
+    if (!__syncthreads_or(mine)) return;
+    for (int t = threadIdx.x; t < P.narule; t += DB_BLOCK) sar[t] = P.arule[t];
+    for (int t = threadIdx.x; t < P.ndrule; t += DB_BLOCK) sdr[t] = P.drule[t];
+    __syncthreads();
+    if (!mine) return;
+    const int nar = P.narule, ndr = P.ndrule;
     const Tab Ti = load_tab_all(B, n, i);
     Gen g{P, B, S, n, ALL};
     const int gi = g.gid_of(i), ti = g.type_of(i);
@@ -688,7 +699,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
                 int a = Ti.p(k1), c = Ti.p(k2);
                 if (a == c) continue;
                 if (!(g.is_new(i, a) || g.is_new(i, c))) continue;
-                int t = match_angle(P, ptype(k1), ti, ptype(k2), Ti.t(k1), Ti.t(k2));
+                int t = match_angle(nar, sar, ptype(k1), ti, ptype(k2), Ti.t(k1), Ti.t(k2));
                 if (t) {
                     push_angle(a, i, c, t);
                     ++ang_new;
@@ -704,7 +715,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
                 int c = Tb.p(m);
                 if (c == i) continue;
                 if (!(g.is_new(i, b) || g.is_new(b, c))) continue;
-                int t = match_angle(P, ti, tb, g.type_of(c), t_bi, Tb.t(m));
+                int t = match_angle(nar, sar, ti, tb, g.type_of(c), t_bi, Tb.t(m));
                 if (t) push_angle(i, b, c, t);
             }
         }
@@ -726,7 +737,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
                     int d = Tc.p(q);
                     if (d == b || d == i) continue;
                     if (!(g.is_new(i, b) || g.is_new(b, c) || g.is_new(c, d))) continue;
-                    int t = match_dihedral(P, ti, tb, tc, g.type_of(d), t_bi, Tb.t(m), t_cb, Tc.t(q));
+                    int t = match_dihedral(ndr, sdr, ti, tb, tc, g.type_of(d), t_bi, Tb.t(m), t_cb, Tc.t(q));
                     if (t) push_dih(i, b, c, d, t);
                 }
             }
@@ -746,7 +757,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_generate(const Params* __restrict_
                     int d = Tc.p(q);
                     if (d == i || d == a) continue;
                     if (!(g.is_new(a, i) || g.is_new(i, c) || g.is_new(c, d))) continue;
-                    int t = match_dihedral(P, ta, ti, tc, g.type_of(d), Ti.t(k1), Ti.t(k2), t_ci, Tc.t(q));
+                    int t = match_dihedral(ndr, sdr, ta, ti, tc, g.type_of(d), Ti.t(k1), Ti.t(k2), t_ci, Tc.t(q));
                     if (t && push_dih(a, i, c, d, t)) ++dih_new;
                 }
             }
