@@ -194,6 +194,17 @@ int db_sweep_now(db_ctx* ctx);
 int db_forces(db_ctx* ctx, double* f, int on_device);
 /* out = {kinetic (full-step velocities), U_pair, U_bond, U_angle, U_dihedral, virial} */
 int db_energy(db_ctx* ctx, double out[6]);
+/* db_energy for callers that cannot allocate device or pinned memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the same
+ * kernels and the same result, bit for bit, with the energy kernel's partial
+ * sums in a fixed device array of the library (3 MiB per device, held until the
+ * process ends) instead of the handle's workspace.  Makes no allocation of any
+ * kind.  At most 16,777,216 beads (DB_EINVAL beyond).  DB_ESTATE unless the
+ * handle's device memory is set up and its state and parameters are current on
+ * the device: after any setter, run one db_step, db_forces or db_energy first.
+ * All handles on one device share that array, so calls that overlap on one
+ * device (from several threads or streams) race; calls in sequence do not. */
+int db_energy_noalloc(db_ctx* ctx, double out[6]);
 int db_get_state(db_ctx* ctx, double* x, double* v, int on_device);
 int db_topology_counts(db_ctx* ctx, int64_t* nb, int64_t* na, int64_t* nd);
 /* canonical, sorted lists: bonds i<j; angles a<c; dihedrals a<d (path reversed if needed) */

@@ -34,6 +34,7 @@ EXPORTS = [
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
     "db_batch_create", "db_batch_get_state", "db_track_topology_energy", "db_external_force",
+    "db_energy_noalloc",
 ]
 
 STAT_FIELDS = [
@@ -100,6 +101,7 @@ _SIG = {
     "db_sweep_now": [_P],
     "db_forces": [_P, _P, _int],
     "db_energy": [_P, _P],
+    "db_energy_noalloc": [_P, _P],
     "db_get_state": [_P, _P, _P, _int],
     "db_topology_counts": [_P, _P, _P, _P],
     "db_get_bonds": [_P, _P, _P, _P],
@@ -315,6 +317,12 @@ def db_forces(ctx, out):
 def db_energy(ctx):
     e = np.zeros(6)
     _check(ctx, _lib.db_energy(ctx, _ptr(e)))
+    return e
+
+
+def db_energy_noalloc(ctx):
+    e = np.zeros(6)
+    _check(ctx, _lib.db_energy_noalloc(ctx, _ptr(e)))
     return e
 
 

@@ -21,12 +21,25 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
 #include "db_device.h"
 
 using namespace db;
+
+// ------------------------------------------------------------------------------------
+// Scratch of db_energy_noalloc: the per-workgroup partial sums of the energy kernel
+// and the six final sums, in a fixed device array (each device holds its own copy for
+// the life of the process).  Host code never uses the array's name as an address: the
+// device address of each device's copy is looked up once, with that device current,
+// when the first handle on it sets up its memory, and kept in noalloc_ptr.
+#define DB_NOALLOC_MAX_BLOCKS 65536   // energy workgroups: n <= 65536 * DB_BLOCK beads
+static __device__ __align__(256) double scratch[6 * DB_NOALLOC_MAX_BLOCKS + 8];
+static constexpr int kMaxDevices = 64;
+static double* noalloc_ptr[kMaxDevices];
+static std::mutex noalloc_mutex;
 
 namespace {
 
@@ -205,8 +218,25 @@ static size_t layout(db_ctx* c, bool assign) {
     return L.total;
 }
 
+// the device address of this device's copy of the no-allocation scratch, once per device
+static int noalloc_setup(db_ctx* c) {
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, DB_EDEVICE, "device ordinal %d beyond %d", dev, kMaxDevices);
+    c->device = dev;
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        noalloc_ptr[dev] = (double*)p;
+    }
+    return DB_OK;
+}
+
 static int ensure_memory(db_ctx* c) {
     if (c->allocated) return DB_OK;
+    int rc0 = noalloc_setup(c);
+    if (rc0) return rc0;
     size_t need = layout(c, false);
     if (!c->arena) {
         void* p = nullptr;
@@ -435,14 +465,14 @@ __global__ void k_gather_state(int n, Bank B, double* __restrict__ xo, double* _
 }
 
 // scratch for gathers: the per-bead storage of the inactive bank (free between reorders)
-static char* scratch(db_ctx* c, size_t bytes) {
+static char* gather_scratch(db_ctx* c, size_t bytes) {
     Bank& O = c->bank[1 - c->cur];
     size_t avail = (size_t)((char*)O.nd - (char*)O.ang);
     (void)avail;
     (void)bytes;
     return (char*)O.ang;
 }
-static size_t scratch_bytes(db_ctx* c) {
+static size_t gather_scratch_bytes(db_ctx* c) {
     Bank& O = c->bank[1 - c->cur];
     return (size_t)((char*)O.nd - (char*)O.ang);
 }
@@ -464,8 +494,8 @@ static int read_owned(db_ctx* c, int kind, std::vector<int32_t>& tup, std::vecto
     int64_t m = ext(c).pin->total[0];
     *count = m;
     size_t need = (size_t)m * 4 * (width + twidth);
-    if (need > scratch_bytes(c)) return fail(c, DB_ECAPACITY, "topology list larger than the gather scratch");
-    int32_t* dtup = (int32_t*)scratch(c, need);
+    if (need > gather_scratch_bytes(c)) return fail(c, DB_ECAPACITY, "topology list larger than the gather scratch");
+    int32_t* dtup = (int32_t*)gather_scratch(c, need);
     int32_t* dtyp = dtup + (size_t)m * width;
     launch_write_owned(c, kind, off, dtup, dtyp);
     tup.resize((size_t)m * width);
@@ -486,7 +516,7 @@ static int download_system(db_ctx* c) {
     const int n = c->n;
     HostSys& h = X.h;
     if (n > 0) {
-        double* d = (double*)scratch(c, 48 * (size_t)n);
+        double* d = (double*)gather_scratch(c, 48 * (size_t)n);
         hipLaunchKernelGGL(k_gather_state, dim3((n + DB_BLOCK - 1) / DB_BLOCK), dim3(DB_BLOCK), 0, c->stream, n,
                            c->bank[c->cur], d, d + 3 * (size_t)n);
         HIPCHK(c, hipMemcpyAsync(h.x.data(), d, 24 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
@@ -611,6 +641,7 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->seed = seed;
     c->precision = precision;
     c->stream = (hipStream_t)stream;
+    c->device = -1;
     memset(&c->hp, 0, sizeof(Params));
     Params& P = c->hp;
     P.n = n;
@@ -1276,7 +1307,7 @@ int db_forces(db_ctx* c, double* f, int on_device) {
     if (rc) return rc;
     rebuild(c, false);
     launch_build_nlist(c);
-    double* d = on_device ? f : (double*)scratch(c, 24 * (size_t)c->n);
+    double* d = on_device ? f : (double*)gather_scratch(c, 24 * (size_t)c->n);
     launch_forces(c, d);
     if (!on_device && c->n) HIPCHK(c, hipMemcpyAsync(f, d, 24 * (size_t)c->n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&ext(c).pin->err, c->err_d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1290,12 +1321,36 @@ int db_energy(db_ctx* c, double out[6]) {
     int rc = ready(c);
     if (rc) return rc;
     rebuild(c, false);
-    double* d = (double*)scratch(c, 64);
+    double* d = (double*)gather_scratch(c, 64);
     launch_energy(c, d);
     HIPCHK(c, hipMemcpyAsync(ext(c).pin->energy, d, 48, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGetLastError());
     memcpy(out, ext(c).pin->energy, 48);
+    return DB_OK;
+}
+
+int db_energy_noalloc(db_ctx* c, double out[6]) {
+    if (!c || !out) return DB_EINVAL;
+    if ((int64_t)c->n > (int64_t)DB_NOALLOC_MAX_BLOCKS * DB_BLOCK)
+        return fail(c, DB_EINVAL, "db_energy_noalloc takes at most %d beads (%d given)",
+                    DB_NOALLOC_MAX_BLOCKS * DB_BLOCK, c->n);
+    db_host_ext& X = ext(c);
+    if (!c->have_state) return fail(c, DB_ESTATE, "db_set_state has not been called");
+    if (X.dev_error) return fail(c, X.dev_error, "a previous device error left the state undefined: %s", c->err.c_str());
+    // everything an allocating call would set up first must already be in place
+    if (!c->allocated || !X.dev_valid || c->params_dirty)
+        return fail(c, DB_ESTATE, "db_energy_noalloc needs device state and parameters that are current: "
+                                  "run db_step, db_forces or db_energy once after the last change");
+    double* part = (c->device >= 0 && c->device < kMaxDevices) ? noalloc_ptr[c->device] : nullptr;
+    if (!part) return fail(c, DB_ESTATE, "no scratch address for device %d", c->device);
+    double* sums = part + 6 * (size_t)DB_NOALLOC_MAX_BLOCKS;
+    rebuild(c, false);
+    launch_energy(c, sums, part);
+    HIPCHK(c, hipMemcpyAsync(X.pin->energy, sums, 48, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    memcpy(out, X.pin->energy, 48);
     return DB_OK;
 }
 
@@ -1315,7 +1370,7 @@ int db_get_state(db_ctx* c, double* x, double* v, int on_device) {
         return DB_OK;
     }
     if (n == 0) return DB_OK;
-    double* d = (double*)scratch(c, 48 * n);
+    double* d = (double*)gather_scratch(c, 48 * n);
     hipLaunchKernelGGL(k_gather_state, dim3((unsigned)((n + DB_BLOCK - 1) / DB_BLOCK)), dim3(DB_BLOCK), 0, c->stream,
                        (int)n, c->bank[c->cur], d, d + 3 * n);
     hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1572,7 +1627,7 @@ int db_batch_get_state(db_ctx* c, int32_t r, double* x, double* v, int on_device
         return DB_OK;
     }
     if (nr == 0) return DB_OK;
-    double* d = (double*)scratch(c, 48 * n);
+    double* d = (double*)gather_scratch(c, 48 * n);
     hipLaunchKernelGGL(k_gather_state, dim3((unsigned)((n + DB_BLOCK - 1) / DB_BLOCK)), dim3(DB_BLOCK), 0, c->stream,
                        (int)n, c->bank[c->cur], d, d + 3 * n);
     hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;

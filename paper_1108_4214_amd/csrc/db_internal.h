@@ -174,6 +174,7 @@ struct db_ctx {
     uint64_t seed;
     int precision;
     hipStream_t stream;
+    int device;          // the HIP device current at creation
     std::string err;
 
     db::Params hp;       // host copy
@@ -266,7 +267,8 @@ void launch_patch_nlist(db_ctx* c, double cut);
 // save: keep the input x, v (the block's input state, for a re-run)
 void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save = false);
 void launch_forces(db_ctx* c, double* f_gid_order);
-void launch_energy(db_ctx* c, double* out6_device);
+// partials: 6 doubles per workgroup of the energy kernel (nullptr: the arena's own)
+void launch_energy(db_ctx* c, double* out6_device, double* partials = nullptr);
 
 // kernels_sweep.hip
 void launch_sweep(db_ctx* c, int64_t step);

@@ -1152,24 +1152,25 @@ void launch_forces(db_ctx* c, double* f) {
 }
 
 template <typename R, bool BATCH>
-static void launch_energy_kernel(db_ctx* c, unsigned nb) {
+static void launch_energy_kernel(db_ctx* c, unsigned nb, double* part) {
     hipLaunchKernelGGL((k_energy<R, BATCH>), dim3(nb), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur],
-                       c->cells.start, c->cells.list, c->step, c->red);
+                       c->cells.start, c->cells.list, c->step, part);
 }
 
-void launch_energy(db_ctx* c, double* out6) {
+void launch_energy(db_ctx* c, double* out6, double* partials) {
     unsigned nb = grid_for(c->n);
+    double* part = partials ? partials : c->red;
     if (c->n > 0) {
         const bool batch = c->nrep > 0;
         if (c->precision == DB_MIXED) {
-            if (batch) launch_energy_kernel<float, true>(c, nb);
-            else launch_energy_kernel<float, false>(c, nb);
+            if (batch) launch_energy_kernel<float, true>(c, nb, part);
+            else launch_energy_kernel<float, false>(c, nb, part);
         } else {
-            if (batch) launch_energy_kernel<double, true>(c, nb);
-            else launch_energy_kernel<double, false>(c, nb);
+            if (batch) launch_energy_kernel<double, true>(c, nb, part);
+            else launch_energy_kernel<double, false>(c, nb, part);
         }
     }
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, c->stream, c->red, (int)(c->n > 0 ? nb : 0), out6);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, c->stream, part, (int)(c->n > 0 ? nb : 0), out6);
 }
 
 }  // namespace db
