@@ -162,6 +162,17 @@ int db_temperature_ramp(db_ctx* ctx, double T0, double T1, int64_t n_steps);
 /* sweep every `every` steps (0 = never); paircheck13/14 admit beads two / three
  * bonds apart as creation partners */
 int db_sweep_every(db_ctx* ctx, int32_t every, int paircheck13, int paircheck14);
+/* How a mutual pair's acceptance test draws its random number (appendix steps 5
+ * and 7).  DB_ACCEPT_PAIR (default): one 53-bit uniform u per unordered pair,
+ * Philox4x32-10 keyed by (lower id, higher id, step, stream tag 1 create / 2
+ * break) and the seed; accept iff u < p, so the acceptance probability is p.
+ * DB_ACCEPT_AVERAGE, the appendix's literal form: each bead draws its own
+ * uniform (counter (id, id, step, tag)), the pair accepts iff the mean of the two
+ * is below p; the probability is then 2p^2 for p <= 1/2 and 1 - 2(1-p)^2 above.
+ * Either way both beads reach the same decision.  EINVAL for another mode. */
+#define DB_ACCEPT_PAIR 0
+#define DB_ACCEPT_AVERAGE 1
+int db_acceptance(db_ctx* ctx, int mode);
 /* createbond: symmetric bond of type bt between bead types bead1, bead2 when
  * r < r_max, with probability p */
 int db_bond_create(db_ctx* ctx, int32_t bt, int32_t bead1, int32_t bead2, double r_max, double p);

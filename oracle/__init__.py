@@ -55,6 +55,7 @@ def lib():
             "or_langevin": (C.c_int, [P, d, d, d]),
             "or_temperature_ramp": (C.c_int, [P, d, d, i64]),
             "or_sweep_every": (C.c_int, [P, i32, C.c_int, C.c_int]),
+            "or_acceptance": (C.c_int, [P, C.c_int]),
             "or_bond_create": (C.c_int, [P, i32, i32, i32, d, d]),
             "or_bond_create_dir": (C.c_int, [P, i32, i32, i32, i32, d, d]),
             "or_bond_break": (C.c_int, [P, i32, d, d]),
@@ -185,6 +186,7 @@ class Oracle:
     def set_rules(self, rs):
         L = lib()
         _chk(L.or_sweep_every(self._h, rs.every, rs.paircheck13, rs.paircheck14), "or_sweep_every")
+        _chk(L.or_acceptance(self._h, 1 if rs.accept == "average" else 0), "or_acceptance")
         for r in rs.rules:
             k = r[0]
             if k == "create":

@@ -73,6 +73,7 @@ struct or_sys {
     angrule_t arule[MAXRULES]; int narule;
     dihrule_t drule[MAXRULES]; int ndrule;
 
+    int accept_average;             /* 1: the appendix's averaged per-bead uniforms */
     int64_t step, swept_step;
     int64_t stat_last[8], stat_cum[8], sweeps;
     int *nomC, *nomK;
@@ -123,6 +124,26 @@ static double pair_uniform(const or_sys* s, int i, int j, int64_t step, uint32_t
     draw(s, lo, hi, step, kind, w);
     uint64_t bits = (((uint64_t)w[0] << 32) | (uint64_t)w[1]) >> 11;
     return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+/* uniform on [0,1) with 53 random bits drawn by bead i alone (its counter names
+ * the bead twice, which no pair draw does) */
+static double bead_uniform(const or_sys* s, int i, int64_t step, uint32_t kind) {
+    uint32_t w[4];
+    draw(s, (uint32_t)i, (uint32_t)i, step, kind, w);
+    uint64_t bits = (((uint64_t)w[0] << 32) | (uint64_t)w[1]) >> 11;
+    return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+/* The number a mutual pair's acceptance compares with p (appendix, steps 5 and 7).
+ * Default: one uniform for the pair.  Literal form: every bead draws its own
+ * uniform, the pair takes the mean of the two and accepts when it is below p, so
+ * that both beads reach the same decision; the acceptance probability is then
+ * 2p^2 for p <= 1/2 and 1 - 2(1 - p)^2 above. */
+static double accept_number(const or_sys* s, int i, int j, int64_t step, uint32_t kind) {
+    if (!s->accept_average) return pair_uniform(s, i, j, step, kind);
+    int lo = i < j ? i : j, hi = i < j ? j : i;
+    return (bead_uniform(s, lo, step, kind) + bead_uniform(s, hi, step, kind)) * 0.5;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -353,6 +374,11 @@ int or_langevin(or_sys* s, double T, double gamma, double dt) {
 int or_temperature_ramp(or_sys* s, double T0, double T1, int64_t n) {
     if (n < 0) return -1;
     s->T0 = T0; s->T1 = T1; s->ramp = n; return 0;
+}
+int or_acceptance(or_sys* s, int mode) {
+    if (mode != 0 && mode != 1) return -1;
+    s->accept_average = mode;
+    return 0;
 }
 int or_sweep_every(or_sys* s, int32_t every, int pc13, int pc14) {
     if (every < 0) return -1;
@@ -955,7 +981,7 @@ static int sweep(or_sys* s, int64_t step) {
         int k = bond_between(s, i, j);
         if (killed[k]) continue;
         const rule_t* r = &s->rule[ruleK[i]];
-        if (pair_uniform(s, i, j, step, KIND_BREAK) < r->p) {
+        if (accept_number(s, i, j, step, KIND_BREAK) < r->p) {
             removed[k] = 1;
             if (r->kind == R_CONVERT) { conv_to[k] = r->bt2; conv_bead[i] = conv_bead[j] = 1; st[3]++; }
             else st[1]++;
@@ -1007,7 +1033,7 @@ static int sweep(or_sys* s, int64_t step) {
         if (j < 0 || j < i || bestC[j] != i) continue;
         if (conv_bead[i] || conv_bead[j]) continue;
         const rule_t* r = &s->rule[ruleC[i]];
-        if (pair_uniform(s, i, j, step, KIND_CREATE) < r->p) {
+        if (accept_number(s, i, j, step, KIND_CREATE) < r->p) {
             push_bond(s, i, j, btC[i], btC[j]);
             st[0]++;
         }

@@ -56,6 +56,8 @@ int or_langevin(or_sys* s, double T, double gamma, double dt);
 int or_temperature_ramp(or_sys* s, double T0, double T1, int64_t n_steps);
 
 int or_sweep_every(or_sys* s, int32_t every, int paircheck13, int paircheck14);
+/* 0: one uniform per pair (default); 1: the mean of one uniform per bead (appendix steps 5, 7) */
+int or_acceptance(or_sys* s, int mode);
 int or_bond_create(or_sys* s, int32_t bt, int32_t bead1, int32_t bead2, double r_max, double p);
 int or_bond_create_dir(or_sys* s, int32_t bt1, int32_t bt2, int32_t bead1, int32_t bead2, double r_max, double p);
 int or_bond_break(or_sys* s, int32_t bt, double r_min, double p);

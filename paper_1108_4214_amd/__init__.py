@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdynbond.so")
 
 DB_OK, DB_EINVAL, DB_ECAPACITY, DB_ENONFINITE, DB_EDEVICE, DB_ESTATE = 0, -1, -2, -3, -4, -5
 DB_FP64, DB_MIXED = 0, 1
+DB_ACCEPT_PAIR, DB_ACCEPT_AVERAGE = 0, 1
 DB_ANY = 0
 DB_ALL_BONDTYPES = 0xFFFFFFFF
 MAX_BONDS_PER_BEAD, MAX_ANGLES_PER_BEAD, MAX_DIHEDRALS_PER_BEAD = 4, 12, 16
@@ -34,7 +35,7 @@ EXPORTS = [
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
     "db_batch_create", "db_batch_get_state", "db_track_topology_energy", "db_external_force",
-    "db_energy_noalloc",
+    "db_energy_noalloc", "db_acceptance",
 ]
 
 STAT_FIELDS = [
@@ -102,6 +103,7 @@ _SIG = {
     "db_forces": [_P, _P, _int],
     "db_energy": [_P, _P],
     "db_energy_noalloc": [_P, _P],
+    "db_acceptance": [_P, _int],
     "db_get_state": [_P, _P, _P, _int],
     "db_topology_counts": [_P, _P, _P, _P],
     "db_get_bonds": [_P, _P, _P, _P],
@@ -262,6 +264,10 @@ def db_temperature_ramp(ctx, T0, T1, n_steps):
 
 def db_sweep_every(ctx, every, paircheck13=0, paircheck14=0):
     _check(ctx, _lib.db_sweep_every(ctx, int(every), int(paircheck13), int(paircheck14)))
+
+
+def db_acceptance(ctx, mode):
+    _check(ctx, _lib.db_acceptance(ctx, int(mode)))
 
 
 def db_bond_create(ctx, bt, bead1, bead2, r_max, p):
@@ -463,6 +469,7 @@ class System:
                 db_temperature_ramp(c, ff.T0, ff.T1, ff.ramp_steps)
         if rules is not None:
             db_sweep_every(c, rules.every, rules.paircheck13, rules.paircheck14)
+            db_acceptance(c, DB_ACCEPT_AVERAGE if rules.accept == "average" else DB_ACCEPT_PAIR)
             for r in rules.rules:
                 k = r[0]
                 if k == "create":

@@ -1011,6 +1011,14 @@ int db_sweep_every(db_ctx* c, int32_t every, int pc13, int pc14) {
     return DB_OK;
 }
 
+int db_acceptance(db_ctx* c, int mode) {
+    if (!c) return DB_EINVAL;
+    if (mode != DB_ACCEPT_PAIR && mode != DB_ACCEPT_AVERAGE) return fail(c, DB_EINVAL, "acceptance mode %d", mode);
+    c->hp.accept_average = mode == DB_ACCEPT_AVERAGE ? 1 : 0;
+    c->params_dirty = true;
+    return DB_OK;
+}
+
 int db_bond_create(db_ctx* c, int32_t bt, int32_t b1, int32_t b2, double rmax, double p) {
     if (!c || bad_bt(bt) || bad_bead(b1) || bad_bead(b2) || !(rmax > 0) || bad_p(p)) return DB_EINVAL;
     return add_rule(c, Rule{RK_CREATE, bt, bt, b1, b2, rmax * rmax, p});
@@ -1512,7 +1520,8 @@ static bool same_physics(const Params& a, const Params& b) {
         !eq(a.aT0, b.aT0, sizeof a.aT0) || !eq(a.dK, b.dK, sizeof a.dK) || !eq(a.dC0, b.dC0, sizeof a.dC0) ||
         !eq(a.dS0, b.dS0, sizeof a.dS0))
         return false;
-    if (a.gamma != b.gamma || a.dt != b.dt || a.every != b.every || a.pc13 != b.pc13 || a.pc14 != b.pc14)
+    if (a.gamma != b.gamma || a.dt != b.dt || a.every != b.every || a.pc13 != b.pc13 || a.pc14 != b.pc14 ||
+        a.accept_average != b.accept_average)
         return false;
     if (a.nrule != b.nrule || a.nmax != b.nmax || a.narule != b.narule || a.ndrule != b.ndrule) return false;
     for (int q = 0; q < a.nrule; ++q) {

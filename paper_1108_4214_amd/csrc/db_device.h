@@ -45,6 +45,26 @@ __device__ __forceinline__ double pair_uniform(const Box& X, int ga, int gb, int
     return (double)bits * (1.0 / 9007199254740992.0);
 }
 
+// uniform in [0,1) with 53 random bits drawn by one bead (global id g) alone: its
+// counter names the bead twice, which no pair draw does
+__device__ __forceinline__ double bead_uniform(const Box& X, int g, int64_t step, uint32_t kind) {
+    g -= X.gid_off;
+    uint4 w = rng_draw(X, (uint32_t)g, (uint32_t)g, step, kind);
+    uint64_t bits = ((((uint64_t)w.x) << 32) | (uint64_t)w.y) >> 11;
+    return (double)bits * (1.0 / 9007199254740992.0);
+}
+
+// The number a mutual pair compares with its rule's probability (appendix steps
+// 5 and 7): one uniform for the pair, or in the literal form of the appendix the
+// mean of one uniform per bead.  Both beads form the same value (the sum is taken
+// lower id first, though IEEE addition does not depend on the order).
+__device__ __forceinline__ double accept_number(const Params& P, const Box& X, int ga, int gb, int64_t step,
+                                                uint32_t kind) {
+    if (!P.accept_average) return pair_uniform(X, ga, gb, step, kind);
+    const int lo = ga < gb ? ga : gb, hi = ga < gb ? gb : ga;
+    return (bead_uniform(X, lo, step, kind) + bead_uniform(X, hi, step, kind)) * 0.5;
+}
+
 // Standard normal for the unordered pair {ga, gb} of global ids in box X at a
 // step (DPD random force): the Box-Muller transform (Box and Muller, 1958) of the
 // first two words, each taken to (0, 1) as (w + 1/2) / 2^32.  Both beads of the

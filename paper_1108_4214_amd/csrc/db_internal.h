@@ -88,6 +88,7 @@ struct Params {
     const double* fext;
     // rules, in call order
     int every, pc13, pc14;
+    int accept_average;         // acceptance compares the mean of two per-bead uniforms with p
     int nrule, nmax, narule, ndrule;
     Rule rule[DB_MAXRULES];
     MaxRule maxr[DB_MAXRULES];

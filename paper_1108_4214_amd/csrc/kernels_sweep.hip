@@ -413,7 +413,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_resolve(const Params* __restrict__
             const double4 xi = B.x[i];
             int gi = meta_gid(xi), gj = meta_gid(B.x[j]);
             const Rule& r = P.rule[S.ruleK[i]];
-            if (pair_uniform(box_of<BATCH>(P, meta_word(xi)), gi, gj, step, RNG_BREAK) < r.p) {
+            if (accept_number(P, box_of<BATCH>(P, meta_word(xi)), gi, gj, step, RNG_BREAK) < r.p) {
                 S.rmlist[rm * n + i] = j;
                 S.rmcnt[i] = (uint8_t)(rm + 1);
                 if (r.kind == RK_CONVERT) {
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_apply(const Params* __restrict__ P
         const double4 xi = B.x[i];
         int gi = meta_gid(xi), gj = meta_gid(B.x[j]);
         const Rule& r = P.rule[S.ruleC[i]];
-        if (pair_uniform(box_of<BATCH>(P, meta_word(xi)), gi, gj, step, RNG_CREATE) < r.p) {
+        if (accept_number(P, box_of<BATCH>(P, meta_word(xi)), gi, gj, step, RNG_CREATE) < r.p) {
             if (w >= DB_MAXB) {
                 atomicOr(err, ERR_BOND_CAP);
             } else {

@@ -87,6 +87,7 @@ class RuleSet:
     paircheck13: int = 0
     paircheck14: int = 0
     rules: List[tuple] = dataclasses.field(default_factory=list)
+    accept: str = "pair"     # "pair": one uniform per pair; "average": the mean of one uniform per bead
 
 
 @dataclasses.dataclass

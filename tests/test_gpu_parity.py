@@ -136,6 +136,20 @@ def test_sweep_isolated_pairs(p):
     assert _stats_equal(g, o)
 
 
+@pytest.mark.parametrize("p", [0.1, 0.6])
+def test_sweep_averaged_acceptance(p):
+    """The appendix's literal acceptance (mean of one uniform per bead) on creations
+    and breaks in one sweep: bit-exact against the oracle."""
+    s = synth.random_gas(2500, 14.0, seed=7, n_types=4)
+    s.bonds = np.array([(2 * k, 2 * k + 1, 1, 1) for k in range(300)], dtype=np.int32)
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, p), ("create", 1, 3, 4, 1.5, p),
+                                          ("break", 1, 1.2, p), ("maxbond", 1, 0, 1)], accept="average")
+    g, o = _sweep_both(s, synth.ForceField(), rules, seed=3, step=23)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+    assert g.stats()["bonds_created"] > 5 and g.stats()["bonds_broken"] > 0
+
+
 @pytest.mark.parametrize("L,n", [(3.0, 30), (4.2, 60)])
 def test_sweep_small_grid(L, n):
     """Boxes of one and two cells per edge, where the scan visits every cell once

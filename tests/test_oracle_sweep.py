@@ -38,6 +38,50 @@ def test_formation_frequency_matches_probability(p):
     assert o.stats()[0]["bonds_created"] == k
 
 
+def _average_law(p):
+    """P[(u1 + u2)/2 < p] for independent uniforms: the triangular distribution of their mean"""
+    return 2 * p * p if p <= 0.5 else 1 - 2 * (1 - p) ** 2
+
+
+@pytest.mark.parametrize("p", [0.1, 0.3, 0.5, 0.9])
+def test_averaged_acceptance_frequency_creation(p):
+    """The appendix's literal acceptance (each bead draws a uniform, the pair takes
+    their mean): the created fraction follows 2p^2 / 1 - 2(1-p)^2, not p."""
+    m = 4000
+    s = synth.isolated_pairs(m, 1.0, seed=int(p * 100) + 7)
+    rs = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, p), ("maxbond", 1, 0, 1)], accept="average")
+    o = oracle.Oracle.from_system(s, synth.ForceField(), rs, seed=2024)
+    o.sweep_now()
+    k = o.counts()[0]
+    q = _average_law(p)
+    assert abs(k - m * q) < 5 * math.sqrt(m * q * (1 - q))
+    if p != 0.5:   # distinguishable from the one-uniform-per-pair law
+        assert abs(k - m * p) > 5 * math.sqrt(m * p * (1 - p))
+
+
+@pytest.mark.parametrize("p", [0.2, 0.8])
+def test_averaged_acceptance_frequency_breakage(p):
+    m = 4000
+    s = synth.isolated_pairs(m, 1.3, seed=int(p * 100) + 9)
+    s.bonds = np.array([(2 * k, 2 * k + 1, 1, 1) for k in range(m)], dtype=np.int32)
+    for accept, q in [("average", _average_law(p)), ("pair", p)]:
+        rs = synth.RuleSet(every=1, rules=[("break", 1, 1.2, p)], accept=accept)
+        o = oracle.Oracle.from_system(s, synth.ForceField(), rs, seed=99)
+        o.sweep_now()
+        k = m - o.counts()[0]
+        assert o.stats()[0]["bonds_broken"] == k
+        assert abs(k - m * q) < 5 * math.sqrt(m * q * (1 - q))
+
+
+def test_averaged_acceptance_edge_probabilities():
+    s = synth.isolated_pairs(300, 1.0, seed=5)
+    for p, exp in [(1.0, 300), (0.0, 0)]:
+        rs = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, p)], accept="average")
+        o = oracle.Oracle.from_system(s, synth.ForceField(), rs, seed=1)
+        o.sweep_now()
+        assert o.counts()[0] == exp
+
+
 def test_unit_probability_creates_every_pair_and_zero_none():
     s = synth.isolated_pairs(200, 1.2, seed=3)
     for p, exp in [(1.0, 200), (0.0, 0)]:
