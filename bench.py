@@ -116,6 +116,8 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
         "rollbacks": st1["rollbacks"] - st0["rollbacks"],
         "bonds_created": st1["cum_bonds_created"] - st0["cum_bonds_created"],
         "bonds_killed": st1["cum_bonds_killed"] - st0["cum_bonds_killed"],
+        "bonds_broken": st1["cum_bonds_broken"] - st0["cum_bonds_broken"],
+        "bonds_converted": st1["cum_bonds_converted"] - st0["cum_bonds_converted"],
         "topology_per_bead": [nb / s.n, na / s.n, nd / s.n],
     }
     g.close()
@@ -164,7 +166,7 @@ def run_leg(w, description, steps, warmup):
     mixed = run_gpu(w, 1, steps, warmup)
     fp64 = run_gpu(w, 0, steps, warmup)
     b, a, d = mixed["topology_per_bead"]
-    kernel_bytes, _ = algorithmic_bytes_per_bead_step(b, a, d, w.rules.every)
+    kernel_bytes, step_bytes = algorithmic_bytes_per_bead_step(b, a, d, w.rules.every)
     n = w.system.n
 
     def frac(r):
@@ -173,9 +175,25 @@ def run_leg(w, description, steps, warmup):
     return {"workload": description, "value": mixed["bead_steps_per_s"], "unit": "bead-steps/s",
             "ms_per_step": mixed["ms_per_step"], "step_kernel_us": mixed["step_kernel_us"],
             "hbm_roofline_frac": frac(mixed), "bytes_per_bead_step": kernel_bytes,
+            "path_roofline_frac": step_bytes * mixed["bead_steps_per_s"] / (HBM_PEAK_GBS * 1e9),
             "fp64": {"value": fp64["bead_steps_per_s"], "ms_per_step": fp64["ms_per_step"],
-                     "step_kernel_us": fp64["step_kernel_us"], "hbm_roofline_frac": frac(fp64)},
+                     "step_kernel_us": fp64["step_kernel_us"], "hbm_roofline_frac": frac(fp64),
+                     "path_roofline_frac": step_bytes * fp64["bead_steps_per_s"] / (HBM_PEAK_GBS * 1e9)},
             "mixed_detail": mixed, "fp64_detail": fp64}
+
+
+def run_c5(steps, warmup):
+    """The stress workload: 4,000,000 beads at density 0.85, a sweep before every
+    step (creation at p = 0.9, conversion of stretched hybridization bonds to the
+    weak type, kills), NVE at dt = 0.002.  Every timed step does topology work.  The
+    run stays within 200 steps of the lattice start: with the angle and dihedral
+    patterns, strained rungs reach near-collinear dihedrals after about 550 steps."""
+    import synth
+
+    steps, warmup = min(steps, 150), min(warmup, 50)
+    return run_leg(synth.c5(), "100000 x 20-nt random strands, 2-bead model, 4000000 beads, rho=0.85, sweep every "
+                   "step (create p=0.9, convert hybridization->weak beyond 1.8, kill), NVE dt=0.002, "
+                   f"steps {warmup + 1}..{warmup + steps} from the lattice start", steps, warmup)
 
 
 def run_dpd(steps, warmup):
@@ -279,18 +297,52 @@ def run_accuracy(ramp_steps=100000, ramp_every=5000, nve_steps=10000, nve_every=
     return out
 
 
-def cpu_baseline(w, steps):
+def _oracle_shard(args):
+    """Worker of the CPU baseline: one single-threaded oracle advancing one shard box
+    of the workload; returns (beads, steps, start, end) on the monotonic clock."""
+    k, n_shards, steps, barrier = args
+    sys.path.insert(0, ROOT)
     import oracle
-
-    s = w.system
-    o = oracle.Oracle.from_system(s, w.ff, w.rules, seed=w.seed)
-    t0 = time.perf_counter()
+    import synth
+    w = synth.c3_shard(k, n_shards)
+    o = oracle.Oracle.from_system(w.system, w.ff, w.rules, seed=w.seed)
+    barrier.wait()
+    t0 = time.monotonic()
     o.step(steps)
-    t1 = time.perf_counter()
-    return {"value": s.n * steps / (t1 - t0), "unit": "bead-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"the oracle (single thread) advancing the same 1,000,000-bead workload {steps} steps "
-                      f"from its initial snapshot, {steps // max(1, w.rules.every)} sweeps included, "
-                      f"{t1 - t0:.1f} s"}
+    t1 = time.monotonic()
+    return w.system.n, steps, t0, t1
+
+
+def host_cores():
+    """cores this process may run on, capped at the GPU's share of its host (16)"""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(steps):
+    """The oracle on all host cores: one single-threaded oracle process per core,
+    each advancing its own shard box of the 1M-bead workload's recipe (same density,
+    duplexes, force field and rules); throughput = all bead-steps over the span from
+    the first start to the last end."""
+    import multiprocessing as mp
+
+    cores = host_cores()
+    ctx = mp.get_context("spawn")   # the parent holds the GPU: no fork
+    with ctx.Manager() as m:
+        barrier = m.Barrier(cores)
+        with ctx.Pool(cores) as pool:
+            res = pool.map(_oracle_shard, [(k, cores, steps, barrier) for k in range(cores)])
+    beads = sum(r[0] for r in res)
+    span = max(r[3] for r in res) - min(r[2] for r in res)
+    cpu_s = sum(r[3] - r[2] for r in res)
+    return {"value": beads * steps / span, "unit": "bead-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} single-threaded oracle processes, one per host core, each advancing its own "
+                      f"box of {beads // cores} beads (1/{cores} of the 1,000,000-bead recipe: pre-hybridized "
+                      f"40-bp duplexes at rho=0.5, same force field and rules) {steps} steps with "
+                      f"{steps // 10} sweeps; {beads} beads in all, {span:.1f} s wall, {cpu_s:.1f} s of CPU work"}
 
 
 def main():
@@ -298,16 +350,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skin", type=float, default=None)
     ap.add_argument("--permute-every", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the replica-ladder measurement")
     ap.add_argument("--no-dpd", action="store_true", help="skip the DPD-solution measurement")
     ap.add_argument("--no-dna1", action="store_true", help="skip the 1-bead DNA model measurement")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 4M-bead stress measurement")
     ap.add_argument("--accuracy", action="store_true",
                     help="also report mixed-vs-FP64 accuracy: force error, hybridized-fraction ramp, NVE drift")
-    ap.add_argument("--leg", choices=["dpd", "dna1", "batch"], default=None,
+    ap.add_argument("--leg", choices=["dpd", "dna1", "batch", "c5"], default=None,
                     help="run only this extra workload and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the traffic counters)")
@@ -324,6 +377,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.leg is not None:
         legs = {"dpd": lambda: run_dpd(args.steps, args.warmup), "dna1": lambda: run_dna1(args.steps, args.warmup),
+                "c5": lambda: run_c5(args.steps, args.warmup),
                 "batch": lambda: run_batch(max(100, args.steps // 4), min(args.warmup, 50))}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
@@ -382,8 +436,11 @@ def main():
     if not args.no_dna1:
         line["dna1"] = run_dna1(args.steps, args.warmup)
         log("bench: 1-bead model done")
+    if not args.no_c5:
+        line["c5"] = run_c5(args.steps, args.warmup)
+        log("bench: 4M-bead stress case done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
         log("bench: CPU oracle done")
     print(json.dumps(line), flush=True)
 

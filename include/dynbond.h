@@ -46,6 +46,7 @@ extern "C" {
 
 #define DB_ANY 0
 #define DB_ALL_BONDTYPES 0xFFFFFFFFu
+#define DB_MAX_BOX_EDGE 65536.0   /* largest box edge db_create accepts */
 
 #define DB_FP64 0           /* all force arithmetic in double */
 #define DB_MIXED 1          /* pair and bonded force arithmetic in float; positions,
@@ -80,7 +81,9 @@ typedef struct {
 /* ---- lifecycle ---------------------------------------------------------------- */
 
 /* Create a handle for n_beads beads (0 .. 2^26 - 1) in a periodic cube of edge
- * box_L.  seed keys every random number (Langevin noise and bond acceptance).
+ * box_L (0 < box_L <= DB_MAX_BOX_EDGE; every cutoff decision is exact in double
+ * at any such edge: the float prefilters of the cell scans widen their cutoffs
+ * by 4 sqrt(3) float ulps of 2 box_L, 0.0017 sigma at box_L = 1000).  seed keys every random number (Langevin noise and bond acceptance).
  * precision: DB_FP64 or DB_MIXED.  hip_stream: a hipStream_t (NULL = the null
  * stream).  Allocates no device memory yet. */
 int db_create(db_ctx** out, int32_t n_beads, double box_L, uint64_t seed, int precision, void* hip_stream);

@@ -524,7 +524,11 @@ typedef void (*pair_fn)(or_sys* s, int i, int j, const double d[3], double r2, v
 
 static void for_pairs(or_sys* s, double rcut, int brute, pair_fn fn, void* ctx) {
     double rc2 = rcut * rcut;
-    int nc = (int)floor(s->L / (rcut * (1.0 + 1e-9)));
+    /* cells no narrower than rcut, and no more of them than about two per bead
+     * (a large sparse box would otherwise ask for more cells than memory holds) */
+    double ncd = floor(s->L / (rcut * (1.0 + 1e-9)));
+    double ncap = floor(cbrt(2.0 * (double)s->n + 64.0));
+    int nc = (int)(ncd < ncap ? ncd : ncap);
     if (brute || nc < 3) {
         double d[3];
         for (int i = 0; i < s->n; ++i)

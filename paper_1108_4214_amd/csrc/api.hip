@@ -288,6 +288,16 @@ static void box_grid(Box& X, double amin, int ncap) {
     }
 }
 
+// 4 sqrt(3) float ulps of 2L: bounds the length error of a separation formed in
+// float from coordinates in [0, L) (each rounded once, one of them shifted by the
+// rounded edge), so that the float prefilters of the cell scans never drop a pair
+// the double test would keep
+static double prefilter_slack(double L) {
+    int e = 0;
+    std::frexp(2.0 * L, &e);                   // 2L = m 2^e, m in [1/2, 1)
+    return 4.0 * std::sqrt(3.0) * std::ldexp(1.0, e - 24);
+}
+
 static void compute_grid(db_ctx* c) {
     Params& P = c->hp;
     double rc = P.have_pair ? std::sqrt(P.rc2) : 0.0;
@@ -310,6 +320,9 @@ static void compute_grid(db_ctx* c) {
                 X.wide_create = X.L / X.nc < rcr ? 1 : 0;
             }
         }
+        X.pf_slack = prefilter_slack(X.L);
+        X.pf_create2 = (float)((rcr + X.pf_slack) * (rcr + X.pf_slack) * 1.0001);
+        X.pf_list2 = (float)((rnl + X.pf_slack) * (rnl + X.pf_slack) * 1.0001);
     };
     if (c->nrep == 0) {
         grid(P.box, ncell_cap(c));
@@ -632,7 +645,7 @@ extern "C" {
 int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, void* stream) {
     if (!out) return DB_EINVAL;
     *out = nullptr;
-    if (n < 0 || n > DB_MAX_BEADS || !(L > 0) || !std::isfinite(L)) return DB_EINVAL;
+    if (n < 0 || n > DB_MAX_BEADS || !(L > 0) || !(L <= DB_MAX_BOX_EDGE)) return DB_EINVAL;
     if (precision != DB_FP64 && precision != DB_MIXED) return DB_EINVAL;
     db_ctx* c = new db_ctx();
     c->hx = new db_host_ext();

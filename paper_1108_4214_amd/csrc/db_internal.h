@@ -61,6 +61,15 @@ struct Box {
     uint32_t seed_lo, seed_hi;
     double T0, T1;       // temperature T0 + (T1 - T0) min(step, ramp) / ramp
     int64_t ramp;
+    // Float prefilters of the cell scans.  A separation formed from float copies
+    // of coordinates below L, shifted by at most one float edge, is off by at most
+    // 2.5 float ulps of 2L per component; pf_slack = 4 sqrt(3) ulp_f(2L) bounds
+    // that in length, and the squared prefilter cutoffs carry it plus a relative
+    // 1e-4 for the float products: a pair within a cutoff in double always passes
+    // its prefilter.
+    double pf_slack;
+    float pf_create2;    // (creation distance + pf_slack)^2 (1 + 1e-4)
+    float pf_list2;      // (list cutoff + pf_slack)^2 (1 + 1e-4)
 };
 
 // Read-only parameters, resident in device memory.

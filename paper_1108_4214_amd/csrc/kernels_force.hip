@@ -28,7 +28,8 @@ struct Acc {
 // and an LDS lookup costs far less than a second dependent global load.
 template <typename R>
 struct Coef {
-    R bK[DB_MAXT], bR0[DB_MAXT], bRc2[DB_MAXT];   // bRc2: squared bond cutoff (+inf: none)
+    double bRc2[DB_MAXT];                         // squared bond cutoff (+inf: none), tested in double
+    R bK[DB_MAXT], bR0[DB_MAXT];
     R aK[DB_MAXT], aT0[DB_MAXT], aPm[DB_MAXT];   // aPm = pi - theta0
     R dK[DB_MAXT], dC0[DB_MAXT], dS0[DB_MAXT];
 };
@@ -40,7 +41,7 @@ __device__ __forceinline__ void load_coef(const Params& P, Coef<R>& C) {
     if (t < DB_MAXT) {
         C.bK[t] = (R)P.bK[t];
         C.bR0[t] = (R)P.bR0[t];
-        C.bRc2[t] = (R)P.bRc2[t];
+        C.bRc2[t] = P.bRc2[t];
         C.aK[t] = (R)P.aK[t];
         C.aT0[t] = (R)P.aT0[t];
         C.aPm[t] = (R)P.aPiMinusT0[t];
@@ -219,11 +220,12 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
 
 // Verlet list of bead i: every bead within the list cutoff (pair cutoff plus a
 // skin) that is not excluded, from the 27 cells of the current cell list.  The
-// float prefilter carries a 1e-4 relative margin, so the list is a superset of
-// the pairs within the cutoff in double.
+// float prefilter's cutoff is widened by the box's bound on float rounding
+// (Box::pf_slack), so the list is a superset of the pairs within the cutoff in
+// double.
 // The full build (list == nullptr: every bead, and with DPD its position is kept
 // in xref, from which the step kernels measure displacements) or the patch after a sweep (list: the beads whose
-// exclusions changed, count at list_n; cut2 then exceeds the list cutoff by the
+// exclusions changed, count at list_n; cut then exceeds the list cutoff by the
 // displacement margin and the wide stencil reaches it).
 template <bool BATCH, bool WIDE>
 __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restrict__ Pp, Bank B,
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
                                                           const float4* __restrict__ xs, NList NL,
                                                           int* __restrict__ err, double4* __restrict__ xref,
                                                           const int* __restrict__ list,
-                                                          const int* __restrict__ list_n, float cut2) {
+                                                          const int* __restrict__ list_n, double cut) {
     const Params& P = *Pp;
     const int n = P.n;
     int i;
@@ -305,8 +307,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         else if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
         ++cnt;
     };
-    if (WIDE) scan_cells_wide(X, cstart, xs, i, xi, cut2, visit);
-    else scan_cells(X, cstart, xs, i, xi, (float)(P.rnl2 * 1.0001), visit);
+    if (WIDE) scan_cells_wide(X, cstart, xs, i, xi, (float)((cut + X.pf_slack) * (cut + X.pf_slack) * 1.0001), visit);
+    else scan_cells(X, cstart, xs, i, xi, X.pf_list2, visit);
     if (!WIDE) {
         const int ns = min(cnt, NL_STAGE);
         for (int k = 0; k < ns; ++k) NL.nl[k * n + i] = stage[k][tid];
@@ -448,9 +450,11 @@ __device__ __forceinline__ void bond_terms(const Params& P, const Box& X, const 
         double dx = near_image(xj.x - xi.x, X);
         double dy = near_image(xj.y - xi.y, X);
         double dz = near_image(xj.z - xi.z, X);
+        // the cutoff decision in double, whatever the force type
+        const double rd2 = (dx * dx + dy * dy) + dz * dz;
+        if (!(rd2 > 0.0) || !(rd2 < C.bRc2[t])) continue;
         R rx = (R)dx, ry = (R)dy, rz = (R)dz;
         R rr2 = (rx * rx + ry * ry) + rz * rz;
-        if (!(rr2 > (R)0) || !(rr2 < C.bRc2[t])) continue;
         R ir = r_rsqrt<R>(rr2);
         R r = rr2 * ir;
         R K = C.bK[t], r0 = C.bR0[t];
@@ -714,7 +718,9 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
     const int nd = B.nd[i];
     const uint32_t acode0 = H.acode[i];
     const uint32_t dcode0 = H.dcode[i];
-    // separations x_k - x_i, G at a time
+    // separations x_k - x_i, G at a time; for the bond partners (the first nb
+    // entries) the cutoff decision is taken here, in double, whatever the force type
+    unsigned inb = 0;
 #pragma unroll
     for (int k0 = 0; k0 < DB_MAXU; k0 += G) {
         int s[G];
@@ -725,9 +731,17 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
         for (int q = 0; q < G; ++q) xk[q] = B.x[s[q]];
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            hx[k0 + q] = (R)near_image(xk[q].x - xi.x, X);
-            hy[k0 + q] = (R)near_image(xk[q].y - xi.y, X);
-            hz[k0 + q] = (R)near_image(xk[q].z - xi.z, X);
+            const double dx = near_image(xk[q].x - xi.x, X);
+            const double dy = near_image(xk[q].y - xi.y, X);
+            const double dz = near_image(xk[q].z - xi.z, X);
+            if (k0 + q < DB_MAXB) {
+                const double rd2 = (dx * dx + dy * dy) + dz * dz;
+                const int t = btk[k0 + q] & (DB_MAXT - 1);
+                inb |= (k0 + q < nb && rd2 > 0.0 && rd2 < C.bRc2[t]) ? 1u << (k0 + q) : 0u;
+            }
+            hx[k0 + q] = (R)dx;
+            hy[k0 + q] = (R)dy;
+            hz[k0 + q] = (R)dz;
             hs[0][k0 + q][tid] = hx[k0 + q];
             hs[1][k0 + q][tid] = hy[k0 + q];
             hs[2][k0 + q][tid] = hz[k0 + q];
@@ -736,11 +750,10 @@ __device__ __forceinline__ void halo_bonded(const Params& P, const Box& X, const
     // bonds: the first nb halo entries are the partners in table order
 #pragma unroll
     for (int k = 0; k < DB_MAXB; ++k) {
-        if (k >= nb) continue;
+        if (!((inb >> k) & 1u)) continue;
         const int t = btk[k] & (DB_MAXT - 1);
         const R rx = hx[k], ry = hy[k], rz = hz[k];
         R rr2 = (rx * rx + ry * ry) + rz * rz;
-        if (!(rr2 > (R)0) || !(rr2 < C.bRc2[t])) continue;
         R ir = r_rsqrt<R>(rr2);
         R r = rr2 * ir;
         R g = (R)2.0 * C.bK[t] * (r - C.bR0[t]) * ir;   // F_i = g * (x_j - x_i)
@@ -1023,11 +1036,11 @@ void launch_build_nlist(db_ctx* c) {
     if (c->nrep > 0)
         hipLaunchKernelGGL((k_build_nlist<true, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                            c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
-                           nullptr, 0.0f);
+                           nullptr, 0.0);
     else
         hipLaunchKernelGGL((k_build_nlist<false, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                            c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
-                           nullptr, 0.0f);
+                           nullptr, 0.0);
 }
 
 // beads whose exclusions the sweep changed: a changed bond table, or (exclusion
@@ -1061,13 +1074,12 @@ void launch_patch_nlist(db_ctx* c, double cut) {
     hipLaunchKernelGGL(k_patch_flags, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
     launch_scan_total(c->sw.act, c->sw.aoff, c->n, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_patch_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
-    const float cut2 = (float)(cut * cut * 1.0001);
     if (c->nrep > 0)
         hipLaunchKernelGGL((k_build_nlist<true, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
-                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut2);
+                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut);
     else
         hipLaunchKernelGGL((k_build_nlist<false, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
-                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut2);
+                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut);
 }
 
 // temperature of the single system's box at a step

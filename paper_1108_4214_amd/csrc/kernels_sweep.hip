@@ -181,7 +181,7 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
     double best_r2 = 0.0;
     const Tab Ti = load_tab_all(B, n, i);
     {
-        const float cut2 = (float)(P.rmax2_create * 1.0001);
+        const float cut2 = X.pf_create2;
         // types and reactivity ride in the scan's words: most candidates are
         // rejected before anything else of them is read
         const uint32_t partner_types = create_partner_types(P, ti);

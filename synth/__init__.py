@@ -540,6 +540,17 @@ def c3(seed_w=3, seed_d=13) -> Workload:
                     ff_t2(T0=0.5, T1=1.5, ramp_steps=100000), rules_t2(p=0.5, every=10), 100000, seed_d)
 
 
+def c3_shard(k, n_shards, seed_w=3, seed_d=13) -> Workload:
+    """One of n_shards independent boxes that together hold the 1,000,000-bead
+    workload's recipe: 6250 / n_shards pre-hybridized 40-bp duplexes at density 0.5,
+    the same force field, temperature ramp and rules, seeds offset by the shard."""
+    nd = max(1, int(round(6250 / n_shards)))
+    s = duplex_box(nd, 40, 0.5, seed_w + 1000 * (k + 1), seed_d + 1000 * (k + 1), T=0.5)
+    return Workload(f"c3 shard {k} of {n_shards}: {nd} duplexes, {s.n} beads, rho=0.5", s,
+                    ff_t2(T0=0.5, T1=1.5, ramp_steps=100000), rules_t2(p=0.5, every=10), 100000,
+                    seed_d + 1000 * (k + 1))
+
+
 def c5(seed_w=5, seed_d=15, n_strands=100000) -> Workload:
     """Random 20-nt single strands on a cubic lattice at density 0.85 (4,000,000
     beads at the default size), sweep every step, conversion to a weak type."""
@@ -667,6 +678,58 @@ def isolated_pairs(m, r, L_per_pair=4.0, seed=0, types=(A, T)) -> System:
         u = rng.normal(size=3)
         u /= np.linalg.norm(u)
         xs += [c, c + r * u]
+        ts += [types[0], types[1]]
+    x = wrap(np.array(xs), L)
+    n = len(ts)
+    return System(L=float(L), x=x, v=np.zeros((n, 3)), type=np.array(ts, dtype=np.int32),
+                  reactive=np.ones(n, dtype=np.uint8), bonds=np.zeros((0, 4), dtype=np.int32))
+
+
+def boundary_pairs(m, r_in, r_out, L, seed=0, types=(A, T)) -> System:
+    """m unbonded bead pairs (types[0], types[1]) straddling the faces, edges and one
+    corner of a large periodic box: the first bead within 0.3 of the upper face(s),
+    the partner across it.  Alternate pairs sit at separation r_in and r_out.  First
+    beads take distinct points of a lattice of spacing 8 on the faces (and along the
+    edges) whose other coordinates are also near L, where float copies of the
+    coordinates are coarsest; beads of different pairs stay more than 2.4 apart."""
+    rng = np.random.default_rng(seed)
+    g = int(math.sqrt(m)) + 2
+    grid = L - 4.0 - 8.0 * np.arange(g)
+    if grid[-1] < 4.0:
+        raise ValueError("box too small for that many pairs")
+    slots = []                                   # (straddled axes mask, point)
+    for k in range(3):                           # faces
+        o1, o2 = [a for a in range(3) if a != k]
+        for u in grid:
+            for v in grid:
+                pnt = np.zeros(3)
+                pnt[o1], pnt[o2] = u, v
+                slots.append((1 << k, pnt))
+    for k in range(3):                           # edges parallel to axis k
+        for u in grid:
+            pnt = np.zeros(3)
+            pnt[k] = u
+            slots.append((7 & ~(1 << k), pnt))
+    slots.append((7, np.zeros(3)))               # the corner
+    n_edge = 3 * len(grid) + 1
+    if m > len(slots):
+        raise ValueError("box too small for that many pairs")
+    # every edge and corner slot first (up to a third of the pairs), then faces at random
+    take_e = min(n_edge, m // 3)
+    pick = list(range(len(slots) - n_edge, len(slots)))[-take_e:] if take_e else []
+    pick += list(rng.choice(len(slots) - n_edge, size=m - take_e, replace=False))
+    xs, ts = [], []
+    for q, idx in enumerate(pick):
+        mask, a = slots[int(idx)]
+        a = a.copy()
+        d = rng.normal(size=3)
+        for k in range(3):
+            if (mask >> k) & 1:
+                a[k] = L - rng.uniform(0.0, 0.3)
+                d[k] = abs(d[k]) + 0.2           # crosses the face
+        d /= np.linalg.norm(d)
+        r = r_in if q % 2 == 0 else r_out
+        xs += [a, a + r * d]
         ts += [types[0], types[1]]
     x = wrap(np.array(xs), L)
     n = len(ts)

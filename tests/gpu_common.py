@@ -27,6 +27,31 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def per_bead_err(a, b):
+    """max over beads of |a_i - b_i| / max(|b_i|, F_rms): a wrong force on a few beads
+    shows here even where the global relative L2 norm averages it away"""
+    nb = np.linalg.norm(b, axis=1)
+    rms = float(np.sqrt(np.mean(nb * nb))) if nb.size else 0.0
+    den = np.maximum(nb, max(rms, 1e-300))
+    return float(np.max(np.linalg.norm(a - b, axis=1) / den)) if nb.size else 0.0
+
+
+def forces_close(a, b, tol, tol_bead=None):
+    """(ok, message): relative L2 norm of the difference <= tol and every bead's error
+    <= tol_bead relative to max(|F_i|, F_rms).
+
+    tol_bead defaults to 10 tol.  A bead's force is a sum of terms each correct to
+    about 1e-6 of itself in float arithmetic (the WCA force goes as r^-14, so the
+    6e-8 rounding of a separation is amplified about 14 times, plus some ten more
+    roundings) and to about 1e-15 in double; in the packed fixtures single terms
+    reach ten times F_rms on beads whose net force is far smaller, so the error of
+    one bead relative to F_rms can reach ten times the per-term figure.  A bead on a
+    wrong code path is off by order one."""
+    tb = 10.0 * tol if tol_bead is None else tol_bead
+    g, p = rel_l2(a, b), per_bead_err(a, b)
+    return (g <= tol and p <= tb), f"relative L2 {g:.3e} (tol {tol:.1e}), per bead {p:.3e} (tol {tb:.1e})"
+
+
 def as_set(rows):
     return {tuple(r) for r in np.asarray(rows).tolist()}
 

@@ -41,6 +41,8 @@ def test_host_side_validation_without_gpu():
         pk.db_create(-1, 10.0, 1)
     with pytest.raises(pk.DynBondError):
         pk.db_create(4, 10.0, 1, precision=7)
+    with pytest.raises(pk.DynBondError):
+        pk.db_create(4, 65536.5, 1)          # beyond the largest box edge
     c = pk.db_create(4, 10.0, 1)
     try:
         assert pk.db_workspace_bytes(c) > 0

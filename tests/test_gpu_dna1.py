@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_common import both, copy_oracle_from_gpu, perturbed, rel_l2, same_topology, topo_diff
+from gpu_common import both, copy_oracle_from_gpu, perturbed, rel_l2, forces_close, same_topology, topo_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +38,8 @@ def _wrapped_diff(a, b, L):
 def test_forces_match_oracle(precision, tol):
     s = perturbed(_solution(), 0.06, 1)
     g, o = both(s, synth.ff_dna1(), synth.rules_fig2(), precision=precision)
-    assert rel_l2(g.forces(), o.forces()) <= tol
+    ok, msg = forces_close(g.forces(), o.forces(), tol)
+    assert ok, msg
 
 
 @pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
@@ -52,7 +53,8 @@ def test_hybridization_cutoff(precision, tol):
     d = _wrapped_diff(s.x[hb[:, 0]], s.x[hb[:, 1]], s.L)
     r = np.sqrt((d * d).sum(axis=1))
     assert (r > 1.0).sum() > 10 and (r < 1.0).sum() > 10
-    assert rel_l2(g.forces(), o.forces()) <= tol
+    ok, msg = forces_close(g.forces(), o.forces(), tol)
+    assert ok, msg
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 1e-5)])
@@ -131,7 +133,8 @@ def test_full_size_forces(precision, tol, dna1_workload):
     import paper_1108_4214_amd as pk
     w, s, _, fo = dna1_workload
     g = pk.System(s.n, s.L, w.seed, precision).configure(s, w.ff, w.rules)
-    assert rel_l2(g.forces(), fo) <= tol
+    ok, msg = forces_close(g.forces(), fo, tol)
+    assert ok, msg
 
 
 def test_full_size_three_swept_steps(dna1_workload):

@@ -82,6 +82,22 @@ def test_averaged_acceptance_edge_probabilities():
         assert o.counts()[0] == exp
 
 
+def test_large_box_pairs_at_the_creation_distance():
+    """The strict FP64 cutoff decision in a box of edge 4000 (pairs straddling faces,
+    edges and a corner, 1e-7 inside or outside the creation distance): exactly the
+    inside pairs bond, as a brute-force distance check says."""
+    L, r = 4000.0, 1.5
+    s = synth.boundary_pairs(1000, r * (1 - 1e-7), r * (1 + 1e-7), L, seed=3)
+    rs = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, r, 1.0), ("maxbond", 1, 0, 1)])
+    o = oracle.Oracle.from_system(s, synth.ForceField(), rs, seed=1)
+    o.sweep_now()
+    d = s.x[1::2] - s.x[0::2]
+    d -= L * np.round(d / L)
+    inside = np.flatnonzero(np.sum(d * d, axis=1) < r * r)
+    assert len(inside) == 500
+    assert _bond_set(o) == {(2 * k, 2 * k + 1, 1, 1) for k in inside.tolist()}
+
+
 def test_unit_probability_creates_every_pair_and_zero_none():
     s = synth.isolated_pairs(200, 1.2, seed=3)
     for p, exp in [(1.0, 200), (0.0, 0)]:
