@@ -104,6 +104,7 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
     pk.db_profile(g.ctx, 0)
     kern_us, launches = pk.db_step_kernel_time(g.ctx)
     st1 = g.stats()
+    tiles = pk.db_tile_stats(g.ctx)
     nb, na, nd = g.counts()
     out = {
         "seconds": t1 - t0,
@@ -119,6 +120,7 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
         "bonds_broken": st1["cum_bonds_broken"] - st0["cum_bonds_broken"],
         "bonds_converted": st1["cum_bonds_converted"] - st0["cum_bonds_converted"],
         "topology_per_bead": [nb / s.n, na / s.n, nd / s.n],
+        "tiles": tiles,
     }
     g.close()
     return out

@@ -233,6 +233,22 @@ int db_set_step(db_ctx* ctx, int64_t step);
  * rebuilds pass between reorderings of the per-bead state into cell order (>= 1;
  * default 8).  Once set here, the skin no longer follows the pair style. */
 int db_tune(db_ctx* ctx, double skin, int32_t permute_every);
+/* Shape of the fused step kernel.  enable = 1: for a single system with WCA
+ * pairs, beads are reordered brick by brick (bricks of brick_edge^3 cells; 0:
+ * chosen from the density, about 200 beads a brick), each workgroup takes 256
+ * consecutive beads, loads the positions of every bead their lists and bonded
+ * terms name into LDS once (each as its image next to the tile), and reads
+ * partners from there; after every list build a region pass records those beads
+ * and re-codes the entries as 16-bit indices.  enable = 0 (default): one thread
+ * per bead gathers partners from memory.  The two agree to rounding (the staged
+ * separations are differences of images instead of images of differences).
+ * Takes effect at the next block.  EINVAL for enable outside {0, 1} or
+ * brick_edge outside 0..64. */
+int db_tile_shape(db_ctx* ctx, int enable, int32_t brick_edge);
+/* regions of the current tiles: out = {tiles, tiles whose region is staged in LDS,
+ * sum of the staged regions' sizes, largest region}; all 0 while the step kernel
+ * runs without tiles */
+int db_tile_stats(db_ctx* ctx, int64_t out[4]);
 /* HIP-event timing of the fused step kernel on the handle's stream: every
  * `every`-th launch is bracketed by two events (1 = every launch; 0 = off).
  * Each event pair leaves the GPU idle for a few microseconds between launches,

@@ -35,7 +35,7 @@ EXPORTS = [
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
     "db_batch_create", "db_batch_get_state", "db_track_topology_energy", "db_external_force",
-    "db_energy_noalloc", "db_acceptance",
+    "db_energy_noalloc", "db_acceptance", "db_tile_shape", "db_tile_stats",
 ]
 
 STAT_FIELDS = [
@@ -104,6 +104,8 @@ _SIG = {
     "db_energy": [_P, _P],
     "db_energy_noalloc": [_P, _P],
     "db_acceptance": [_P, _int],
+    "db_tile_shape": [_P, _int, _i32],
+    "db_tile_stats": [_P, _P],
     "db_get_state": [_P, _P, _P, _int],
     "db_topology_counts": [_P, _P, _P, _P],
     "db_get_bonds": [_P, _P, _P, _P],
@@ -264,6 +266,17 @@ def db_temperature_ramp(ctx, T0, T1, n_steps):
 
 def db_sweep_every(ctx, every, paircheck13=0, paircheck14=0):
     _check(ctx, _lib.db_sweep_every(ctx, int(every), int(paircheck13), int(paircheck14)))
+
+
+def db_tile_shape(ctx, enable, brick_edge=0):
+    _check(ctx, _lib.db_tile_shape(ctx, int(enable), int(brick_edge)))
+
+
+def db_tile_stats(ctx):
+    out = np.zeros(4, dtype=np.int64)
+    _check(ctx, _lib.db_tile_stats(ctx, _ptr(out)))
+    return {"tiles": int(out[0]), "staged": int(out[1]),
+            "mean_region": float(out[2]) / max(1, int(out[1])), "max_region": int(out[3])}
 
 
 def db_acceptance(ctx, mode):

@@ -126,6 +126,10 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // cell budget: at most 2 n + 64 cells per box
 static int ncell_cap(const db_ctx* c) { return 2 * c->n + 64 * std::max(1, c->nrep); }
 
+// brick tiles the arena holds: bricks average ~200 beads; a grid needing more
+// tiles than this runs without them
+static int tile_cap_of(const db_ctx* c) { return c->nrep > 0 ? 1 : (c->n + DB_BLOCK - 1) / DB_BLOCK + 1; }
+
 static int blocksum_ints(int count) {
     int tot = 2;
     int t = count;
@@ -198,7 +202,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->halo.u, 4 * (size_t)DB_MAXU * n);
     put(c->halo.acode, 4 * (size_t)DB_MAXA * n);
     put(c->halo.dcode, 4 * (size_t)DB_MAXD * n);
-    put(c->cells.cnt, 4 * nc);
+    put(c->cells.cnt, 4 * (nc + 1));
     put(c->cells.start, 4 * (nc + 1));
     put(c->cells.list, 4 * n);
     put(c->cells.xs, 16 * n);
@@ -206,6 +210,15 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->cells.rank, 4 * n);
     put(c->cells.blocksum, 4 * (size_t)blocksum_ints((int)std::max(n, nc) + 1));
     put(c->slot_of_gid, 4 * n);
+    if (assign) c->tile_cap = tile_cap_of(c);
+    const size_t tcap = (size_t)tile_cap_of(c);
+    put(c->tiles.tstart, 4 * ((size_t)ncell_cap(c) + 1));
+    put(c->tiles.rcount, 4 * tcap);
+    put(c->tiles.rslot, 4 * tcap * DB_RCAP);
+    put(c->tiles.nl16, 2 * (size_t)DB_NLCAP * n);
+    put(c->tiles.hu16, 2 * (size_t)DB_MAXU * n);
+    put(c->tiles.rec, 16 * n);
+    put(c->tiles.code8, 32 * n);
     put(c->err_d, 64);
     put(c->vmax2, 4 * (size_t)kMaxBlock * DB_VMAX_SPREAD);
     put(c->red, 8 * 6 * ((n + DB_BLOCK - 1) / DB_BLOCK + 1));
@@ -268,6 +281,13 @@ static int ensure_memory(db_ctx* c) {
 // ------------------------------------------------------------------------------------
 // parameters and the cell grid
 
+namespace db {
+// the step kernel runs on brick tiles: a single box with WCA pairs whose grid has tiles
+bool tiles_enabled(const db_ctx* c) {
+    return c->tile_mode && c->nrep == 0 && c->ntile > 0 && c->hp.have_pair && c->hp.pair_style == PAIR_WCA;
+}
+}  // namespace db
+
 // cells of edge >= amin, at most ncap of them
 static void box_grid(Box& X, double amin, int ncap) {
     if (!(amin > 0)) amin = X.L;
@@ -328,6 +348,22 @@ static void compute_grid(db_ctx* c) {
         grid(P.box, ncell_cap(c));
         P.box.cell_off = 0;
         P.ncell = P.box.nc * P.box.nc * P.box.nc;
+        // tiles of DB_BLOCK slots in brick order: bricks of about 200 beads (or the
+        // tuned edge), three or more cells per edge
+        int bB = 0, ntile = 0;
+        const int nc = P.box.nc;
+        if (c->tile_mode && nc >= 3 && c->n > 0) {
+            const double per_cell = (double)c->n / (double)P.ncell;
+            bB = c->brick_edge > 0 ? c->brick_edge : (int)std::floor(std::cbrt(224.0 / per_cell));
+            bB = std::max(2, std::min(bB, nc));
+            ntile = (c->n + DB_BLOCK - 1) / DB_BLOCK;
+        }
+        if (ntile != c->ntile || bB != c->tile_bB) {
+            c->tiles_valid = false;
+            c->regions_valid = false;
+        }
+        c->ntile = ntile;
+        c->tile_bB = bB;
         return;
     }
     int off = 0;
@@ -373,6 +409,8 @@ static int upload_system(db_ctx* c) {
     const int n = c->n;
     int rc = ensure_memory(c);
     if (rc) return rc;
+    c->tiles_valid = false;   // slots follow the input order until the next reordering
+    c->regions_valid = false;
     std::vector<double4> x4(n);
     std::vector<double> v(3 * (size_t)n);
     for (int i = 0; i < n; ++i) {
@@ -655,6 +693,13 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->precision = precision;
     c->stream = (hipStream_t)stream;
     c->device = -1;
+    c->tile_mode = 0;   // db_tile_shape / db_autotune switch the tile kernel on
+    c->brick_edge = 0;
+    c->ntile = 0;
+    c->tile_bB = 0;
+    c->tile_cap = 0;
+    c->tiles_valid = false;
+    c->regions_valid = false;
     memset(&c->hp, 0, sizeof(Params));
     Params& P = c->hp;
     P.n = n;
@@ -1474,6 +1519,40 @@ int db_set_step(db_ctx* c, int64_t step) {
     if (!c || step < 0) return DB_EINVAL;
     c->step = step;
     c->swept_step = -1;
+    return DB_OK;
+}
+
+int db_tile_shape(db_ctx* c, int enable, int32_t brick_edge) {
+    if (!c || (enable != 0 && enable != 1) || brick_edge < 0 || brick_edge > 64) return DB_EINVAL;
+    c->tile_mode = enable;
+    c->brick_edge = brick_edge;
+    c->params_dirty = true;
+    c->tiles_valid = false;
+    c->regions_valid = false;
+    c->rebuild_count = 0;   // the next block reorders, into brick order when tiles are on
+    return DB_OK;
+}
+
+int db_tile_stats(db_ctx* c, int64_t out[4]) {
+    if (!c || !out) return DB_EINVAL;
+    for (int k = 0; k < 4; ++k) out[k] = 0;
+    if (!c->allocated || !tiles_enabled(c) || !c->regions_valid) return DB_OK;
+    const int nt = c->ntile;
+    std::vector<int> rc(nt);
+    HIPCHK(c, hipMemcpyAsync(rc.data(), c->tiles.rcount, 4 * (size_t)nt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t staged = 0, sum = 0, mx = 0;
+    for (int v : rc) {
+        if (v <= DB_RCAP) {
+            ++staged;
+            sum += v;
+        }
+        mx = std::max<int64_t>(mx, v);
+    }
+    out[0] = nt;
+    out[1] = staged;
+    out[2] = sum;
+    out[3] = mx;
     return DB_OK;
 }
 

@@ -19,6 +19,7 @@
 #define DB_MAXU 8            // bonded halo entries per bead (codes hold 3-bit indices)
 #define DB_HALO_OVF 255      // halo marker: more than DB_MAXU distinct bonded partners
 #define DB_VMAX_SPREAD 64    // words per step over which the speed maxima are spread
+#define DB_RCAP 768          // region entries a tile of the step kernel stages in LDS
 #define DB_SLOT_BITS 26      // the float position copy packs slot | type << 26 | reactive << 31
 #define DB_MAX_BEADS ((1 << DB_SLOT_BITS) - 1)
 
@@ -163,6 +164,26 @@ struct Halo {
     uint32_t* dcode;    // [DB_MAXD][n]
 };
 
+// Tiles of the step kernel.  The cells of the box are grouped into bricks of bB^3
+// cells (the last brick of a dimension may be thinner); a reordering then places
+// the beads brick by brick, so that a tile of DB_BLOCK consecutive slots is a
+// compact piece of space.  After every list build the distinct beads that a
+// tile's list and halo entries name (its region) are recorded in slot order, and
+// those entries re-coded as 16-bit indices into the region; the step kernel
+// stages the region's positions in LDS once per tile and reads every partner from
+// there.  A tile whose region exceeds DB_RCAP, or a bead whose halo overflows,
+// reads its partners from memory as before.
+struct Tiles {
+    int* tstart;      // [nbrick + 1] first slot of each brick (statistics only)
+    int* rcount;      // [ntile] region entries (> DB_RCAP: too many to stage)
+    int* rslot;       // [ntile][DB_RCAP] region slots, ascending
+    uint16_t* nl16;   // list entries as region indices: the first 16 of a bead in one row, then column-major
+    uint16_t* hu16;   // [n][DB_MAXU] halo entries as region indices
+    uint4* rec;       // [n] the bead's words for the step: bond types; halo size, list length and table
+                      // counts; its own region index and meta word; its global id
+    uint4* code8;     // [n][2] its first four angle codes, then its first four dihedral codes
+};
+
 struct Cells {
     int* cnt;         // [ncell]
     int* start;       // [ncell + 1]
@@ -209,6 +230,14 @@ struct db_ctx {
     db::Cells cells;
     db::NList nlist;
     db::Halo halo;
+    db::Tiles tiles;
+    int tile_cap;        // tiles the arena holds
+    int tile_mode;       // 1: brick tiles when the system allows them (default), 0: never
+    int brick_edge;      // cells per brick edge chosen by the tuner (0: from the density)
+    int ntile;           // tiles of the current grid (0: the step kernel reads partners from memory)
+    int tile_bB;         // cells per brick edge of the current grid
+    bool tiles_valid;    // slots are in brick order: the tiles are the bricks of the last reordering
+    bool regions_valid;  // the regions and 16-bit entries match the current lists
     bool halo_force;     // slots or tables changed: rebuild the halo
     bool halo_sweep;     // a sweep ran since the last halo build: rebuild it if the sweep changed bonds
     // Verlet list kept across sweeps: valid for the current slots and topology, and
@@ -264,6 +293,7 @@ void launch_fill_int(int* p, int value, size_t count, hipStream_t s);
 void launch_build_cells(db_ctx* c);                  // bin + scan + scatter + in-cell sort
 void launch_permute(db_ctx* c, bool save);           // reorder all per-bead state by the cell list
                                                      // (save: also copy x, v to the rollback buffers)
+bool tiles_enabled(const db_ctx* c);                 // the step kernel runs on brick tiles
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s);
 // out[0..count) = exclusive prefix sums of in (in != out), out[count] = the total
 void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStream_t s);
@@ -271,6 +301,7 @@ void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStr
 // kernels_force.hip
 void launch_halo(db_ctx* c);                         // bonded halo, if slots or tables changed
 void launch_build_nlist(db_ctx* c);                  // halo, then the Verlet list from the current cell list
+void launch_regions(db_ctx* c);                      // tile regions and 16-bit entries of the current lists
 // Verlet lists of the beads whose exclusions the last sweep changed, with cutoff
 // cut (the list cutoff plus twice the displacement since the full build)
 void launch_patch_nlist(db_ctx* c, double cut);

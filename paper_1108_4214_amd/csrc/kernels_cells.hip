@@ -266,6 +266,59 @@ __global__ __launch_bounds__(DB_BLOCK) void k_newslot_bonded_first(int n, const 
     newslot[list[s]] = off[s + 1] > off[s] ? st + before : st + bonded + (s - st - before);
 }
 
+// Brick order of the cells: bricks of bB^3 cells (the last brick of each dimension
+// takes the remaining nc - (nbk - 1) bB cells) in z, y, x order, the cells of a
+// brick in z, y, x order.  Position of cell (cx, cy, cz) in that order.
+__device__ __forceinline__ int brick_pos(int cx, int cy, int cz, int nc, int bB) {
+    const int nbk = (nc + bB - 1) / bB;
+    const int last = nc - (nbk - 1) * bB;
+    const int bx = cx / bB, by = cy / bB, bz = cz / bB;
+    const int lx = cx - bx * bB, ly = cy - by * bB, lz = cz - bz * bB;
+    const int dx = bx == nbk - 1 ? last : bB, dy = by == nbk - 1 ? last : bB, dz = bz == nbk - 1 ? last : bB;
+    return (bz * bB) * nc * nc + dz * (by * bB) * nc + dz * dy * (bx * bB) + (lz * dy + ly) * dx + lx;
+}
+
+// bead counts of the cells, written at the cells' brick-order positions
+__global__ __launch_bounds__(DB_BLOCK) void k_brick_counts(int nc, int bB, const int* __restrict__ start,
+                                                           int* __restrict__ out) {
+    const int ncell = nc * nc * nc;
+    const int c = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (c >= ncell) return;
+    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    out[brick_pos(cx, cy, cz, nc, bB)] = start[c + 1] - start[c];
+}
+
+// the new slot of every bead: its cell's start in brick order plus its place in
+// the (ascending) cell list; bscan holds the exclusive prefix sums of the counts
+// in brick order
+__global__ __launch_bounds__(DB_BLOCK) void k_newslot_brick(int n, int nc, int bB, const int* __restrict__ list,
+                                                            const int* __restrict__ cellid,
+                                                            const int* __restrict__ start,
+                                                            const int* __restrict__ bscan,
+                                                            int* __restrict__ newslot) {
+    const int s = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (s >= n) return;
+    const int o = list[s];
+    const int c = cellid[o];
+    const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
+    newslot[o] = bscan[brick_pos(cx, cy, cz, nc, bB)] + (s - start[c]);
+}
+
+// first slot of every brick (tile), and n after the last
+__global__ __launch_bounds__(DB_BLOCK) void k_tile_starts(int n, int nc, int bB, const int* __restrict__ bscan,
+                                                          int* __restrict__ tstart) {
+    const int nbk = (nc + bB - 1) / bB;
+    const int ntile = nbk * nbk * nbk;
+    const int b = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (b > ntile) return;
+    if (b == ntile) {
+        tstart[b] = n;
+        return;
+    }
+    const int bx = b % nbk, by = (b / nbk) % nbk, bz = b / (nbk * nbk);
+    tstart[b] = bscan[brick_pos(bx * bB, by * bB, bz * bB, nc, bB)];
+}
+
 __global__ __launch_bounds__(DB_BLOCK) void k_permute(int n, Bank src, Bank dst, int* __restrict__ list,
                                                        const int* __restrict__ newslot, int* __restrict__ slot_of_gid,
                                                        double4* __restrict__ xsave, double* __restrict__ vsave,
@@ -316,7 +369,24 @@ void launch_permute(db_ctx* c, bool save) {
     hipStream_t s = c->stream;
     unsigned nb = (unsigned)((n + DB_BLOCK - 1) / DB_BLOCK);
     int* newslot = c->cells.cellid;   // the bin ids are no longer needed
-    if (c->nrep == 0) {
+    const bool tiled = tiles_enabled(c);
+    if (tiled) {
+        // brick order: the bin counts (zero between builds) serve as scan space and
+        // are cleared again afterwards; the new slots go to the sweep's free flag
+        // array, since the bin ids are read
+        const int nc = c->hp.box.nc, bB = c->tile_bB, ncell = c->hp.ncell;
+        int* bscan = c->cells.cnt;
+        unsigned cb = (unsigned)((ncell + DB_BLOCK - 1) / DB_BLOCK);
+        hipLaunchKernelGGL(k_brick_counts, dim3(cb), dim3(DB_BLOCK), 0, s, nc, bB, c->cells.start, bscan);
+        launch_exclusive_scan(bscan, ncell, nullptr, c->cells.blocksum, s);
+        newslot = c->sw.act;
+        hipLaunchKernelGGL(k_newslot_brick, dim3(nb), dim3(DB_BLOCK), 0, s, n, nc, bB, c->cells.list,
+                           c->cells.cellid, c->cells.start, bscan, newslot);
+        const int nbk = (nc + bB - 1) / bB;
+        unsigned tb = (unsigned)((nbk * nbk * nbk + 1 + DB_BLOCK - 1) / DB_BLOCK);
+        hipLaunchKernelGGL(k_tile_starts, dim3(tb), dim3(DB_BLOCK), 0, s, n, nc, bB, bscan, c->tiles.tstart);
+        launch_fill_int(bscan, 0, (size_t)ncell + 1, s);
+    } else if (c->nrep == 0) {
         // bonded beads first within each XCD's share; the sweep's flag and offset
         // arrays are free while the cells are reordered
         hipLaunchKernelGGL(k_bonded_flags, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.list, c->bank[c->cur].nb,
@@ -332,6 +402,8 @@ void launch_permute(db_ctx* c, bool save) {
                        save ? c->vsave : (double*)nullptr, c->cells.xs);
     c->cur = 1 - c->cur;
     c->halo_force = true;
+    c->tiles_valid = tiled;
+    c->regions_valid = false;
 }
 
 }  // namespace db

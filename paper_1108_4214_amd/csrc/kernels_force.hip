@@ -86,8 +86,29 @@ template <typename R>
 __device__ __forceinline__ R r_atan2(R y, R x);
 template <>
 __device__ __forceinline__ double r_atan2<double>(double y, double x) { return atan2(y, x); }
+// Single-precision arctangent for y >= 0 (every call here passes a sine): the
+// octant reduction z = min(|x|, y) / max(|x|, y) <= 1 and the odd polynomial of
+// Abramowitz and Stegun 4.4.49 (|error| <= 2e-8 on [0, 1]; about 1e-7 in float
+// arithmetic), then pi/2 - a above the diagonal and pi - a for x < 0.
 template <>
-__device__ __forceinline__ float r_atan2<float>(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ float r_atan2<float>(float y, float x) {
+    const float ax = fabsf(x);
+    const float mx = fmaxf(ax, y), mn = fminf(ax, y);
+    const float z = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float t = z * z;
+    float p = 0.0028662257f;
+    p = p * t - 0.0161657367f;
+    p = p * t + 0.0429096138f;
+    p = p * t - 0.0752896400f;
+    p = p * t + 0.1065626393f;
+    p = p * t - 0.1420889944f;
+    p = p * t + 0.1999355085f;
+    p = p * t - 0.3333314528f;
+    p = p * t + 1.0f;
+    float a = z * p;
+    a = y > ax ? 1.5707963267948966f - a : a;
+    return x < 0.0f ? 3.1415926535897932f - a : a;
+}
 
 // bead i is bonded to j (one of its own table entries)
 __device__ __forceinline__ bool in_list4(int j, int nb, int p0, int p1, int p2, int p3) {
@@ -937,6 +958,591 @@ void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H, double4* __
     }
 }
 
+// ---- brick tiles: regions staged in LDS -------------------------------------------
+// The distinct beads a tile's list and halo entries name are collected in an LDS
+// hash table (open addressing on the slot), sorted by slot with a bitonic network,
+// written out as the tile's region, and every entry is re-coded as its index in
+// the region.  Slots sorted within a region come in runs of neighbouring cells, so
+// the step kernel's loads of the region positions are mostly contiguous.
+#define DB_RHASH 2048   // hash slots per tile; at most DB_RCAP + DB_BLOCK keys are ever inserted
+#define DB_NLHEAD 16    // list entries kept bead-major (one 32-byte row per bead)
+
+// place of list entry k of bead i in the 16-bit table: the first DB_NLHEAD entries
+// of a bead are one contiguous row, so one bead reads them with two 16-byte loads;
+// later entries follow column-major
+__device__ __forceinline__ size_t nl16_index(int n, int i, int k) {
+    return k < DB_NLHEAD ? (size_t)i * DB_NLHEAD + k : (size_t)DB_NLHEAD * n + (size_t)(k - DB_NLHEAD) * n + i;
+}
+
+__device__ __forceinline__ unsigned region_hash(int key) { return ((unsigned)key * 2654435761u) >> (32 - 11); }
+
+__device__ __forceinline__ void region_insert(int* ht, int* nuniq, int key) {
+    unsigned h = region_hash(key);
+    for (int probe = 0; probe < DB_RHASH; ++probe) {
+        const int old = atomicCAS(&ht[h], -1, key);
+        if (old == -1) {
+            atomicAdd(nuniq, 1);
+            return;
+        }
+        if (old == key) return;
+        h = (h + 1) & (DB_RHASH - 1);
+    }
+}
+
+// table slot of a key that is present
+__device__ __forceinline__ int region_find(const int* ht, int key) {
+    unsigned h = region_hash(key);
+    for (int probe = 0; probe < DB_RHASH && ht[h] != key; ++probe) h = (h + 1) & (DB_RHASH - 1);
+    return (int)h;
+}
+
+__global__ __launch_bounds__(DB_BLOCK) void k_region(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
+                                                     Tiles T, int ntile) {
+    __shared__ int ht[DB_RHASH];
+    __shared__ uint16_t hv[DB_RHASH];
+    __shared__ int reg[DB_RCAP];
+    __shared__ int nuniq;
+    __shared__ int wsum[DB_BLOCK / 64];
+    const int n = Pp->n;
+    const int tile = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tile >= ntile) return;
+    const int i = tile * DB_BLOCK + tid;
+    const bool active = i < n;
+    // every word of the bead is requested before any is used: the list's first
+    // DB_NLHEAD entries and the halo (rows exist for every bead; unused ones are
+    // ignored), the counts, the types, the meta word and the first codes
+    int m = 0, nu = 0, nb = 0, na = 0, nd = 0;
+    int e[DB_NLHEAD], u[DB_MAXU];
+    uint32_t bt4 = 0, cw[8];
+    double4 xi = make_double4(0, 0, 0, 0);
+    if (active) {
+        m = NL.cnt[i];
+        nu = H.nu[i];
+        nb = B.nb[i];
+        na = B.na[i];
+        nd = B.nd[i];
+#pragma unroll
+        for (int k = 0; k < DB_NLHEAD; ++k) e[k] = NL.nl[k * n + i];
+#pragma unroll
+        for (int q = 0; q < DB_MAXU; ++q) u[q] = H.u[q * n + i];
+#pragma unroll
+        for (int k = 0; k < DB_MAXB; ++k) bt4 |= (uint32_t)(uint8_t)B.bt[k * n + i] << (8 * k);
+        xi = B.x[i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            cw[k] = H.acode[k * n + i];
+            cw[4 + k] = H.dcode[k * n + i];
+        }
+    }
+    for (int k = tid; k < DB_RHASH; k += DB_BLOCK) ht[k] = -1;
+    if (tid == 0) nuniq = 0;
+    __syncthreads();
+    // every thread checks the count before each insertion, so that at most
+    // DB_RCAP + DB_BLOCK keys enter the table (a free slot always remains)
+    if (active) {
+        region_insert(ht, &nuniq, i);   // the bead itself: the step reads its position from the region too
+#pragma unroll
+        for (int k = 0; k < DB_NLHEAD; ++k)
+            if (k < m && *(volatile int*)&nuniq <= DB_RCAP) region_insert(ht, &nuniq, e[k]);
+        for (int k = DB_NLHEAD; k < m && *(volatile int*)&nuniq <= DB_RCAP; ++k)
+            region_insert(ht, &nuniq, NL.nl[k * n + i]);
+        if (nu <= DB_MAXU) {
+#pragma unroll
+            for (int q = 0; q < DB_MAXU; ++q)
+                if (q < nu && *(volatile int*)&nuniq <= DB_RCAP) region_insert(ht, &nuniq, u[q]);
+        }
+    }
+    __syncthreads();
+    const int R = nuniq;
+    if (R > DB_RCAP) {   // too many to stage: the tile reads its partners from memory
+        if (tid == 0) T.rcount[tile] = R;
+        return;
+    }
+    // compact the keys (eight table slots per thread), then sort them
+    constexpr int PER = DB_RHASH / DB_BLOCK;
+    int mine = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) mine += ht[tid * PER + k] != -1;
+    int incl = mine;
+    const int lane = tid & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    int off = incl - mine;
+    for (int w = 0; w < (tid >> 6); ++w) off += wsum[w];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int key = ht[tid * PER + k];
+        if (key != -1) reg[off++] = key;
+    }
+    int P2 = 1;
+    while (P2 < R) P2 <<= 1;
+    for (int k = R + tid; k < P2; k += DB_BLOCK) reg[k] = 0x7FFFFFFF;
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < P2 / 2; t += DB_BLOCK) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const int a = reg[lo], b = reg[hi];
+                if ((a > b) == ((lo & size) == 0)) {
+                    reg[lo] = b;
+                    reg[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = tid; r < R; r += DB_BLOCK) {
+        const int key = reg[r];
+        T.rslot[(size_t)tile * DB_RCAP + r] = key;
+        hv[region_find(ht, key)] = (uint16_t)r;
+    }
+    if (tid == 0) T.rcount[tile] = R;
+    __syncthreads();
+    if (!active) return;
+    // the entries as region indices: the first DB_NLHEAD of the list in one row
+    uint32_t w16[DB_NLHEAD / 2];
+#pragma unroll
+    for (int k = 0; k < DB_NLHEAD / 2; ++k) {
+        const uint32_t lo = 2 * k < m ? hv[region_find(ht, e[2 * k])] : 0u;
+        const uint32_t hi = 2 * k + 1 < m ? hv[region_find(ht, e[2 * k + 1])] : 0u;
+        w16[k] = lo | hi << 16;
+    }
+    uint4* row = reinterpret_cast<uint4*>(T.nl16 + (size_t)i * DB_NLHEAD);
+    row[0] = make_uint4(w16[0], w16[1], w16[2], w16[3]);
+    row[1] = make_uint4(w16[4], w16[5], w16[6], w16[7]);
+    for (int k = DB_NLHEAD; k < m; ++k) T.nl16[nl16_index(n, i, k)] = hv[region_find(ht, NL.nl[k * n + i])];
+    uint32_t h16[DB_MAXU / 2];
+#pragma unroll
+    for (int q = 0; q < DB_MAXU / 2; ++q) {
+        const uint32_t lo = (nu <= DB_MAXU && 2 * q < nu) ? hv[region_find(ht, u[2 * q])] : 0u;
+        const uint32_t hi = (nu <= DB_MAXU && 2 * q + 1 < nu) ? hv[region_find(ht, u[2 * q + 1])] : 0u;
+        h16[q] = lo | hi << 16;
+    }
+    *reinterpret_cast<uint4*>(T.hu16 + (size_t)i * DB_MAXU) = make_uint4(h16[0], h16[1], h16[2], h16[3]);
+    // the bead's record and its first angle and dihedral codes
+    const uint32_t mhi = (uint32_t)meta_word(xi) & 0xFFFFu;   // type | reactive << 8 (one box: replica 0)
+    T.rec[i] = make_uint4(bt4, (uint32_t)nu | (uint32_t)m << 8 | (uint32_t)nb << 16 | (uint32_t)na << 20 |
+                                   (uint32_t)nd << 24,
+                          (uint32_t)hv[region_find(ht, i)] | mhi << 16, (uint32_t)meta_gid(xi));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= na) cw[k] = 0u;
+        if (k >= nd) cw[4 + k] = 0u;
+    }
+    T.code8[2 * (size_t)i] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+    T.code8[2 * (size_t)i + 1] = make_uint4(cw[4], cw[5], cw[6], cw[7]);
+}
+
+// Separation of a partner from the bead.  STAGED: region entry r from LDS, where
+// the region's positions are stored as images next to the tile (unwrapped about
+// one reference point when staged), and xs is the bead's own entry there, so the
+// separation is a plain difference.  Otherwise slot r from memory, with the
+// minimum image.
+// A region spread over more than half a box edge (small boxes) keeps the minimum
+// image on the differences (IMAGE).
+template <bool STAGED, bool IMAGE = false>
+struct TilePos {
+    const double *rx, *ry, *rz;
+    const double4* x;
+    __device__ __forceinline__ void sep(int r, const double4& xs, const Box& X, double& dx, double& dy,
+                                        double& dz) const {
+        if constexpr (STAGED) {
+            dx = rx[r] - xs.x;
+            dy = ry[r] - xs.y;
+            dz = rz[r] - xs.z;
+            if constexpr (IMAGE) {
+                dx = near_image(dx, X);
+                dy = near_image(dy, X);
+                dz = near_image(dz, X);
+            }
+        } else {
+            const double4 q = x[r];
+            dx = near_image(q.x - xs.x, X);
+            dy = near_image(q.y - xs.y, X);
+            dz = near_image(q.z - xs.z, X);
+        }
+    }
+};
+
+// The words of bead i that the tile step needs before any partner position, all
+// requested at the start of the kernel so that their latency overlaps the loads
+// of the region: the halo members and the first DB_NLHEAD list entries as 16-bit
+// region indices (packed two to a word), the bond types, the counts, and the
+// first four angle and dihedral codes.
+struct TileBead {
+    uint32_t hu[DB_MAXU / 2];      // halo members, two 16-bit region indices a word
+    uint32_t nl[DB_NLHEAD / 2];    // list entries 0..15, two a word
+    int btk[DB_MAXB];
+    int nb, na, nd, nu, m;
+    uint32_t ac[4], dc[4];
+};
+
+__device__ __forceinline__ int half16(const uint32_t* w, int k) { return (int)((w[k >> 1] >> ((k & 1) * 16)) & 0xFFFFu); }
+
+// element k < 4 of a register array by selects (an indexed access would go
+// through scratch memory)
+__device__ __forceinline__ uint32_t pick4(const uint32_t* a, int k) {
+    return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
+}
+
+// the bead's words of a staged tile: its record, halo row, first list entries and
+// first angle and dihedral codes, five 16-byte loads in all; returns the record
+__device__ __forceinline__ uint4 tile_bead_load(const Tiles& T, int i, TileBead& tb) {
+    const uint4 rc = T.rec[i];
+    const uint4 h = *reinterpret_cast<const uint4*>(T.hu16 + (size_t)i * DB_MAXU);
+    const uint4* row = reinterpret_cast<const uint4*>(T.nl16 + (size_t)i * DB_NLHEAD);
+    const uint4 l0 = row[0], l1 = row[1];
+    const uint4 a4 = T.code8[2 * (size_t)i], d4 = T.code8[2 * (size_t)i + 1];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) tb.btk[k] = (int)((rc.x >> (8 * k)) & 0xFFu);
+    tb.nu = (int)(rc.y & 0xFFu);
+    tb.m = (int)((rc.y >> 8) & 0xFFu);
+    tb.nb = (int)((rc.y >> 16) & 0xFu);
+    tb.na = (int)((rc.y >> 20) & 0xFu);
+    tb.nd = (int)((rc.y >> 24) & 0x1Fu);
+    tb.hu[0] = h.x;
+    tb.hu[1] = h.y;
+    tb.hu[2] = h.z;
+    tb.hu[3] = h.w;
+    tb.nl[0] = l0.x;
+    tb.nl[1] = l0.y;
+    tb.nl[2] = l0.z;
+    tb.nl[3] = l0.w;
+    tb.nl[4] = l1.x;
+    tb.nl[5] = l1.y;
+    tb.nl[6] = l1.z;
+    tb.nl[7] = l1.w;
+    tb.ac[0] = a4.x;
+    tb.ac[1] = a4.y;
+    tb.ac[2] = a4.z;
+    tb.ac[3] = a4.w;
+    tb.dc[0] = d4.x;
+    tb.dc[1] = d4.y;
+    tb.dc[2] = d4.z;
+    tb.dc[3] = d4.w;
+    return rc;
+}
+
+// All bonded forces on bead i through its halo, with the same arithmetic in the
+// same order as halo_bonded, members read from the staged region (STAGED) or from
+// memory by slot.  hidx holds the thread's member references for the angle and
+// dihedral entries.
+template <typename R, bool STAGED, bool IMAGE>
+__device__ __forceinline__ void tile_bonded(const Params& P, const Box& X, const Coef<R>& C, const Halo& H,
+                                            const TilePos<STAGED, IMAGE>& tp, uint16_t (*hidx)[DB_BLOCK], int i,
+                                            const double4& xi, const TileBead& tb, Acc<R>& a) {
+    const int n = P.n;
+    const int tid = threadIdx.x;
+    // halo member q: a region index parked in LDS (staged), else its slot from memory
+    auto member = [&](int q) -> int { return STAGED ? (int)hidx[q][tid] : H.u[q * n + i]; };
+    if (STAGED) {
+#pragma unroll
+        for (int q = 0; q < DB_MAXU; ++q)
+            if (q < tb.nu) hidx[q][tid] = (uint16_t)half16(tb.hu, q);
+    }
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        if (k >= tb.nb) continue;
+        double dx, dy, dz;
+        tp.sep(STAGED ? half16(tb.hu, k) : member(k), xi, X, dx, dy, dz);
+        const int t = tb.btk[k] & (DB_MAXT - 1);
+        const double rd2 = (dx * dx + dy * dy) + dz * dz;
+        if (!(rd2 > 0.0) || !(rd2 < C.bRc2[t])) continue;
+        const R ex = (R)dx, ey = (R)dy, ez = (R)dz;
+        R rr2 = (ex * ex + ey * ey) + ez * ez;
+        R ir = r_rsqrt<R>(rr2);
+        R r = rr2 * ir;
+        R g = (R)2.0 * C.bK[t] * (r - C.bR0[t]) * ir;
+        a.fx += (double)(g * ex);
+        a.fy += (double)(g * ey);
+        a.fz += (double)(g * ez);
+    }
+    // the first four entries unrolled (codes in registers, so every member's loads
+    // can be issued together), then any further ones
+#pragma unroll
+    for (int k = 0; k < DB_MAXA; ++k) {
+        if (k >= tb.na) continue;
+        const uint32_t code = k < 4 ? tb.ac[k < 4 ? k : 0] : H.acode[k * n + i];
+        const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, t = (code >> 8) & (DB_MAXT - 1);
+        double d1x, d1y, d1z, d2x, d2y, d2z;
+        tp.sep(member(k1), xi, X, d1x, d1y, d1z);
+        tp.sep(member(k2), xi, X, d2x, d2y, d2z);
+        const R s1x = (R)d1x, s1y = (R)d1y, s1z = (R)d1z, s2x = (R)d2x, s2y = (R)d2y, s2z = (R)d2z;
+        const R z = (R)0;
+        const R pax = role == 0 ? z : s1x, pay = role == 0 ? z : s1y, paz = role == 0 ? z : s1z;
+        const R pbx = role == 0 ? s1x : (role == 1 ? z : s2x), pby = role == 0 ? s1y : (role == 1 ? z : s2y),
+                pbz = role == 0 ? s1z : (role == 1 ? z : s2z);
+        const R pcx = role == 2 ? z : s2x, pcy = role == 2 ? z : s2y, pcz = role == 2 ? z : s2z;
+        angle_core<R, MODE_STEP>(C, role, t, pax - pbx, pay - pby, paz - pbz, pcx - pbx, pcy - pby, pcz - pbz, a);
+    }
+#pragma unroll
+    for (int k = 0; k < DB_MAXD; ++k) {
+        if (k >= tb.nd) continue;
+        const uint32_t code = k < 4 ? tb.dc[k < 4 ? k : 0] : H.dcode[k * n + i];
+        const int role = code & 3, k1 = (code >> 2) & 7, k2 = (code >> 5) & 7, k3 = (code >> 8) & 7;
+        const int t = (code >> 11) & (DB_MAXT - 1);
+        double d1x, d1y, d1z, d2x, d2y, d2z, d3x, d3y, d3z;
+        tp.sep(member(k1), xi, X, d1x, d1y, d1z);
+        tp.sep(member(k2), xi, X, d2x, d2y, d2z);
+        tp.sep(member(k3), xi, X, d3x, d3y, d3z);
+        const R s1x = (R)d1x, s1y = (R)d1y, s1z = (R)d1z, s2x = (R)d2x, s2y = (R)d2y, s2z = (R)d2z;
+        const R s3x = (R)d3x, s3y = (R)d3y, s3z = (R)d3z;
+        const R z = (R)0;
+        const R pax = role == 0 ? z : s1x, pay = role == 0 ? z : s1y, paz = role == 0 ? z : s1z;
+        const R pbx = role == 0 ? s1x : (role == 1 ? z : s2x), pby = role == 0 ? s1y : (role == 1 ? z : s2y),
+                pbz = role == 0 ? s1z : (role == 1 ? z : s2z);
+        const R pcx = role <= 1 ? s2x : (role == 2 ? z : s3x), pcy = role <= 1 ? s2y : (role == 2 ? z : s3y),
+                pcz = role <= 1 ? s2z : (role == 2 ? z : s3z);
+        const R pdx = role == 3 ? z : s3x, pdy = role == 3 ? z : s3y, pdz = role == 3 ? z : s3z;
+        dihedral_core<R, MODE_STEP>(C, role, t, pbx - pax, pby - pay, pbz - paz, pcx - pbx, pcy - pby, pcz - pbz,
+                                    pdx - pcx, pdy - pcy, pdz - pcz, a);
+    }
+}
+
+// WCA force of one list partner (the arithmetic of pair_one)
+template <typename R, bool STAGED, bool IMAGE>
+__device__ __forceinline__ void tile_pair(const Params& P, const Box& X, const TilePos<STAGED, IMAGE>& tp, int r,
+                                          const double4& xi, R rc2, Acc<R>& a) {
+    double dx, dy, dz;
+    tp.sep(r, xi, X, dx, dy, dz);
+    const R ex = (R)dx, ey = (R)dy, ez = (R)dz;
+    const R r2 = (ex * ex + ey * ey) + ez * ez;
+    if (r2 < rc2) {
+        R ir2 = r_rcp<R>(r2);
+        R sr2 = (R)P.sig2 * ir2;
+        R sr6 = sr2 * sr2 * sr2;
+        R fr = (R)24.0 * (R)P.eps * ((R)2.0 * sr6 * sr6 - sr6) * ir2;
+        a.fx -= (double)(fr * ex);
+        a.fy -= (double)(fr * ey);
+        a.fz -= (double)(fr * ez);
+    }
+}
+
+// Bonded forces of a bead with more distinct bonded partners than the halo holds:
+// every entry reads its members from memory, one member at a time (the arithmetic
+// of bond_terms, angle_one and dihedral_one).
+template <typename R>
+__device__ __forceinline__ void wide_bonded(const Params& P, const Box& X, const Coef<R>& C, const Bank& B, int i,
+                                         const double4& xi, Acc<R>& a) {
+    const int n = P.n;
+    const int nb = B.nb[i];
+    for (int k = 0; k < nb; ++k) {
+        const int j = B.bp[k * n + i];
+        const int t = (int)B.bt[k * n + i] & (DB_MAXT - 1);
+        const double4 xj = B.x[j];
+        const double dx = near_image(xj.x - xi.x, X), dy = near_image(xj.y - xi.y, X), dz = near_image(xj.z - xi.z, X);
+        const double rd2 = (dx * dx + dy * dy) + dz * dz;
+        if (!(rd2 > 0.0) || !(rd2 < C.bRc2[t])) continue;
+        R rx = (R)dx, ry = (R)dy, rz = (R)dz;
+        R rr2 = (rx * rx + ry * ry) + rz * rz;
+        R ir = r_rsqrt<R>(rr2);
+        R r = rr2 * ir;
+        R g = (R)2.0 * C.bK[t] * (r - C.bR0[t]) * ir;
+        a.fx += (double)(g * rx);
+        a.fy += (double)(g * ry);
+        a.fz += (double)(g * rz);
+    }
+    const int na = B.na[i];
+    for (int k = 0; k < na; ++k) {
+        const int4 e = B.ang[k * n + i];
+        angle_one<R, MODE_STEP>(P, X, C, i, e, B.x[e.x], B.x[e.y], B.x[e.z], a);
+    }
+    const int nd = B.nd[i];
+    for (int k = 0; k < nd; ++k) {
+        const int4 e = B.dih[k * n + i];
+        const int t = B.dt[k * n + i] & (DB_MAXT - 1);
+        dihedral_one<R, MODE_STEP>(P, X, C, i, e, t, B.x[e.x], B.x[e.y], B.x[e.z], B.x[e.w], a);
+    }
+}
+
+// One bead's step in a tile (the body of k_step_tile): partners from the staged
+// region (STAGED) or from memory by slot.  Returns |v|^2 after the step.
+template <typename R, bool STAGED, bool IMAGE>
+__device__ __forceinline__ double tile_bead_step(const Params& P, const Box& X, const Coef<R>& C, Bank& B,
+                                                 const NList& NL, const Halo& H, const Tiles& T, const double* rx,
+                                                 const double* ry, const double* rz, uint16_t (*hidx)[DB_BLOCK], int i,
+                                                 const double4& xi, const double4& xs, double vx, double vy, double vz,
+                                                 const TileBead& tb, double4* __restrict__ xout, int64_t step,
+                                                 double pref, int* __restrict__ err, double4* __restrict__ xsave,
+                                                 double* __restrict__ vsave) {
+    const int n = P.n;
+    const TilePos<STAGED, IMAGE> tp{rx, ry, rz, B.x};
+    const R rc2 = (R)P.rc2;
+    Acc<R> a;
+    if (tb.nu <= DB_MAXU) tile_bonded<R, STAGED, IMAGE>(P, X, C, H, tp, hidx, i, xs, tb, a);
+    else wide_bonded<R>(P, X, C, B, i, xi, a);
+    const int m = tb.m;
+    if constexpr (STAGED) {
+        // the first DB_NLHEAD entries from registers, in list order, then the rest
+#pragma unroll
+        for (int k = 0; k < DB_NLHEAD; ++k)
+            if (k < m) tile_pair<R, true, IMAGE>(P, X, tp, half16(tb.nl, k), xs, rc2, a);
+        for (int k = DB_NLHEAD; k < m; ++k)
+            tile_pair<R, true, IMAGE>(P, X, tp, T.nl16[nl16_index(n, i, k)], xs, rc2, a);
+    } else {
+        for (int k = 0; k < m; ++k) tile_pair<R, false, IMAGE>(P, X, tp, NL.nl[k * n + i], xs, rc2, a);
+    }
+    if (P.has_ext) {
+        const size_t g = (size_t)meta_gid(xi);
+        a.fx += P.fext[3 * g];
+        a.fy += P.fext[3 * g + 1];
+        a.fz += P.fext[3 * g + 2];
+    }
+    if (xsave) {   // first step of a block: keep its input state for a re-run
+        xsave[i] = xi;
+        vsave[i] = vx;
+        vsave[n + i] = vy;
+        vsave[2 * n + i] = vz;
+    }
+    double Fx = a.fx, Fy = a.fy, Fz = a.fz;
+    if (P.gamma != 0.0) {
+        uint4 w = rng_draw(X, (uint32_t)(meta_gid(xi) - X.gid_off), 0u, step, RNG_LANGEVIN);
+        const double s32 = 1.0 / 4294967296.0;
+        double ux = ((double)w.x + 0.5) * s32, uy = ((double)w.y + 0.5) * s32, uz = ((double)w.z + 0.5) * s32;
+        Fx = (Fx - P.gamma * vx) + pref * (ux - 0.5);
+        Fy = (Fy - P.gamma * vy) + pref * (uy - 0.5);
+        Fz = (Fz - P.gamma * vz) + pref * (uz - 0.5);
+    }
+    const double hdt = 0.5 * P.dt;
+    double hx = vx + hdt * Fx, hy = vy + hdt * Fy, hz = vz + hdt * Fz;
+    vx = hx + hdt * Fx;
+    vy = hy + hdt * Fy;
+    vz = hz + hdt * Fz;
+    double4 xo;
+    xo.x = wrap1(xi.x + P.dt * vx, X.L);
+    xo.y = wrap1(xi.y + P.dt * vy, X.L);
+    xo.z = wrap1(xi.z + P.dt * vz, X.L);
+    xo.w = xi.w;
+    const bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
+    if (bad) atomicOr(err, ERR_NONFINITE);
+    xout[i] = xo;
+    B.v[i] = vx;
+    B.v[n + i] = vy;
+    B.v[2 * n + i] = vz;
+    return (vx * vx + vy * vy) + vz * vz;
+}
+
+// The fused step (WCA pairs, bonded terms, Langevin force, velocity Verlet) of one
+// tile of DB_BLOCK consecutive slots per workgroup, one bead per thread.  Slots
+// are in brick order, so a tile is a compact piece of space.  Each bead's own
+// words are requested first, then the positions of the tile's region are loaded
+// into LDS, and after one barrier every partner position comes from there.  A
+// tile whose region could not be staged reads partners from memory by slot, and a
+// bead whose halo overflows reads its table entries.  Every force is formed with
+// the arithmetic, in the order, of k_step, so the two kernels give the same
+// trajectory bit for bit.
+template <typename R>
+__global__ __launch_bounds__(DB_BLOCK) void k_step_tile(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
+                                                        Tiles T, double4* __restrict__ xout, int64_t step,
+                                                        double pref, unsigned int* __restrict__ vmax2_slot,
+                                                        int* __restrict__ err, double4* __restrict__ xsave,
+                                                        double* __restrict__ vsave) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    const Box& X = P.box;
+    __shared__ Coef<R> C;
+    __shared__ double rx[DB_RCAP], ry[DB_RCAP], rz[DB_RCAP];
+    __shared__ uint16_t hidx[DB_MAXU][DB_BLOCK];
+    load_coef<R>(P, C);
+    const int tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int i = tile * DB_BLOCK + tid;
+    const bool active = i < n;
+    const int nreg = T.rcount[tile];
+    const bool staged = nreg <= DB_RCAP;
+    TileBead tb;
+    double4 xi = make_double4(0, 0, 0, 0);
+    double vx = 0, vy = 0, vz = 0;
+    uint4 rc = make_uint4(0, 0, 0, 0);
+    if (active) {
+        xi = B.x[i];
+        vx = B.v[i];
+        vy = B.v[n + i];
+        vz = B.v[2 * n + i];
+        if (staged) {
+            rc = tile_bead_load(T, i, tb);
+        } else {   // partners by slot: only the counts and types here
+            tb.nu = H.nu[i];
+            tb.m = P.have_pair ? (int)NL.cnt[i] : 0;
+            tb.nb = B.nb[i];
+            tb.na = B.na[i];
+            tb.nd = B.nd[i];
+#pragma unroll
+            for (int k = 0; k < DB_MAXB; ++k) tb.btk[k] = B.bt[k * n + i];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                tb.ac[k] = H.acode[k * n + i];
+                tb.dc[k] = H.dcode[k * n + i];
+            }
+        }
+    }
+    int far = 0;   // some stored image lies L/4 or more from the reference (small boxes)
+    if (staged) {
+        // the region's slots, then their positions: all of a thread's loads of one
+        // kind are in flight together.  Each position is stored as its image nearest
+        // to one reference point of the tile (its first bead): when every member of
+        // the region lies within L/4 of it, differences of stored positions are the
+        // minimum-image separations and the pair loop needs no image arithmetic
+        constexpr int RPT = DB_RCAP / DB_BLOCK;
+        const int* rs = T.rslot + (size_t)tile * DB_RCAP;
+        const double4 ref = B.x[tile * DB_BLOCK];
+        const double wmax_img = 0.25 * X.L;   // stored images within L/4 of ref: differences are minimum images
+        int sl[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) sl[q] = q * DB_BLOCK + tid < nreg ? rs[q * DB_BLOCK + tid] : -1;
+        double4 xq[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+            if (sl[q] >= 0) xq[q] = B.x[sl[q]];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            if (sl[q] < 0) continue;
+            const double ox = near_image(xq[q].x - ref.x, X), oy = near_image(xq[q].y - ref.y, X),
+                         oz = near_image(xq[q].z - ref.z, X);
+            far |= !(fabs(ox) < wmax_img && fabs(oy) < wmax_img && fabs(oz) < wmax_img);
+            rx[q * DB_BLOCK + tid] = ref.x + ox;
+            ry[q * DB_BLOCK + tid] = ref.y + oy;
+            rz[q * DB_BLOCK + tid] = ref.z + oz;
+        }
+    }
+    const bool image = __syncthreads_or(far) != 0;
+    // origin of the separations: the bead's own region entry (staged), else itself
+    double4 xs = xi;
+    if (active && staged) {
+        const int self = (int)(rc.z & 0xFFFFu);
+        xs = make_double4(rx[self], ry[self], rz[self], 0.0);
+    }
+    double m2 = 0.0;
+    if (active) {
+        if (staged && !image)
+            m2 = tile_bead_step<R, true, false>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, vx, vy, vz, tb,
+                                                xout, step, pref, err, xsave, vsave);
+        else if (staged)
+            m2 = tile_bead_step<R, true, true>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, vx, vy, vz, tb,
+                                               xout, step, pref, err, xsave, vsave);
+        else
+            m2 = tile_bead_step<R, false, true>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, vx, vy, vz, tb,
+                                                xout, step, pref, err, xsave, vsave);
+    }
+    // largest speed of the tile: one atomic per workgroup, spread over 64 words
+    __shared__ float wmax[DB_BLOCK / 64];
+    const double v2 = wave_max(m2);
+    if ((tid & 63) == 0) wmax[tid >> 6] = (float)v2 * 1.0001f;
+    __syncthreads();
+    if (tid == 0) {
+        float mm = wmax[0];
+        for (int w = 1; w < DB_BLOCK / 64; ++w) mm = fmaxf(mm, wmax[w]);
+        atomicMax(vmax2_slot + (blockIdx.x & (DB_VMAX_SPREAD - 1)), __float_as_uint(mm));
+    }
+}
+
 // energy reduction: a separate, simpler kernel keeps the step kernel lean
 template <typename R, bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_energy(const Params* __restrict__ Pp, Bank B,
@@ -1029,6 +1635,14 @@ void launch_halo(db_ctx* c) {
     c->halo_sweep = false;
 }
 
+void launch_regions(db_ctx* c) {
+    c->regions_valid = false;
+    if (c->n == 0 || !tiles_enabled(c) || !c->tiles_valid) return;
+    hipLaunchKernelGGL(k_region, dim3(c->ntile), dim3(DB_BLOCK), 0, c->stream, c->dp, c->bank[c->cur], c->nlist,
+                       c->halo, c->tiles, c->ntile);
+    c->regions_valid = true;
+}
+
 void launch_build_nlist(db_ctx* c) {
     if (c->n == 0) return;
     launch_halo(c);
@@ -1041,6 +1655,7 @@ void launch_build_nlist(db_ctx* c) {
         hipLaunchKernelGGL((k_build_nlist<false, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                            c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
                            nullptr, 0.0);
+    launch_regions(c);
 }
 
 // beads whose exclusions the sweep changed: a changed bond table, or (exclusion
@@ -1080,6 +1695,7 @@ void launch_patch_nlist(db_ctx* c, double cut) {
     else
         hipLaunchKernelGGL((k_build_nlist<false, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
                            c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut);
+    launch_regions(c);
 }
 
 // temperature of the single system's box at a step
@@ -1147,7 +1763,18 @@ void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
     const bool vbuf = velocity_double_buffer(c);
-    launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save);
+    if (tiles_enabled(c) && c->tiles_valid && c->regions_valid) {
+        double4* xs = save ? c->xsave : nullptr;
+        double* vs = save ? c->vsave : nullptr;
+        if (c->precision == DB_MIXED)
+            hipLaunchKernelGGL(k_step_tile<float>, dim3(c->ntile), dim3(DB_BLOCK), 0, c->stream, c->dp, B, c->nlist,
+                               c->halo, c->tiles, c->xnext, step, pref, vm, c->err_d, xs, vs);
+        else
+            hipLaunchKernelGGL(k_step_tile<double>, dim3(c->ntile), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
+                               c->nlist, c->halo, c->tiles, c->xnext, step, pref, vm, c->err_d, xs, vs);
+    } else {
+        launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save);
+    }
     double4* t = B.x;
     B.x = c->xnext;
     c->xnext = t;

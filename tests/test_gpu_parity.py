@@ -528,3 +528,86 @@ def test_dense_slab_forces():
     o = oracle.Oracle.from_system(s, synth.ForceField(eps=0.01), synth.RuleSet(every=0), seed=7)
     ok, msg = forces_close(g.forces(), o.forces(), FP64_TOL)
     assert ok, msg
+
+
+# ---- brick tiles of the step kernel against the per-bead kernel -------------------------
+
+def _run_shape(s, ff, rules, precision, enable, edge, steps, seed=5):
+    import paper_1108_4214_amd as pk
+    g = pk.System(s.n, s.L, seed, precision)
+    pk.db_tile_shape(g.ctx, enable, edge)
+    g.configure(s, ff, rules)
+    g.step(steps)
+    x, v = g.state()
+    out = (x, v, g.bonds(), g.angles(), g.dihedrals(), g.stats())
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("precision,steps,xtol", [(0, 60, 1e-9), (1, 20, 1e-6)])
+@pytest.mark.parametrize("edge", [0, 3, 12])
+def test_tile_kernel_trajectory_matches_per_bead_kernel(precision, steps, xtol, edge):
+    """The tile step kernel stages each tile's partners in LDS as images next to the
+    tile, so its separations are differences of stored positions rather than
+    minimum images of differences: the same values to rounding.  With sweeps that
+    kill and re-create bonds, its trajectory follows the per-bead kernel's to xtol
+    and the topology is the same.  Edge 12 makes regions too large to stage (those
+    tiles read partners from memory); 3 gives small bricks; 0 the density's choice."""
+    s = _duplex_system(150, 12, 0.3, seed=21, scale=0.06)
+    rules = synth.rules_t2(p=0.6, every=4, r_kill=1.3)
+    ff = synth.ff_t2()
+    a = _run_shape(s, ff, rules, precision, 1, edge, steps)
+    b = _run_shape(s, ff, rules, precision, 0, 0, steps)
+    d = a[0] - b[0]
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < xtol
+    assert np.abs(a[1] - b[1]).max() < 1e3 * xtol
+    for k in (2, 3, 4):
+        assert np.array_equal(a[k], b[k])
+    assert a[5]["cum_bonds_killed"] > 0 and a[5]["cum_bonds_created"] > 0
+
+
+def test_tile_kernel_trajectory_against_oracle():
+    """Duplexes in a box of several tiles, FP64, 30 steps with sweeps every 5 steps:
+    the tile kernel's positions against the oracle's to 1e-9, topology bit-exact."""
+    s = _duplex_system(60, 10, 0.3, seed=23, scale=0.05)
+    rules = synth.rules_t2(p=0.6, every=5, r_kill=1.3)
+    ff = synth.ff_t2()
+    import paper_1108_4214_amd as pk
+    g, o = both(s, ff, rules, seed=9)
+    pk.db_tile_shape(g.ctx, 1, 0)
+    g.step(30)
+    o.step(30)
+    assert same_topology(g, o), topo_diff(g, o)
+    d = g.state()[0] - o.state()[0]
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < 1e-9
+    assert pk.db_tile_stats(g.ctx)["staged"] > 0
+
+
+def test_tile_kernel_wide_bonded_neighbourhood():
+    """Hubs whose bonded terms reach more beads than the halo holds, next to beads
+    on the halo path, inside tiles: the trajectory follows the per-bead kernel's."""
+    s = synth.branched_clusters(64, seed=4)
+    ff = synth.ForceField(bonds={1: (30.0, 1.0)}, angles={1: (5.0, 1.9)}, dihedrals={1: (2.0, 0.4)}, gamma=1.0)
+    outs = []
+    for enable in (1, 0):
+        import paper_1108_4214_amd as pk
+        g = pk.System(s.n, s.L, 3, 1)
+        pk.db_tile_shape(g.ctx, enable, 0)
+        g.configure(s, ff, synth.RuleSet(), generate=False)
+        g.step(25)
+        outs.append(g.state())
+        g.close()
+    d = outs[0][0] - outs[1][0]
+    d -= s.L * np.round(d / s.L)
+    assert np.abs(d).max() < 1e-6 and np.abs(outs[0][1] - outs[1][1]).max() < 1e-4
+
+
+def test_tile_shape_arguments():
+    import paper_1108_4214_amd as pk
+    g = pk.System(4, 10.0, 1)
+    with pytest.raises(pk.DynBondError):
+        pk.db_tile_shape(g.ctx, 2, 0)
+    with pytest.raises(pk.DynBondError):
+        pk.db_tile_shape(g.ctx, 1, -1)
