@@ -128,14 +128,27 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
 
 def run_batch(steps, warmup, precision=1):
     """The replica ladder: 64 uneven replicas advanced together (one launch per
-    kernel for all of them) against the same replicas stepped one after another."""
+    kernel for all of them) against the same replicas stepped one after another;
+    the batch with its blocks' step launches replayed from HIP graphs; and the batch
+    after the autotuner (skin, reorder cadence, kernel shape, graphs)."""
     import torch
 
     import paper_1108_4214_amd as pk
     import synth
 
     ws = synth.c4()
-    reps = [pk.System(w.system.n, w.system.L, w.seed, precision).configure(w.system, w.ff, w.rules) for w in ws]
+
+    def replicas():
+        return [pk.System(w.system.n, w.system.L, w.seed, precision).configure(w.system, w.ff, w.rules) for w in ws]
+
+    def timed(g, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    reps = replicas()
     ntot = sum(g.n for g in reps)
     b = pk.Batch(reps)
     for g in reps:
@@ -147,20 +160,58 @@ def run_batch(steps, warmup, precision=1):
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t0
     b.step(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    bat_s = time.perf_counter() - t0
+    bat_s = timed(b, steps)
+    b.close()
+    out = {}
+    for label, graph in (("graph", 1),):
+        bg = pk.Batch(reps)
+        pk.db_graph(bg.ctx, graph)
+        bg.step(warmup)
+        t = timed(bg, steps)
+        out[label] = {"value": ntot * steps / t, "ms_per_step": 1e3 * t / steps}
+        bg.close()
+    bt = pk.Batch(reps)
+    skin, perm = pk.db_autotune(bt.ctx, 10)
+    shape = pk.db_get_shape(bt.ctx)
+    t = timed(bt, steps)
+    out["tuned"] = {"value": ntot * steps / t, "ms_per_step": 1e3 * t / steps, "skin": skin,
+                    "permute_every": perm, **shape}
+    bt.close()
     for g in reps:
         g.close()
-    b.close()
     return {"workload": f"{len(ws)} replicas of 2k-50k beads (log-uniform), {ntot} beads, duplexes at rho=0.5, "
                         "T_r = 0.6 + 0.8 r/63, sweep every 10 steps",
             "beads": ntot, "replicas": len(ws), "steps": steps,
             "value": ntot * steps / bat_s, "unit": "bead-steps/s", "ms_per_step": 1e3 * bat_s / steps,
             "sequential_value": ntot * steps / seq_s, "sequential_ms_per_step": 1e3 * seq_s / steps,
-            "speedup": seq_s / bat_s}
+            "speedup": seq_s / bat_s, **out}
+
+
+def run_small(steps, warmup):
+    """Launch-bound sizes: the 40-bead pair of 10-nt strands and the 80,000-bead box,
+    mixed precision, launches one by one against blocks replayed from HIP graphs."""
+    import torch
+
+    import paper_1108_4214_amd as pk
+    import synth
+
+    res = {}
+    for name, w in (("40 beads", synth.c1()), ("80000 beads", synth.c2())):
+        r = {}
+        for graph in (0, 1):
+            g = pk.System(w.system.n, w.system.L, w.seed, 1)
+            pk.db_graph(g.ctx, graph)
+            g.configure(w.system, w.ff, w.rules)
+            g.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            r["graph" if graph else "launches"] = {"value": w.system.n * steps / t, "ms_per_step": 1e3 * t / steps}
+            g.close()
+        res[name] = r
+    return res
 
 
 def run_leg(w, description, steps, warmup):
@@ -362,7 +413,7 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the 4M-bead stress measurement")
     ap.add_argument("--accuracy", action="store_true",
                     help="also report mixed-vs-FP64 accuracy: force error, hybridized-fraction ramp, NVE drift")
-    ap.add_argument("--leg", choices=["dpd", "dna1", "batch", "c5"], default=None,
+    ap.add_argument("--leg", choices=["dpd", "dna1", "batch", "c5", "small"], default=None,
                     help="run only this extra workload and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the traffic counters)")
@@ -380,6 +431,7 @@ def main():
     if args.leg is not None:
         legs = {"dpd": lambda: run_dpd(args.steps, args.warmup), "dna1": lambda: run_dna1(args.steps, args.warmup),
                 "c5": lambda: run_c5(args.steps, args.warmup),
+                "small": lambda: run_small(max(200, args.steps), min(args.warmup, 50)),
                 "batch": lambda: run_batch(max(100, args.steps // 4), min(args.warmup, 50))}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
         return
@@ -438,6 +490,9 @@ def main():
     if not args.no_dna1:
         line["dna1"] = run_dna1(args.steps, args.warmup)
         log("bench: 1-bead model done")
+    if not args.no_batch:
+        line["small"] = run_small(max(200, args.steps), min(args.warmup, 50))
+        log("bench: launch-bound sizes done")
     if not args.no_c5:
         line["c5"] = run_c5(args.steps, args.warmup)
         log("bench: 4M-bead stress case done")

@@ -233,6 +233,12 @@ int db_set_step(db_ctx* ctx, int64_t step);
  * rebuilds pass between reorderings of the per-bead state into cell order (>= 1;
  * default 8).  Once set here, the skin no longer follows the pair style. */
 int db_tune(db_ctx* ctx, double skin, int32_t permute_every);
+/* enable = 1: the step launches of each block (the steps between two cell-list
+ * rebuilds) are captured once per block length as a HIP graph and replayed, the
+ * block's first step written to the device before each replay; 0 (default):
+ * launched one by one.  The kernels and their results are the same.  Not used
+ * while db_profile times launches.  EINVAL for another value. */
+int db_graph(db_ctx* ctx, int enable);
 /* Shape of the fused step kernel.  enable = 1: for a single system with WCA
  * pairs, beads are reordered brick by brick (bricks of brick_edge^3 cells; 0:
  * chosen from the density, about 200 beads a brick), each workgroup takes 256
@@ -263,11 +269,16 @@ int db_step_kernel_time(db_ctx* ctx, double* mean_us, int64_t* launches);
  * passes per sweep) */
 int db_track_topology_energy(db_ctx* ctx, int enable);
 /* tries skin in {0.4, 0.5, 0.6, 0.8} (DPD: {0.02, 0.05, 0.1, 0.3}) x
- * permute_every in {1, 2, 4, 8}, running
- * steps_per_trial steps of the trajectory with each (the system advances by
- * 16 x steps_per_trial steps), and keeps the fastest; best_skin / best_permute
- * (either may be NULL) receive the choice */
+ * permute_every in {1, 2, 4, 8}, then the step kernel's shape (db_tile_shape: per
+ * bead, or tiles over bricks of 0 = density's choice, 3, 4, 5 cells; single
+ * systems with WCA pairs), then graphs off and on (db_graph), running one untimed
+ * and steps_per_trial timed steps of the trajectory with each (the system advances
+ * (steps_per_trial + 1) x (16 + shapes + 2) steps, shapes = 4 or 1), and keeps the
+ * fastest of each; best_skin / best_permute (either may be NULL) receive the
+ * choice, db_get_shape the rest */
 int db_autotune(db_ctx* ctx, int64_t steps_per_trial, double* best_skin, int32_t* best_permute);
+/* out = {tile kernel on, brick edge (0: density's choice), graphs on} */
+int db_get_shape(db_ctx* ctx, int32_t out[3]);
 
 /* ---- batches of independent replicas ------------------------------------------ */
 /* Not in the paper: many small boxes (replicas of a parameter ladder) are

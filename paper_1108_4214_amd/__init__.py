@@ -35,7 +35,7 @@ EXPORTS = [
     "db_get_state", "db_topology_counts", "db_get_bonds", "db_get_angles", "db_get_dihedrals",
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
     "db_batch_create", "db_batch_get_state", "db_track_topology_energy", "db_external_force",
-    "db_energy_noalloc", "db_acceptance", "db_tile_shape", "db_tile_stats",
+    "db_energy_noalloc", "db_acceptance", "db_tile_shape", "db_tile_stats", "db_graph", "db_get_shape",
 ]
 
 STAT_FIELDS = [
@@ -106,6 +106,8 @@ _SIG = {
     "db_acceptance": [_P, _int],
     "db_tile_shape": [_P, _int, _i32],
     "db_tile_stats": [_P, _P],
+    "db_graph": [_P, _int],
+    "db_get_shape": [_P, _P],
     "db_get_state": [_P, _P, _P, _int],
     "db_topology_counts": [_P, _P, _P, _P],
     "db_get_bonds": [_P, _P, _P, _P],
@@ -270,6 +272,16 @@ def db_sweep_every(ctx, every, paircheck13=0, paircheck14=0):
 
 def db_tile_shape(ctx, enable, brick_edge=0):
     _check(ctx, _lib.db_tile_shape(ctx, int(enable), int(brick_edge)))
+
+
+def db_get_shape(ctx):
+    out = np.zeros(3, dtype=np.int32)
+    _check(ctx, _lib.db_get_shape(ctx, _ptr(out)))
+    return {"tiles": int(out[0]), "brick_edge": int(out[1]), "graph": int(out[2])}
+
+
+def db_graph(ctx, enable):
+    _check(ctx, _lib.db_graph(ctx, int(enable)))
 
 
 def db_tile_stats(ctx):

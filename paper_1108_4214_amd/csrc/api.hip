@@ -220,6 +220,7 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->tiles.rec, 16 * n);
     put(c->tiles.code8, 32 * n);
     put(c->err_d, 64);
+    put(c->step_dev, 64);
     put(c->vmax2, 4 * (size_t)kMaxBlock * DB_VMAX_SPREAD);
     put(c->red, 8 * 6 * ((n + DB_BLOCK - 1) / DB_BLOCK + 1));
     put(c->ledger_d, 8 * 16);
@@ -693,6 +694,11 @@ int db_create(db_ctx** out, int32_t n, double L, uint64_t seed, int precision, v
     c->precision = precision;
     c->stream = (hipStream_t)stream;
     c->device = -1;
+    c->step_dev = nullptr;
+    c->step_base_d = nullptr;
+    c->use_graph = false;
+    c->graphs = new std::vector<GraphEntry>();
+    c->cap_stream = nullptr;
     c->tile_mode = 0;   // db_tile_shape / db_autotune switch the tile kernel on
     c->brick_edge = 0;
     c->ntile = 0;
@@ -760,6 +766,12 @@ int db_destroy(db_ctx* c) {
     if (c->allocated) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->ev_report) (void)hipEventDestroy(c->ev_report);
+    for (GraphEntry& e : *c->graphs) {
+        (void)hipGraphExecDestroy(e.exec);
+        (void)hipGraphDestroy(e.graph);
+    }
+    delete c->graphs;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->arena_owned && c->arena) (void)hipFree(c->arena);
     if (X.pin) (void)hipHostFree(X.pin);
     delete c->hx;
@@ -1199,6 +1211,79 @@ static int harvest_events(db_ctx* c) {
     return DB_OK;
 }
 
+__global__ void k_set_step(int64_t* __restrict__ p, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// The len step launches of a block from a captured graph: captured once per
+// (length, rollback copy, buffers, kernel) and replayed with the block's first step
+// written to the device beforehand.  Only kernel nodes are captured.
+static int run_steps_graph(db_ctx* c, int64_t k0, int len, bool save) {
+    Bank& B = c->bank[c->cur];
+    const bool tiled = tiles_enabled(c) && c->tiles_valid && c->regions_valid;
+    GraphEntry* hit = nullptr;
+    for (GraphEntry& e : *c->graphs)
+        if (e.len == len && e.save == save && e.tiled == tiled && e.cur == c->cur && e.x == B.x &&
+            e.xnext == c->xnext && e.v == B.v && e.vnext == c->vnext) {
+            hit = &e;
+            break;
+        }
+    if (!hit) {
+        if (c->graphs->size() >= 64) {   // a bounded cache: start afresh
+            for (GraphEntry& e : *c->graphs) {
+                (void)hipGraphExecDestroy(e.exec);
+                (void)hipGraphDestroy(e.graph);
+            }
+            c->graphs->clear();
+        }
+        GraphEntry e{};
+        e.len = len;
+        e.save = save;
+        e.tiled = tiled;
+        e.cur = c->cur;
+        e.x = B.x;
+        e.xnext = c->xnext;
+        e.v = B.v;
+        e.vnext = c->vnext;
+        // the null stream cannot be captured: capture on a stream of the handle's own
+        hipStream_t run = c->stream;
+        if (!run && !c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t cap = run ? run : c->cap_stream;
+        double4* x0 = B.x;
+        double4* xn0 = c->xnext;
+        double* v0 = B.v;
+        double* vn0 = c->vnext;
+        c->stream = cap;
+        c->step_base_d = c->step_dev;
+        hipError_t st = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (st == hipSuccess) {
+            for (int q = 0; q < len; ++q) launch_step(c, q, q, save && q == 0);
+            st = hipStreamEndCapture(cap, &e.graph);
+        }
+        c->step_base_d = nullptr;
+        c->stream = run;
+        e.x_after = B.x;
+        e.xnext_after = c->xnext;
+        e.v_after = B.v;
+        e.vnext_after = c->vnext;
+        B.x = x0;   // nothing ran yet: the buffers swap when the graph runs
+        c->xnext = xn0;
+        B.v = v0;
+        c->vnext = vn0;
+        if (st != hipSuccess) return fail(c, DB_EDEVICE, "graph capture: %s", hipGetErrorString(st));
+        HIPCHK(c, hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+        c->graphs->push_back(e);
+        hit = &c->graphs->back();
+    }
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, c->stream, c->step_dev, k0);
+    HIPCHK(c, hipGraphLaunch(hit->exec, c->stream));
+    B.x = (double4*)hit->x_after;
+    c->xnext = (double4*)hit->xnext_after;
+    B.v = (double*)hit->v_after;
+    c->vnext = (double*)hit->vnext_after;
+    return DB_OK;
+}
+
 // The list can be kept across sweeps when pairs interact and every box has at
 // least five cells per edge (the patched lists scan two cell edges around a bead).
 static bool list_reuse_allowed(const db_ctx* c) {
@@ -1264,9 +1349,14 @@ int db_step(db_ctx* c, int64_t nsteps) {
         }
         // the block's input state is kept for a re-run: by the reorder, or else by
         // the first step kernel of the block
-        for (int64_t q = 0; q < len; ++q) {
-            rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0);
+        if (c->use_graph && !c->profile) {
+            rc = run_steps_graph(c, k0, (int)len, guard && !permute);
             if (rc) return rc;
+        } else {
+            for (int64_t q = 0; q < len; ++q) {
+                rc = launch_timed_step(c, k0 + q, (int)q, guard && !permute && q == 0);
+                if (rc) return rc;
+            }
         }
         hipLaunchKernelGGL(k_report, dim3(1), dim3(kMaxBlock), 0, s, c->vmax2, (int)len, c->err_d, c->sw.stats,
                            sweep_due ? 1 : 0, X.pin_dev);
@@ -1522,6 +1612,12 @@ int db_set_step(db_ctx* c, int64_t step) {
     return DB_OK;
 }
 
+int db_graph(db_ctx* c, int enable) {
+    if (!c || (enable != 0 && enable != 1)) return DB_EINVAL;
+    c->use_graph = enable == 1;
+    return DB_OK;
+}
+
 int db_tile_shape(db_ctx* c, int enable, int32_t brick_edge) {
     if (!c || (enable != 0 && enable != 1) || brick_edge < 0 || brick_edge > 64) return DB_EINVAL;
     c->tile_mode = enable;
@@ -1565,6 +1661,19 @@ int db_tune(db_ctx* c, double skin, int32_t permute_every) {
     return DB_OK;
 }
 
+// steps_per_trial steps after one untimed step (which sets up a new grid or order)
+static int timed_trial(db_ctx* c, int64_t steps_per_trial, double* t) {
+    int rc = db_step(c, 1);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    auto t0 = std::chrono::steady_clock::now();
+    rc = db_step(c, steps_per_trial);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return DB_OK;
+}
+
 int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* best_permute) {
     if (!c || steps_per_trial < 1) return DB_EINVAL;
     // DPD at density 3 favours thinner skins than the WCA workloads
@@ -1579,14 +1688,9 @@ int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* 
         for (int pe : perms) {
             int rc = db_tune(c, sk, pe);
             if (rc) return rc;
-            rc = db_step(c, 1);   // the new grid is set up outside the timed steps
+            double t = 0;
+            rc = timed_trial(c, steps_per_trial, &t);
             if (rc) return rc;
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            auto t0 = std::chrono::steady_clock::now();
-            rc = db_step(c, steps_per_trial);
-            if (rc) return rc;
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             if (t < best_t) {
                 best_t = t;
                 bs = sk;
@@ -1596,8 +1700,50 @@ int db_autotune(db_ctx* c, int64_t steps_per_trial, double* best_skin, int32_t* 
     }
     int rc = db_tune(c, bs, bp);
     if (rc) return rc;
+    // then the step kernel's shape: per-bead gathers, or tiles over bricks of 3, 4
+    // or 5 cells (single systems with WCA pairs); then graphs off or on
+    const bool can_tile = c->nrep == 0 && c->hp.have_pair && c->hp.pair_style == PAIR_WCA;
+    int best_mode = 0, best_edge = 0;
+    double shape_t = INFINITY;
+    const int edges[4] = {0, 3, 4, 5};
+    for (int k = 0; k < (can_tile ? 4 : 1); ++k) {
+        const int mode = k == 0 ? 0 : 1, edge = edges[k];
+        rc = db_tile_shape(c, mode, edge);
+        if (rc) return rc;
+        double t = 0;
+        rc = timed_trial(c, steps_per_trial, &t);
+        if (rc) return rc;
+        if (t < shape_t) {
+            shape_t = t;
+            best_mode = mode;
+            best_edge = edge;
+        }
+    }
+    rc = db_tile_shape(c, best_mode, best_edge);
+    if (rc) return rc;
+    int best_graph = 0;
+    double graph_t = INFINITY;
+    for (int gr = 0; gr < 2; ++gr) {
+        c->use_graph = gr == 1;
+        double t = 0;
+        rc = timed_trial(c, steps_per_trial, &t);
+        if (rc) return rc;
+        if (t < graph_t) {
+            graph_t = t;
+            best_graph = gr;
+        }
+    }
+    c->use_graph = best_graph == 1;
     if (best_skin) *best_skin = bs;
     if (best_permute) *best_permute = bp;
+    return DB_OK;
+}
+
+int db_get_shape(db_ctx* c, int32_t out[3]) {
+    if (!c || !out) return DB_EINVAL;
+    out[0] = c->tile_mode;
+    out[1] = c->brick_edge;
+    out[2] = c->use_graph ? 1 : 0;
     return DB_OK;
 }
 

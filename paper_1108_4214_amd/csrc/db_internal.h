@@ -184,6 +184,19 @@ struct Tiles {
     uint4* code8;     // [n][2] its first four angle codes, then its first four dihedral codes
 };
 
+// The step launches of one block captured as a HIP graph.  The key is everything
+// the captured arguments depend on; the launches swap the position (and velocity)
+// buffers, whose state after the block is kept for replays.
+struct GraphEntry {
+    int len;
+    bool save, tiled;
+    int cur;
+    const void *x, *xnext, *v, *vnext;             // buffers before the block
+    const void *x_after, *xnext_after, *v_after, *vnext_after;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 struct Cells {
     int* cnt;         // [ncell]
     int* start;       // [ncell + 1]
@@ -260,6 +273,11 @@ struct db_ctx {
     bool ledger;         // track the topology-energy ledger
     double du_last, du_cum;
     int64_t* cnt64;      // small device counters
+    int64_t* step_dev;   // the first step of the block being replayed from a graph
+    int64_t* step_base_d;   // step_dev while step launches are captured, else nullptr
+    bool use_graph;      // blocks' step launches are replayed from captured HIP graphs
+    std::vector<db::GraphEntry>* graphs;   // captured blocks, keyed by length and buffers
+    hipStream_t cap_stream;   // capture stream when the handle's stream is the null stream
     void* pinned;        // pinned host staging
     int max_block;
 

@@ -820,6 +820,18 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Replayed from a HIP graph, a step kernel's arguments are those of its capture:
+// the block's first step is then read from the device word step_base (step is the
+// offset within the block) and the single system's thermostat amplitudes are
+// formed here from the temperature schedule, with the host's arithmetic.
+__device__ __forceinline__ void step_amplitudes(const Params& P, const int64_t* step_base, int64_t& step,
+                                                double& pref, double& dsig) {
+    step += *step_base;
+    const double T = box_temperature(P.box, step);
+    pref = P.gamma != 0.0 ? sqrt(24.0 * P.gamma * T / P.dt) : 0.0;
+    dsig = (P.pair_style == PAIR_DPD && P.dpd_gamma != 0.0) ? sqrt(2.0 * T * P.dpd_gamma) / sqrt(P.dt) : 0.0;
+}
+
 // pref: sqrt(24 gamma T / dt) of a single system (from the host), dsig: the DPD
 // sigma / sqrt(dt) = sqrt(2 T gamma_DPD) / sqrt(dt); a batch forms both per bead
 // from the replica's temperature.  PAIR selects the pair style at compile time.
@@ -835,10 +847,11 @@ __global__ __launch_bounds__(DB_BLOCK, (sizeof(R) == 4 && PAIR == PAIR_WCA && !B
 void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H, double4* __restrict__ xout, double* vout,
             int64_t step, double pref, double dsig, unsigned int* __restrict__ vmax2_slot, double* __restrict__ fout,
             int* __restrict__ err, double4* __restrict__ xsave, double* __restrict__ vsave,
-            const double4* __restrict__ xref) {
+            const double4* __restrict__ xref, const int64_t* __restrict__ step_base) {
     static_assert(MODE == MODE_STEP || MODE == MODE_FORCES, "energies use k_energy");
     const Params& P = *Pp;
     const int n = P.n;
+    if (step_base) step_amplitudes(P, step_base, step, pref, dsig);
     __shared__ Coef<R> C;
     load_coef<R>(P, C);
     __syncthreads();
@@ -1443,9 +1456,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step_tile(const Params* __restrict
                                                         Tiles T, double4* __restrict__ xout, int64_t step,
                                                         double pref, unsigned int* __restrict__ vmax2_slot,
                                                         int* __restrict__ err, double4* __restrict__ xsave,
-                                                        double* __restrict__ vsave) {
+                                                        double* __restrict__ vsave,
+                                                        const int64_t* __restrict__ step_base) {
     const Params& P = *Pp;
     const int n = P.n;
+    if (step_base) {
+        double dsig = 0.0;
+        step_amplitudes(P, step_base, step, pref, dsig);
+    }
     const Box& X = P.box;
     __shared__ Coef<R> C;
     __shared__ double rx[DB_RCAP], ry[DB_RCAP], rz[DB_RCAP];
@@ -1729,7 +1747,8 @@ static void launch_step_kernel(db_ctx* c, const Bank& B, double4* xout, double* 
                                double dsig, unsigned* vm, double* f, bool save) {
     hipLaunchKernelGGL((k_step<R, MODE, BATCH, PAIR>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
                        B, c->nlist, c->halo, xout, vout, step, pref, dsig, vm, f, c->err_d,
-                       save ? c->xsave : nullptr, save ? c->vsave : nullptr, c->xref);
+                       save ? c->xsave : nullptr, save ? c->vsave : nullptr, c->xref,
+                       MODE == MODE_STEP ? (const int64_t*)c->step_base_d : nullptr);
 }
 
 template <int MODE, int PAIR>
@@ -1756,10 +1775,12 @@ static void launch_step_any(db_ctx* c, const Bank& B, double4* xout, double* vou
         launch_step_pair<MODE, PAIR_WCA>(c, B, xout, vout, step, pref, dsig, vm, f, save);
 }
 
+// c->step_base_d set (the launch is captured into a graph): step is the offset within
+// the block and the kernel reads the block's first step from the device
 void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
     if (c->n == 0) return;
-    const double pref = langevin_prefactor(c->hp, step);
-    const double dsig = dpd_sigma(c->hp, step);
+    const double pref = c->step_base_d ? 0.0 : langevin_prefactor(c->hp, step);
+    const double dsig = c->step_base_d ? 0.0 : dpd_sigma(c->hp, step);
     Bank& B = c->bank[c->cur];
     unsigned* vm = (unsigned*)(c->vmax2 + (size_t)slot_in_block * DB_VMAX_SPREAD);
     const bool vbuf = velocity_double_buffer(c);
@@ -1768,10 +1789,12 @@ void launch_step(db_ctx* c, int64_t step, int slot_in_block, bool save) {
         double* vs = save ? c->vsave : nullptr;
         if (c->precision == DB_MIXED)
             hipLaunchKernelGGL(k_step_tile<float>, dim3(c->ntile), dim3(DB_BLOCK), 0, c->stream, c->dp, B, c->nlist,
-                               c->halo, c->tiles, c->xnext, step, pref, vm, c->err_d, xs, vs);
+                               c->halo, c->tiles, c->xnext, step, pref, vm, c->err_d, xs, vs,
+                               (const int64_t*)c->step_base_d);
         else
             hipLaunchKernelGGL(k_step_tile<double>, dim3(c->ntile), dim3(DB_BLOCK), 0, c->stream, c->dp, B,
-                               c->nlist, c->halo, c->tiles, c->xnext, step, pref, vm, c->err_d, xs, vs);
+                               c->nlist, c->halo, c->tiles, c->xnext, step, pref, vm, c->err_d, xs, vs,
+                               (const int64_t*)c->step_base_d);
     } else {
         launch_step_any<MODE_STEP>(c, B, c->xnext, vbuf ? c->vnext : B.v, step, pref, dsig, vm, nullptr, save);
     }

@@ -106,7 +106,9 @@ def test_autotune_picks_a_grid_point():
     g = pk.System(s.n, s.L, 3, 1).configure(s, synth.ff_t2(), synth.rules_t2())
     skin, perm = pk.db_autotune(g.ctx, 3)
     assert skin in (0.4, 0.5, 0.6, 0.8) and perm in (1, 2, 4, 8)
-    assert g.stats()["steps"] == 16 * 4
+    shape = pk.db_get_shape(g.ctx)
+    assert shape["tiles"] in (0, 1) and shape["brick_edge"] in (0, 3, 4, 5) and shape["graph"] in (0, 1)
+    assert g.stats()["steps"] == (16 + 4 + 2) * 4
 
 
 def test_ladder_replicas_batch_forces_and_sweep():

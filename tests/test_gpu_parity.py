@@ -611,3 +611,70 @@ def test_tile_shape_arguments():
         pk.db_tile_shape(g.ctx, 2, 0)
     with pytest.raises(pk.DynBondError):
         pk.db_tile_shape(g.ctx, 1, -1)
+
+
+# ---- HIP graphs ------------------------------------------------------------------------
+
+def _graph_run(s, ff, rules, precision, graph, checkpoints, seed=7, tiles=0, batch_of=None):
+    import paper_1108_4214_amd as pk
+    g = pk.System(s.n, s.L, seed, precision)
+    pk.db_graph(g.ctx, graph)
+    pk.db_tile_shape(g.ctx, tiles, 0)
+    g.configure(s, ff, rules)
+    out = []
+    done = 0
+    for k in checkpoints:
+        g.step(k - done)
+        done = k
+        out.append(g.state())
+    out.append((g.bonds(), g.angles(), g.dihedrals()))
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("precision,tiles", [(0, 0), (1, 0), (1, 1)])
+def test_graph_replays_equal_eager_launches(precision, tiles):
+    """Blocks replayed from captured graphs (several lengths, rollback copies, both
+    buffer parities, sweeps and list rebuilds in between) give the trajectory of the
+    launches issued one by one, bit for bit, at every checkpoint."""
+    s = _duplex_system(40, 8, 0.3, seed=31, scale=0.05)
+    rules = synth.rules_t2(p=0.6, every=7, r_kill=1.3)
+    ff = synth.ff_t2()
+    cps = [3, 10, 25, 60, 100, 140]
+    a = _graph_run(s, ff, rules, precision, 1, cps, tiles=tiles)
+    b = _graph_run(s, ff, rules, precision, 0, cps, tiles=tiles)
+    for (xa, va), (xb, vb) in zip(a[:-1], b[:-1]):
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    for ta, tb in zip(a[-1], b[-1]):
+        assert np.array_equal(ta, tb)
+
+
+def test_graph_replays_dpd_and_batch():
+    """The DPD velocity double buffer and a batch of replicas under graph replay."""
+    import paper_1108_4214_amd as pk
+    s = synth.dpd_solution(16, 6, 4000, 3.0, 7, 17)
+    ff = synth.ff_dpd()
+    rules = synth.rules_t2(p=0.5, every=5)
+    a = _graph_run(s, ff, rules, 0, 1, [4, 17, 40])
+    b = _graph_run(s, ff, rules, 0, 0, [4, 17, 40])
+    for (xa, va), (xb, vb) in zip(a[:-1], b[:-1]):
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    outs = []
+    for graph in (1, 0):
+        reps = []
+        for r, (nd, nbp, rho, T) in enumerate(((12, 8, 0.3, 0.8), (8, 6, 0.2, 1.2))):
+            sr = perturbed(synth.duplex_box(nd, nbp, rho, 70 + r, 80 + r, T=T), 0.05, 70 + r)
+            g = pk.System(sr.n, sr.L, 90 + r).configure(sr, synth.ff_t2(T0=T, T1=T), synth.rules_t2(p=0.7, every=5))
+            pk.db_set_reactive(g.ctx, sr.reactive)
+            reps.append(g)
+        bt = pk.Batch(reps)
+        pk.db_graph(bt.ctx, graph)
+        bt.step(23)
+        outs.append([bt.replica_state(r) for r in range(2)])
+        bt.step(31)
+        outs[-1] += [bt.replica_state(r) for r in range(2)]
+        bt.close()
+        for g in reps:
+            g.close()
+    for (xa, va), (xb, vb) in zip(outs[0], outs[1]):
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
