@@ -219,6 +219,9 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->tiles.hu16, 2 * (size_t)DB_MAXU * n);
     put(c->tiles.rec, 16 * n);
     put(c->tiles.code8, 32 * n);
+    put(c->tiles.itemA, 8 * tcap * DB_CAPA);
+    put(c->tiles.itemD, 8 * tcap * DB_CAPD);
+    put(c->tiles.nitems, 4 * tcap);
     put(c->err_d, 64);
     put(c->step_dev, 64);
     put(c->vmax2, 4 * (size_t)kMaxBlock * DB_VMAX_SPREAD);

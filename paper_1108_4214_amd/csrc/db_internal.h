@@ -20,6 +20,8 @@
 #define DB_HALO_OVF 255      // halo marker: more than DB_MAXU distinct bonded partners
 #define DB_VMAX_SPREAD 64    // words per step over which the speed maxima are spread
 #define DB_RCAP 768          // region entries a tile of the step kernel stages in LDS
+#define DB_CAPA 448          // angle work items of a tile
+#define DB_CAPD 224          // dihedral work items of a tile
 #define DB_SLOT_BITS 26      // the float position copy packs slot | type << 26 | reactive << 31
 #define DB_MAX_BEADS ((1 << DB_SLOT_BITS) - 1)
 
@@ -181,7 +183,15 @@ struct Tiles {
     uint16_t* hu16;   // [n][DB_MAXU] halo entries as region indices
     uint4* rec;       // [n] the bead's words for the step: bond types; halo size, list length and table
                       // counts; its own region index and meta word; its global id
-    uint4* code8;     // [n][2] its first four angle codes, then its first four dihedral codes
+    uint4* code8;     // [n][2] its first four angle codes, then its first four dihedral codes (tiles with
+                      // work items: the item and the bead's member role of each entry instead)
+    // Work items: every angle and dihedral with a member in the tile, once per tile,
+    // as the region indices of its members (10 bits each) and its type; the step
+    // kernel evaluates each once for all of its members and the members collect
+    // their forces from LDS
+    uint2* itemA;     // [ntile][DB_CAPA]
+    uint2* itemD;     // [ntile][DB_CAPD]
+    uint32_t* nitems; // [ntile] angle items | dihedral items << 16; 0xFFFFFFFF: no items (per-bead terms)
 };
 
 // The step launches of one block captured as a HIP graph.  The key is everything

@@ -599,6 +599,73 @@ __device__ __forceinline__ void dihedral_core(const Coef<R>& C, int role, int t,
     }
 }
 
+// The forces on all three members of an angle (a, b, c), u = x_a - x_b, w = x_c - x_b:
+// the arithmetic of angle_core, every role at once (f[role][component])
+template <typename R>
+__device__ __forceinline__ void angle_all(const Coef<R>& C, int t, R ux, R uy, R uz, R wx, R wy, R wz,
+                                          R (&f)[3][3]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) f[r][0] = f[r][1] = f[r][2] = (R)0;
+    R ru2 = (ux * ux + uy * uy) + uz * uz;
+    R rw2 = (wx * wx + wy * wy) + wz * wz;
+    if (!(ru2 > (R)0) || !(rw2 > (R)0)) return;
+    R iru = r_rsqrt<R>(ru2), irw = r_rsqrt<R>(rw2);
+    R cux = ux * iru, cuy = uy * iru, cuz = uz * iru;
+    R cwx = wx * irw, cwy = wy * irw, cwz = wz * irw;
+    R cs = (cux * cwx + cuy * cwy) + cuz * cwz;
+    R crx = cuy * cwz - cuz * cwy, cry = cuz * cwx - cux * cwz, crz = cux * cwy - cuy * cwx;
+    R sn = r_sqrt<R>((crx * crx + cry * cry) + crz * crz);
+    R K = C.aK[t];
+    R del = r_atan2<R>(sn, -cs);   // pi - theta
+    R isn = r_rcp<R>(sn > (R)1e-8 ? sn : (R)1e-8);
+    R ratio = del < (R)1e-6 ? (R)1.0 + del * del * (R)(1.0 / 6.0) : del * isn;
+    R pth = C.aPm[t];
+    R A = (R)2.0 * K * (-ratio + (pth != (R)0 ? pth * isn : (R)0));
+    R Au = -A * iru, Aw = -A * irw;
+    f[0][0] = Au * (cs * cux - cwx);
+    f[0][1] = Au * (cs * cuy - cwy);
+    f[0][2] = Au * (cs * cuz - cwz);
+    f[2][0] = Aw * (cs * cwx - cux);
+    f[2][1] = Aw * (cs * cwy - cuy);
+    f[2][2] = Aw * (cs * cwz - cuz);
+    f[1][0] = -(f[0][0] + f[2][0]);
+    f[1][1] = -(f[0][1] + f[2][1]);
+    f[1][2] = -(f[0][2] + f[2][2]);
+}
+
+// The forces on the end members (a, d) of a dihedral (a, b, c, d) from its bond
+// vectors, and the projections pp = b1.b2 / |b2|^2, qq = b3.b2 / |b2|^2 that give
+// those on the inner ones: f_b = qq f_d - (pp + 1) f_a, f_c = pp f_a - (qq + 1) f_d.
+// The arithmetic of dihedral_core.
+template <typename R>
+__device__ __forceinline__ void dihedral_ends(const Coef<R>& C, int t, R b1x, R b1y, R b1z, R b2x, R b2y, R b2z,
+                                              R b3x, R b3y, R b3z, R (&fa)[3], R (&fd)[3], R& pp, R& qq) {
+    fa[0] = fa[1] = fa[2] = (R)0;
+    fd[0] = fd[1] = fd[2] = (R)0;
+    pp = qq = (R)0;
+    R mx = b1y * b2z - b1z * b2y, my = b1z * b2x - b1x * b2z, mz = b1x * b2y - b1y * b2x;
+    R nx = b2y * b3z - b2z * b3y, ny = b2z * b3x - b2x * b3z, nz = b2x * b3y - b2y * b3x;
+    R m2 = (mx * mx + my * my) + mz * mz;
+    R n2 = (nx * nx + ny * ny) + nz * nz;
+    R b22 = (b2x * b2x + b2y * b2y) + b2z * b2z;
+    if (m2 < (R)1e-24 || n2 < (R)1e-24 || b22 < (R)1e-24) return;   // collinear: no defined plane
+    R nb2 = r_sqrt<R>(b22);
+    R inv = r_rsqrt<R>(m2 * n2);
+    R cphi = ((mx * nx + my * ny) + mz * nz) * inv;
+    R sphi = nb2 * ((b1x * nx + b1y * ny) + b1z * nz) * inv;
+    R K = C.dK[t], c0 = C.dC0[t], s0 = C.dS0[t];
+    R dU = K * (sphi * c0 - cphi * s0);   // dU/dphi
+    R sa = -nb2 * r_rcp<R>(m2), sd = nb2 * r_rcp<R>(n2), ib22 = r_rcp<R>(b22);
+    pp = ((b1x * b2x + b1y * b2y) + b1z * b2z) * ib22;
+    qq = ((b3x * b2x + b3y * b2y) + b3z * b2z) * ib22;
+    fa[0] = -dU * (sa * mx);
+    fa[1] = -dU * (sa * my);
+    fa[2] = -dU * (sa * mz);
+    fd[0] = -dU * (sd * nx);
+    fd[1] = -dU * (sd * ny);
+    fd[2] = -dU * (sd * nz);
+}
+
 template <typename R, int MODE>
 __device__ __forceinline__ void dihedral_one(const Params& P, const Box& X, const Coef<R>& C, int i, const int4& e, int t,
                                              const double4& xa, const double4& xb, const double4& xc,
@@ -1118,36 +1185,155 @@ __global__ __launch_bounds__(DB_BLOCK) void k_region(const Params* __restrict__ 
     }
     if (tid == 0) T.rcount[tile] = R;
     __syncthreads();
-    if (!active) return;
-    // the entries as region indices: the first DB_NLHEAD of the list in one row
-    uint32_t w16[DB_NLHEAD / 2];
+    if (active) {
+        // the entries as region indices: the first DB_NLHEAD of the list in one row
+        uint32_t w16[DB_NLHEAD / 2];
 #pragma unroll
-    for (int k = 0; k < DB_NLHEAD / 2; ++k) {
-        const uint32_t lo = 2 * k < m ? hv[region_find(ht, e[2 * k])] : 0u;
-        const uint32_t hi = 2 * k + 1 < m ? hv[region_find(ht, e[2 * k + 1])] : 0u;
-        w16[k] = lo | hi << 16;
-    }
-    uint4* row = reinterpret_cast<uint4*>(T.nl16 + (size_t)i * DB_NLHEAD);
-    row[0] = make_uint4(w16[0], w16[1], w16[2], w16[3]);
-    row[1] = make_uint4(w16[4], w16[5], w16[6], w16[7]);
-    for (int k = DB_NLHEAD; k < m; ++k) T.nl16[nl16_index(n, i, k)] = hv[region_find(ht, NL.nl[k * n + i])];
-    uint32_t h16[DB_MAXU / 2];
+        for (int k = 0; k < DB_NLHEAD / 2; ++k) {
+            const uint32_t lo = 2 * k < m ? hv[region_find(ht, e[2 * k])] : 0u;
+            const uint32_t hi = 2 * k + 1 < m ? hv[region_find(ht, e[2 * k + 1])] : 0u;
+            w16[k] = lo | hi << 16;
+        }
+        uint4* row = reinterpret_cast<uint4*>(T.nl16 + (size_t)i * DB_NLHEAD);
+        row[0] = make_uint4(w16[0], w16[1], w16[2], w16[3]);
+        row[1] = make_uint4(w16[4], w16[5], w16[6], w16[7]);
+        for (int k = DB_NLHEAD; k < m; ++k) T.nl16[nl16_index(n, i, k)] = hv[region_find(ht, NL.nl[k * n + i])];
+        uint32_t h16[DB_MAXU / 2];
 #pragma unroll
-    for (int q = 0; q < DB_MAXU / 2; ++q) {
-        const uint32_t lo = (nu <= DB_MAXU && 2 * q < nu) ? hv[region_find(ht, u[2 * q])] : 0u;
-        const uint32_t hi = (nu <= DB_MAXU && 2 * q + 1 < nu) ? hv[region_find(ht, u[2 * q + 1])] : 0u;
-        h16[q] = lo | hi << 16;
+        for (int q = 0; q < DB_MAXU / 2; ++q) {
+            const uint32_t lo = (nu <= DB_MAXU && 2 * q < nu) ? hv[region_find(ht, u[2 * q])] : 0u;
+            const uint32_t hi = (nu <= DB_MAXU && 2 * q + 1 < nu) ? hv[region_find(ht, u[2 * q + 1])] : 0u;
+            h16[q] = lo | hi << 16;
+        }
+        *reinterpret_cast<uint4*>(T.hu16 + (size_t)i * DB_MAXU) = make_uint4(h16[0], h16[1], h16[2], h16[3]);
+        const uint32_t mhi = (uint32_t)meta_word(xi) & 0xFFFFu;   // type | reactive << 8 (one box: replica 0)
+        T.rec[i] = make_uint4(bt4, (uint32_t)nu | (uint32_t)m << 8 | (uint32_t)nb << 16 | (uint32_t)na << 20 |
+                                       (uint32_t)nd << 24,
+                              (uint32_t)hv[region_find(ht, i)] | mhi << 16, (uint32_t)meta_gid(xi));
     }
-    *reinterpret_cast<uint4*>(T.hu16 + (size_t)i * DB_MAXU) = make_uint4(h16[0], h16[1], h16[2], h16[3]);
-    // the bead's record and its first angle and dihedral codes
-    const uint32_t mhi = (uint32_t)meta_word(xi) & 0xFFFFu;   // type | reactive << 8 (one box: replica 0)
-    T.rec[i] = make_uint4(bt4, (uint32_t)nu | (uint32_t)m << 8 | (uint32_t)nb << 16 | (uint32_t)na << 20 |
-                                   (uint32_t)nd << 24,
-                          (uint32_t)hv[region_find(ht, i)] | mhi << 16, (uint32_t)meta_gid(xi));
+    // Work items.  Every angle (dihedral) with a member in the tile is emitted once,
+    // by its centre (its second bead) when that is in the tile, else by its lowest
+    // member in the tile; each member then finds the item through the emitter's
+    // table and records it with its own role.  A tile whose beads hold more than four
+    // angles or dihedrals, or whose halo overflows, keeps per-bead terms.
+    __shared__ uint16_t emitA[DB_BLOCK][4], emitD[DB_BLOCK][4];
+    __shared__ int nA, nD, bad;
+    if (tid == 0) {
+        nA = 0;
+        nD = 0;
+        bad = 0;
+    }
+    const int t0 = tile * DB_BLOCK, t1 = min(t0 + DB_BLOCK, n);
+    auto in_tile = [&](int x) { return x >= t0 && x < t1; };
+    int4 ang[4], dih[4];
+    int dt4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (k >= na) cw[k] = 0u;
-        if (k >= nd) cw[4 + k] = 0u;
+        ang[k] = make_int4(0, 0, 0, 0);
+        dih[k] = make_int4(0, 0, 0, 0);
+        dt4[k] = 0;
+        if (active && k < na) ang[k] = B.ang[k * n + i];
+        if (active && k < nd) {
+            dih[k] = B.dih[k * n + i];
+            dt4[k] = B.dt[k * n + i] & (DB_MAXT - 1);
+        }
+    }
+    __syncthreads();
+    if (active && (na > 4 || nd > 4 || nu > DB_MAXU)) bad = 1;
+    auto emitter3 = [&](int4 q) {   // centre if in the tile, else the lowest member in the tile
+        if (in_tile(q.y)) return q.y;
+        int em = 0x7FFFFFFF;
+        if (in_tile(q.x)) em = min(em, q.x);
+        if (in_tile(q.z)) em = min(em, q.z);
+        return em;
+    };
+    auto emitter4 = [&](int4 q) {
+        if (in_tile(q.y)) return q.y;
+        int em = 0x7FFFFFFF;
+        if (in_tile(q.x)) em = min(em, q.x);
+        if (in_tile(q.z)) em = min(em, q.z);
+        if (in_tile(q.w)) em = min(em, q.w);
+        return em;
+    };
+    auto rix = [&](int slot) { return (uint32_t)hv[region_find(ht, slot)]; };
+    if (active && na <= 4 && nd <= 4 && nu <= DB_MAXU) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            emitA[tid][k] = 0xFFFF;
+            emitD[tid][k] = 0xFFFF;
+            if (k < na && emitter3(ang[k]) == i) {
+                const int idx = atomicAdd(&nA, 1);
+                if (idx < DB_CAPA) {
+                    T.itemA[(size_t)tile * DB_CAPA + idx] =
+                        make_uint2(rix(ang[k].x) | rix(ang[k].y) << 10 | rix(ang[k].z) << 20,
+                                   (uint32_t)(ang[k].w & (DB_MAXT - 1)));
+                    emitA[tid][k] = (uint16_t)idx;
+                }
+            }
+            if (k < nd && emitter4(dih[k]) == i) {
+                const int idx = atomicAdd(&nD, 1);
+                if (idx < DB_CAPD) {
+                    T.itemD[(size_t)tile * DB_CAPD + idx] =
+                        make_uint2(rix(dih[k].x) | rix(dih[k].y) << 10 | rix(dih[k].z) << 20,
+                                   rix(dih[k].w) | (uint32_t)dt4[k] << 10);
+                    emitD[tid][k] = (uint16_t)idx;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const bool items = !bad && nA <= DB_CAPA && nD <= DB_CAPD;
+    if (tid == 0) T.nitems[tile] = items ? ((uint32_t)nA | (uint32_t)nD << 16) : 0xFFFFFFFFu;
+    if (!active) return;
+    if (items) {
+        // code of entry k: item | role << 16 | 1 << 31, found through the emitter's table
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t ca = 0u, cd = 0u;
+            if (k < na) {
+                const int4 q = ang[k];
+                const int em = emitter3(q);
+                int idx = 0xFFFF;
+                if (em == i) {
+                    idx = emitA[tid][k];
+                } else {
+                    const int ne = B.na[em];
+                    for (int kk = 0; kk < ne && kk < 4; ++kk) {
+                        const int4 r = B.ang[kk * n + em];
+                        if (r.x == q.x && r.y == q.y && r.z == q.z && r.w == q.w) idx = emitA[em - t0][kk];
+                    }
+                }
+                const int role = q.x == i ? 0 : (q.y == i ? 1 : 2);
+                ca = (uint32_t)idx | (uint32_t)role << 16 | 1u << 31;
+            }
+            if (k < nd) {
+                const int4 q = dih[k];
+                const int em = emitter4(q);
+                int idx = 0xFFFF;
+                if (em == i) {
+                    idx = emitD[tid][k];
+                } else {
+                    const int ne = B.nd[em];
+                    for (int kk = 0; kk < ne && kk < 4; ++kk) {
+                        const int4 r = B.dih[kk * n + em];
+                        const int rt = B.dt[kk * n + em] & (DB_MAXT - 1);
+                        if (r.x == q.x && r.y == q.y && r.z == q.z && r.w == q.w && rt == dt4[k])
+                            idx = emitD[em - t0][kk];
+                    }
+                }
+                const int role = q.x == i ? 0 : (q.y == i ? 1 : (q.z == i ? 2 : 3));
+                cd = (uint32_t)idx | (uint32_t)role << 16 | 1u << 31;
+            }
+            cw[k] = ca;
+            cw[4 + k] = cd;
+        }
+    } else {
+        // per-bead terms: the first angle and dihedral codes of the halo
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k >= na) cw[k] = 0u;
+            if (k >= nd) cw[4 + k] = 0u;
+        }
     }
     T.code8[2 * (size_t)i] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
     T.code8[2 * (size_t)i + 1] = make_uint4(cw[4], cw[5], cw[6], cw[7]);
@@ -1241,6 +1427,30 @@ __device__ __forceinline__ uint4 tile_bead_load(const Tiles& T, int i, TileBead&
     tb.dc[2] = d4.z;
     tb.dc[3] = d4.w;
     return rc;
+}
+
+// The bond forces on bead i (its halo's first nb members), as in tile_bonded
+template <typename R, bool STAGED, bool IMAGE>
+__device__ __forceinline__ void tile_bonds(const Params& P, const Box& X, const Coef<R>& C,
+                                           const TilePos<STAGED, IMAGE>& tp, const double4& xi, const TileBead& tb,
+                                           Acc<R>& a) {
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k) {
+        if (k >= tb.nb) continue;
+        double dx, dy, dz;
+        tp.sep(half16(tb.hu, k), xi, X, dx, dy, dz);
+        const int t = tb.btk[k] & (DB_MAXT - 1);
+        const double rd2 = (dx * dx + dy * dy) + dz * dz;
+        if (!(rd2 > 0.0) || !(rd2 < C.bRc2[t])) continue;
+        const R ex = (R)dx, ey = (R)dy, ez = (R)dz;
+        R rr2 = (ex * ex + ey * ey) + ez * ez;
+        R ir = r_rsqrt<R>(rr2);
+        R r = rr2 * ir;
+        R g = (R)2.0 * C.bK[t] * (r - C.bR0[t]) * ir;
+        a.fx += (double)(g * ex);
+        a.fy += (double)(g * ey);
+        a.fz += (double)(g * ez);
+    }
 }
 
 // All bonded forces on bead i through its halo, with the same arithmetic in the
@@ -1375,22 +1585,24 @@ __device__ __forceinline__ void wide_bonded(const Params& P, const Box& X, const
     }
 }
 
-// One bead's step in a tile (the body of k_step_tile): partners from the staged
-// region (STAGED) or from memory by slot.  Returns |v|^2 after the step.
-template <typename R, bool STAGED, bool IMAGE>
-__device__ __forceinline__ double tile_bead_step(const Params& P, const Box& X, const Coef<R>& C, Bank& B,
+// Forces on one bead of a tile (the first part of k_step_tile's work): partners
+// from the staged region (STAGED) or from memory by slot.  Bonds and pairs always;
+// angles and dihedrals here only without ITEMS (with ITEMS the tile's work items
+// form them and tile_collect adds them afterwards).
+template <typename R, bool STAGED, bool IMAGE, bool ITEMS>
+__device__ __forceinline__ void tile_bead_forces(const Params& P, const Box& X, const Coef<R>& C, const Bank& B,
                                                  const NList& NL, const Halo& H, const Tiles& T, const double* rx,
                                                  const double* ry, const double* rz, uint16_t (*hidx)[DB_BLOCK], int i,
-                                                 const double4& xi, const double4& xs, double vx, double vy, double vz,
-                                                 const TileBead& tb, double4* __restrict__ xout, int64_t step,
-                                                 double pref, int* __restrict__ err, double4* __restrict__ xsave,
-                                                 double* __restrict__ vsave) {
+                                                 const double4& xi, const double4& xs, const TileBead& tb, Acc<R>& a) {
     const int n = P.n;
     const TilePos<STAGED, IMAGE> tp{rx, ry, rz, B.x};
     const R rc2 = (R)P.rc2;
-    Acc<R> a;
-    if (tb.nu <= DB_MAXU) tile_bonded<R, STAGED, IMAGE>(P, X, C, H, tp, hidx, i, xs, tb, a);
-    else wide_bonded<R>(P, X, C, B, i, xi, a);
+    if constexpr (ITEMS) {
+        tile_bonds<R, STAGED, IMAGE>(P, X, C, tp, xs, tb, a);
+    } else {
+        if (tb.nu <= DB_MAXU) tile_bonded<R, STAGED, IMAGE>(P, X, C, H, tp, hidx, i, xs, tb, a);
+        else wide_bonded<R>(P, X, C, B, i, xi, a);
+    }
     const int m = tb.m;
     if constexpr (STAGED) {
         // the first DB_NLHEAD entries from registers, in list order, then the rest
@@ -1402,11 +1614,73 @@ __device__ __forceinline__ double tile_bead_step(const Params& P, const Box& X, 
     } else {
         for (int k = 0; k < m; ++k) tile_pair<R, false, IMAGE>(P, X, tp, NL.nl[k * n + i], xs, rc2, a);
     }
+}
+
+// Work-item force tables of a tile in LDS.  An angle item keeps the forces on its
+// two outer members (the centre's is minus their sum); a dihedral item keeps the
+// forces on its end members and the two projections pp, qq from which those on
+// the inner members follow.
+template <typename R>
+struct ItemForces {
+    R a[6][DB_CAPA];   // angle: role 0 then role 2, x y z
+    R d[8][DB_CAPD];   // dihedral: role 0, role 3 (x y z), pp, qq
+};
+
+// The angle and dihedral forces of a bead from its tile's work items, in its table
+// order (codes: item | role << 16)
+template <typename R>
+__device__ __forceinline__ void tile_collect(const ItemForces<R>& F, const TileBead& tb, int nAi, int nDi, Acc<R>& a) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= tb.na) continue;
+        const uint32_t code = tb.ac[k];
+        const int it = (int)(code & 0xFFFFu), role = (int)((code >> 16) & 3u);
+        if (it >= nAi) continue;
+        R f[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R f0 = F.a[c][it], f2 = F.a[3 + c][it];
+            f[c] = role == 0 ? f0 : (role == 2 ? f2 : -(f0 + f2));
+        }
+        a.fx += (double)f[0];
+        a.fy += (double)f[1];
+        a.fz += (double)f[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= tb.nd) continue;
+        const uint32_t code = tb.dc[k];
+        const int it = (int)(code & 0xFFFFu), role = (int)((code >> 16) & 3u);
+        if (it >= nDi) continue;
+        const R pp = F.d[6][it], qq = F.d[7][it];
+        R f[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R f0 = F.d[c][it], f3 = F.d[3 + c][it];
+            const R f1 = qq * f3 - (pp + (R)1) * f0, f2 = pp * f0 - (qq + (R)1) * f3;
+            f[c] = role == 0 ? f0 : (role == 3 ? f3 : (role == 1 ? f1 : f2));
+        }
+        a.fx += (double)f[0];
+        a.fy += (double)f[1];
+        a.fz += (double)f[2];
+    }
+}
+
+// The rest of one bead's step once its force is complete: the external force, the
+// Langevin force and the velocity-Verlet update.  Returns |v|^2 after the step.
+template <typename R>
+__device__ __forceinline__ double tile_bead_finish(const Params& P, const Box& X, Bank& B, int i, const double4& xi,
+                                                   double vx, double vy, double vz, const Acc<R>& a,
+                                                   double4* __restrict__ xout, int64_t step, double pref,
+                                                   int* __restrict__ err, double4* __restrict__ xsave,
+                                                   double* __restrict__ vsave) {
+    const int n = P.n;
+    double Fx = a.fx, Fy = a.fy, Fz = a.fz;
     if (P.has_ext) {
         const size_t g = (size_t)meta_gid(xi);
-        a.fx += P.fext[3 * g];
-        a.fy += P.fext[3 * g + 1];
-        a.fz += P.fext[3 * g + 2];
+        Fx += P.fext[3 * g];
+        Fy += P.fext[3 * g + 1];
+        Fz += P.fext[3 * g + 2];
     }
     if (xsave) {   // first step of a block: keep its input state for a re-run
         xsave[i] = xi;
@@ -1414,7 +1688,6 @@ __device__ __forceinline__ double tile_bead_step(const Params& P, const Box& X, 
         vsave[n + i] = vy;
         vsave[2 * n + i] = vz;
     }
-    double Fx = a.fx, Fy = a.fy, Fz = a.fz;
     if (P.gamma != 0.0) {
         uint4 w = rng_draw(X, (uint32_t)(meta_gid(xi) - X.gid_off), 0u, step, RNG_LANGEVIN);
         const double s32 = 1.0 / 4294967296.0;
@@ -1448,9 +1721,13 @@ __device__ __forceinline__ double tile_bead_step(const Params& P, const Box& X, 
 // words are requested first, then the positions of the tile's region are loaded
 // into LDS, and after one barrier every partner position comes from there.  A
 // tile whose region could not be staged reads partners from memory by slot, and a
-// bead whose halo overflows reads its table entries.  Every force is formed with
-// the arithmetic, in the order, of k_step, so the two kernels give the same
-// trajectory bit for bit.
+// bead whose halo overflows reads its table entries.  In a staged tile whose beads
+// hold at most four angles and four dihedrals each (and whose counts fit
+// DB_CAPA / DB_CAPD), every angle and dihedral is evaluated once, by one thread,
+// after the bead's bonds and pairs, and its members add their shares after a
+// second barrier; otherwise each bead evaluates its own terms as k_step does.  The
+// terms are those of k_step; the order in which a bead's force is summed differs
+// (bonds, pairs, then angles and dihedrals), so the trajectories agree to rounding.
 template <typename R>
 __global__ __launch_bounds__(DB_BLOCK) void k_step_tile(const Params* __restrict__ Pp, Bank B, NList NL, Halo H,
                                                         Tiles T, double4* __restrict__ xout, int64_t step,
@@ -1467,7 +1744,13 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step_tile(const Params* __restrict
     const Box& X = P.box;
     __shared__ Coef<R> C;
     __shared__ double rx[DB_RCAP], ry[DB_RCAP], rz[DB_RCAP];
-    __shared__ uint16_t hidx[DB_MAXU][DB_BLOCK];
+    // per-thread halo indices (per-bead bonded terms) or the work items' forces:
+    // a tile uses one or the other
+    __shared__ union {
+        uint16_t hidx[DB_MAXU][DB_BLOCK];
+        ItemForces<R> f;
+    } lu;
+    auto& hidx = lu.hidx;
     load_coef<R>(P, C);
     const int tid = threadIdx.x;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1475,6 +1758,20 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step_tile(const Params* __restrict
     const bool active = i < n;
     const int nreg = T.rcount[tile];
     const bool staged = nreg <= DB_RCAP;
+    // work items of the tile (a staged tile whose beads hold at most four angles and
+    // dihedrals each): requested with the bead's own words
+    const uint32_t ni = staged ? T.nitems[tile] : 0xFFFFFFFFu;
+    const bool items = ni != 0xFFFFFFFFu;
+    const int nAi = items ? (int)(ni & 0xFFFFu) : 0, nDi = items ? (int)(ni >> 16) : 0;
+    constexpr int APT = (DB_CAPA + DB_BLOCK - 1) / DB_BLOCK;
+    uint2 ia[APT], idh = make_uint2(0, 0);
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        ia[q] = make_uint2(0, 0);
+        if (q * DB_BLOCK + tid < nAi) ia[q] = T.itemA[(size_t)tile * DB_CAPA + q * DB_BLOCK + tid];
+    }
+    static_assert(DB_CAPD <= DB_BLOCK, "one dihedral item per thread");
+    if (tid < nDi) idh = T.itemD[(size_t)tile * DB_CAPD + tid];
     TileBead tb;
     double4 xi = make_double4(0, 0, 0, 0);
     double vx = 0, vy = 0, vz = 0;
@@ -1537,18 +1834,63 @@ __global__ __launch_bounds__(DB_BLOCK) void k_step_tile(const Params* __restrict
         const int self = (int)(rc.z & 0xFFFFu);
         xs = make_double4(rx[self], ry[self], rz[self], 0.0);
     }
-    double m2 = 0.0;
+    Acc<R> a;
     if (active) {
-        if (staged && !image)
-            m2 = tile_bead_step<R, true, false>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, vx, vy, vz, tb,
-                                                xout, step, pref, err, xsave, vsave);
+        if (items && !image)
+            tile_bead_forces<R, true, false, true>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, tb, a);
+        else if (items)
+            tile_bead_forces<R, true, true, true>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, tb, a);
+        else if (staged && !image)
+            tile_bead_forces<R, true, false, false>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, tb, a);
         else if (staged)
-            m2 = tile_bead_step<R, true, true>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, vx, vy, vz, tb,
-                                               xout, step, pref, err, xsave, vsave);
+            tile_bead_forces<R, true, true, false>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, tb, a);
         else
-            m2 = tile_bead_step<R, false, true>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, vx, vy, vz, tb,
-                                                xout, step, pref, err, xsave, vsave);
+            tile_bead_forces<R, false, true, false>(P, X, C, B, NL, H, T, rx, ry, rz, hidx, i, xi, xs, tb, a);
     }
+    if (items) {
+        // every angle and dihedral of the tile once, from the stored positions
+        // (differences of images, or with the minimum image in a small box); after
+        // the barrier each member adds its share
+        auto dif = [&](const double* r, int p, int q) {
+            const double d = r[p] - r[q];
+            return image ? near_image(d, X) : d;
+        };
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            const int it = q * DB_BLOCK + tid;
+            if (it >= nAi) continue;
+            const int ra = (int)(ia[q].x & 0x3FFu), rb = (int)((ia[q].x >> 10) & 0x3FFu),
+                      rcn = (int)((ia[q].x >> 20) & 0x3FFu), t = (int)(ia[q].y & (DB_MAXT - 1));
+            R f[3][3];
+            angle_all<R>(C, t, (R)dif(rx, ra, rb), (R)dif(ry, ra, rb), (R)dif(rz, ra, rb), (R)dif(rx, rcn, rb),
+                         (R)dif(ry, rcn, rb), (R)dif(rz, rcn, rb), f);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lu.f.a[c][it] = f[0][c];
+                lu.f.a[3 + c][it] = f[2][c];
+            }
+        }
+        if (tid < nDi) {
+            const int ra = (int)(idh.x & 0x3FFu), rb = (int)((idh.x >> 10) & 0x3FFu),
+                      rcn = (int)((idh.x >> 20) & 0x3FFu), rd = (int)(idh.y & 0x3FFu),
+                      t = (int)((idh.y >> 10) & (DB_MAXT - 1));
+            R f0[3], f3[3], pp, qq;
+            dihedral_ends<R>(C, t, (R)dif(rx, rb, ra), (R)dif(ry, rb, ra), (R)dif(rz, rb, ra), (R)dif(rx, rcn, rb),
+                             (R)dif(ry, rcn, rb), (R)dif(rz, rcn, rb), (R)dif(rx, rd, rcn), (R)dif(ry, rd, rcn),
+                             (R)dif(rz, rd, rcn), f0, f3, pp, qq);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lu.f.d[c][tid] = f0[c];
+                lu.f.d[3 + c][tid] = f3[c];
+            }
+            lu.f.d[6][tid] = pp;
+            lu.f.d[7][tid] = qq;
+        }
+        __syncthreads();
+        if (active) tile_collect<R>(lu.f, tb, nAi, nDi, a);
+    }
+    const double m2 = active ? tile_bead_finish<R>(P, X, B, i, xi, vx, vy, vz, a, xout, step, pref, err, xsave, vsave)
+                             : 0.0;
     // largest speed of the tile: one atomic per workgroup, spread over 64 words
     __shared__ float wmax[DB_BLOCK / 64];
     const double v2 = wave_max(m2);
