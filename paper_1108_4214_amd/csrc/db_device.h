@@ -146,6 +146,36 @@ __device__ __forceinline__ const Box& box_of(const Params& P, int meta) {
     return P.box;
 }
 
+// f(X) with the box of the lane's bead.  In a batch, a wave whose beads all lie in
+// one replica (every wave but those that straddle a boundary between replicas)
+// reads the replica's box with scalar loads into scalar registers, as the
+// single-system path does; the others read it per lane.
+template <bool BATCH, class F>
+__device__ __forceinline__ void with_box(const Params& P, int meta, F&& f) {
+    if constexpr (!BATCH) {
+        f(P.box);
+    } else {
+        const int rep = meta_rep(meta);
+        const int ru = __builtin_amdgcn_readfirstlane(rep);
+        if (__builtin_amdgcn_ballot_w64(rep != ru) == 0) {
+            // word by word through the constant address space: the table is never
+            // written by a kernel, and a uniform load from there is a scalar load
+            using CWord = __attribute__((address_space(4))) const uint32_t;
+            static_assert(sizeof(Box) % 4 == 0, "box of whole words");
+            constexpr int NW = (int)(sizeof(Box) / 4);
+            const CWord* src = (const CWord*)(P.rep) + (size_t)ru * NW;
+            uint32_t w[NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) w[k] = src[k];
+            Box X;
+            __builtin_memcpy(&X, w, sizeof(Box));
+            f(X);
+        } else {
+            f(P.rep[rep]);
+        }
+    }
+}
+
 // temperature of box X at a step: T0 + (T1 - T0) min(step, ramp) / ramp
 __device__ __forceinline__ double box_temperature(const Box& X, int64_t step) {
     if (X.ramp <= 0) return X.T0;

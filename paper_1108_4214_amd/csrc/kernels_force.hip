@@ -315,22 +315,53 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     constexpr int NL_STAGE = WIDE ? 1 : 20;
     __shared__ int stage[NL_STAGE][DB_BLOCK];
     const int tid = threadIdx.x;
-    int cnt = 0;
-    auto visit = [&](int j, int) {
-        if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return;
+    auto excluded = [&](int j) {
+        if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return true;
+        bool ex = false;
         if (depth2 && nb > 0) {
-            bool ex = false;
 #pragma unroll
             for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) ex |= two[k] == j;
-            if (ex) return;
         }
-        if (!WIDE && cnt < NL_STAGE) stage[cnt][tid] = j;
-        else if (cnt < DB_NLCAP) NL.nl[cnt * n + i] = j;
-        ++cnt;
+        return ex;
     };
-    if (WIDE) scan_cells_wide(X, cstart, xs, i, xi, (float)((cut + X.pf_slack) * (cut + X.pf_slack) * 1.0001), visit);
-    else scan_cells(X, cstart, xs, i, xi, X.pf_list2, visit);
-    if (!WIDE) {
+    auto put = [&](int k, int j) {
+        if (!WIDE && k < NL_STAGE) stage[k][tid] = j;
+        else if (k < DB_NLCAP) NL.nl[k * n + i] = j;
+    };
+    auto get = [&](int k) { return (!WIDE && k < NL_STAGE) ? stage[k][tid] : NL.nl[k * n + i]; };
+    int cnt = 0;
+    if (WIDE) {
+        auto visit = [&](int j, int) {
+            if (excluded(j)) return;
+            put(cnt, j);
+            ++cnt;
+        };
+        scan_cells_wide(X, cstart, xs, i, xi, (float)((cut + X.pf_slack) * (cut + X.pf_slack) * 1.0001), visit);
+    } else {
+        // Every candidate within the cutoff is kept first and the exclusions are
+        // applied afterwards, compacting in place in scan order.  (Tested inside
+        // the scan, the exclusion test runs for every candidate some lane of the
+        // wave keeps, which is nearly every candidate.)  A bead with more kept
+        // candidates than the list holds is scanned again with the test inside.
+        int raw = 0;
+        scan_cells(X, cstart, xs, i, xi, X.pf_list2, [&](int j, int) {
+            put(raw, j);
+            ++raw;
+        });
+        if (raw <= DB_NLCAP) {
+            for (int k = 0; k < raw; ++k) {
+                const int j = get(k);
+                if (excluded(j)) continue;
+                put(cnt, j);
+                ++cnt;
+            }
+        } else {
+            scan_cells(X, cstart, xs, i, xi, X.pf_list2, [&](int j, int) {
+                if (excluded(j)) return;
+                put(cnt, j);
+                ++cnt;
+            });
+        }
         const int ns = min(cnt, NL_STAGE);
         for (int k = 0; k < ns; ++k) NL.nl[k * n + i] = stage[k][tid];
     }
@@ -931,97 +962,98 @@ void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H, double4* __
     double m2 = 0.0;   // |v|^2, or the squared displacement from the reference
     if (active) {
         xi = B.x[i];
-        const Box& X = box_of<BATCH>(P, meta_word(xi));
-        const int nu = H.nu[i];
-        // the list's count and first entries are requested ahead of the bonded terms
-        constexpr int PQ = pair_batch<R, PAIR>();
-        int m_pair = 0;
-        int jpre[PQ];
+        with_box<BATCH>(P, meta_word(xi), [&](const Box& X) {
+            const int nu = H.nu[i];
+            // the list's count and first entries are requested ahead of the bonded terms
+            constexpr int PQ = pair_batch<R, PAIR>();
+            int m_pair = 0;
+            int jpre[PQ];
 #pragma unroll
-        for (int q = 0; q < PQ; ++q) jpre[q] = i;
-        if (P.have_pair) {
-            m_pair = NL.cnt[i];
+            for (int q = 0; q < PQ; ++q) jpre[q] = i;
+            if (P.have_pair) {
+                m_pair = NL.cnt[i];
 #pragma unroll
-            for (int q = 0; q < PQ; ++q) jpre[q] = NL.nl[q * n + i];
-        }
-        if (nu <= DB_MAXU) {
-            halo_bonded<R>(P, X, C, B, H, i, xi, nu, a);
-        } else {
-            // more distinct bonded partners than the halo holds: read them per entry
-            bond_terms<R, MODE_STEP>(P, X, C, B, i, xi, B.nb[i], a);
-            angle_terms<R, MODE_STEP>(P, X, C, B, i, B.na[i], a);
-            dihedral_terms<R, MODE_STEP>(P, X, C, B, i, B.nd[i], a);
-        }
-        if constexpr (PAIR == PAIR_DPD) {
-            if (MODE == MODE_STEP && P.dpd_gamma != 0.0) {
-                if (BATCH) dsig = sqrt(2.0 * box_temperature(X, step) * P.dpd_gamma) / sqrt(P.dt);
-                list_pair_dpd<R, true>(P, X, B, NL, i, xi, B.v[i], B.v[n + i], B.v[2 * n + i], step, dsig, m_pair,
-                                       jpre, a);
-            } else {
-                list_pair_dpd<R, false>(P, X, B, NL, i, xi, 0, 0, 0, 0, 0, m_pair, jpre, a);
+                for (int q = 0; q < PQ; ++q) jpre[q] = NL.nl[q * n + i];
             }
-        } else {
-            if (P.have_pair) list_pair_forces<R>(P, X, B, NL, i, xi, m_pair, jpre, a);
-        }
-        if (P.has_ext) {
-            const size_t g = (size_t)meta_gid(xi);
-            a.fx += P.fext[3 * g];
-            a.fy += P.fext[3 * g + 1];
-            a.fz += P.fext[3 * g + 2];
-        }
-        if (MODE == MODE_FORCES) {
-            int g = meta_gid(xi);
-            fout[3 * (size_t)g] = a.fx;
-            fout[3 * (size_t)g + 1] = a.fy;
-            fout[3 * (size_t)g + 2] = a.fz;
-            return;
-        }
-        vx = B.v[i];
-        vy = B.v[n + i];
-        vz = B.v[2 * n + i];
-        if (xsave) {   // first step of a block: keep its input state for a re-run
-            xsave[i] = xi;
-            vsave[i] = vx;
-            vsave[n + i] = vy;
-            vsave[2 * n + i] = vz;
-        }
-        double Fx = a.fx, Fy = a.fy, Fz = a.fz;
-        if (P.gamma != 0.0) {
-            if (BATCH) pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
-            uint4 w = rng_draw(X, (uint32_t)(meta_gid(xi) - X.gid_off), 0u, step, RNG_LANGEVIN);
-            const double s32 = 1.0 / 4294967296.0;
-            double ux = ((double)w.x + 0.5) * s32, uy = ((double)w.y + 0.5) * s32, uz = ((double)w.z + 0.5) * s32;
-            Fx = (Fx - P.gamma * vx) + pref * (ux - 0.5);
-            Fy = (Fy - P.gamma * vy) + pref * (uy - 0.5);
-            Fz = (Fz - P.gamma * vz) + pref * (uz - 0.5);
-        }
-        const double hdt = 0.5 * P.dt;
-        {
-            double hx = vx + hdt * Fx, hy = vy + hdt * Fy, hz = vz + hdt * Fz;
-            vx = hx + hdt * Fx;
-            vy = hy + hdt * Fy;
-            vz = hz + hdt * Fz;
-            double nxp = xi.x + P.dt * vx, nyp = xi.y + P.dt * vy, nzp = xi.z + P.dt * vz;
-            double4 xo;
-            xo.x = wrap1(nxp, X.L);
-            xo.y = wrap1(nyp, X.L);
-            xo.z = wrap1(nzp, X.L);
-            xo.w = xi.w;
-            bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
-            if (bad) atomicOr(err, ERR_NONFINITE);
-            if (PAIR == PAIR_DPD) {
-                const double4 r = xref[i];
-                const double ex = near_image(xo.x - r.x, X), ey = near_image(xo.y - r.y, X),
-                             ez = near_image(xo.z - r.z, X);
-                m2 = (ex * ex + ey * ey) + ez * ez;
+            if (nu <= DB_MAXU) {
+                halo_bonded<R>(P, X, C, B, H, i, xi, nu, a);
             } else {
-                m2 = (vx * vx + vy * vy) + vz * vz;
+                // more distinct bonded partners than the halo holds: read them per entry
+                bond_terms<R, MODE_STEP>(P, X, C, B, i, xi, B.nb[i], a);
+                angle_terms<R, MODE_STEP>(P, X, C, B, i, B.na[i], a);
+                dihedral_terms<R, MODE_STEP>(P, X, C, B, i, B.nd[i], a);
             }
-            xout[i] = xo;
-            vout[i] = vx;
-            vout[n + i] = vy;
-            vout[2 * n + i] = vz;
-        }
+            if constexpr (PAIR == PAIR_DPD) {
+                if (MODE == MODE_STEP && P.dpd_gamma != 0.0) {
+                    if (BATCH) dsig = sqrt(2.0 * box_temperature(X, step) * P.dpd_gamma) / sqrt(P.dt);
+                    list_pair_dpd<R, true>(P, X, B, NL, i, xi, B.v[i], B.v[n + i], B.v[2 * n + i], step, dsig, m_pair,
+                                           jpre, a);
+                } else {
+                    list_pair_dpd<R, false>(P, X, B, NL, i, xi, 0, 0, 0, 0, 0, m_pair, jpre, a);
+                }
+            } else {
+                if (P.have_pair) list_pair_forces<R>(P, X, B, NL, i, xi, m_pair, jpre, a);
+            }
+            if (P.has_ext) {
+                const size_t g = (size_t)meta_gid(xi);
+                a.fx += P.fext[3 * g];
+                a.fy += P.fext[3 * g + 1];
+                a.fz += P.fext[3 * g + 2];
+            }
+            if (MODE == MODE_FORCES) {
+                int g = meta_gid(xi);
+                fout[3 * (size_t)g] = a.fx;
+                fout[3 * (size_t)g + 1] = a.fy;
+                fout[3 * (size_t)g + 2] = a.fz;
+                return;
+            }
+            vx = B.v[i];
+            vy = B.v[n + i];
+            vz = B.v[2 * n + i];
+            if (xsave) {   // first step of a block: keep its input state for a re-run
+                xsave[i] = xi;
+                vsave[i] = vx;
+                vsave[n + i] = vy;
+                vsave[2 * n + i] = vz;
+            }
+            double Fx = a.fx, Fy = a.fy, Fz = a.fz;
+            if (P.gamma != 0.0) {
+                if (BATCH) pref = sqrt(24.0 * P.gamma * box_temperature(X, step) / P.dt);
+                uint4 w = rng_draw(X, (uint32_t)(meta_gid(xi) - X.gid_off), 0u, step, RNG_LANGEVIN);
+                const double s32 = 1.0 / 4294967296.0;
+                double ux = ((double)w.x + 0.5) * s32, uy = ((double)w.y + 0.5) * s32, uz = ((double)w.z + 0.5) * s32;
+                Fx = (Fx - P.gamma * vx) + pref * (ux - 0.5);
+                Fy = (Fy - P.gamma * vy) + pref * (uy - 0.5);
+                Fz = (Fz - P.gamma * vz) + pref * (uz - 0.5);
+            }
+            const double hdt = 0.5 * P.dt;
+            {
+                double hx = vx + hdt * Fx, hy = vy + hdt * Fy, hz = vz + hdt * Fz;
+                vx = hx + hdt * Fx;
+                vy = hy + hdt * Fy;
+                vz = hz + hdt * Fz;
+                double nxp = xi.x + P.dt * vx, nyp = xi.y + P.dt * vy, nzp = xi.z + P.dt * vz;
+                double4 xo;
+                xo.x = wrap1(nxp, X.L);
+                xo.y = wrap1(nyp, X.L);
+                xo.z = wrap1(nzp, X.L);
+                xo.w = xi.w;
+                bool bad = !(xo.x >= 0.0 && xo.x < X.L && xo.y >= 0.0 && xo.y < X.L && xo.z >= 0.0 && xo.z < X.L);
+                if (bad) atomicOr(err, ERR_NONFINITE);
+                if (PAIR == PAIR_DPD) {
+                    const double4 r = xref[i];
+                    const double ex = near_image(xo.x - r.x, X), ey = near_image(xo.y - r.y, X),
+                                 ez = near_image(xo.z - r.z, X);
+                    m2 = (ex * ex + ey * ey) + ez * ez;
+                } else {
+                    m2 = (vx * vx + vy * vy) + vz * vz;
+                }
+                xout[i] = xo;
+                vout[i] = vx;
+                vout[n + i] = vy;
+                vout[2 * n + i] = vz;
+            }
+        });
     }
     if (MODE == MODE_STEP) {
         // largest speed of the workgroup; one atomic per workgroup, spread over
