@@ -226,6 +226,22 @@ int db_get_bonds(db_ctx* ctx, int32_t* ij, int32_t* t_ij, int32_t* t_ji);
 int db_get_angles(db_ctx* ctx, int32_t* abc, int32_t* type);
 int db_get_dihedrals(db_ctx* ctx, int32_t* abcd, int32_t* type);
 int db_get_stats(db_ctx* ctx, db_stats* out);
+/* Checkpoints of a single system.  db_checkpoint_bytes gives the size of the
+ * host buffer; db_checkpoint_save fills it with every device array of the handle
+ * (positions, velocities and topology tables in slot order, the Verlet and cell
+ * lists, the per-bead sweep buffers) and the step scheduler's state (step, list
+ * validity and displacement bound, rebuild interval and count, statistics).  The
+ * caller owns the buffer.  db_checkpoint_load restores one into a handle made by
+ * db_create with the same bead count, box edge, seed and precision and given the
+ * same force field, rules, db_tune and db_tile_shape settings (the buffer holds
+ * state, not configuration); the run then continues bit for bit as the saved run
+ * would have.  Random numbers are keyed by bead ids, step and seed (no generator
+ * state to keep).  EINVAL: a batch handle, a buffer too small, or a checkpoint of
+ * another system, version, layout or tuning; the loading handle is unchanged
+ * then.  Saving needs a current state (ESTATE otherwise). */
+int db_checkpoint_bytes(db_ctx* ctx, size_t* bytes);
+int db_checkpoint_save(db_ctx* ctx, void* host_buf, size_t bytes);
+int db_checkpoint_load(db_ctx* ctx, const void* host_buf, size_t bytes);
 /* current step counter; db_set_step also allows the sweep of that step again */
 int db_set_step(db_ctx* ctx, int64_t step);
 /* tuning knobs of the step scheduler: the neighbour-list skin (list cutoff minus

@@ -36,6 +36,7 @@ EXPORTS = [
     "db_get_stats", "db_set_step", "db_tune", "db_profile", "db_step_kernel_time", "db_autotune",
     "db_batch_create", "db_batch_get_state", "db_track_topology_energy", "db_external_force",
     "db_energy_noalloc", "db_acceptance", "db_tile_shape", "db_tile_stats", "db_graph", "db_get_shape",
+    "db_checkpoint_bytes", "db_checkpoint_save", "db_checkpoint_load",
 ]
 
 STAT_FIELDS = [
@@ -122,6 +123,9 @@ _SIG = {
     "db_batch_create": [C.POINTER(C.c_void_p), _P, _i32, _P],
     "db_batch_get_state": [_P, _i32, _P, _P, _int],
     "db_track_topology_energy": [_P, _int],
+    "db_checkpoint_bytes": [_P, C.POINTER(C.c_size_t)],
+    "db_checkpoint_save": [_P, _P, C.c_size_t],
+    "db_checkpoint_load": [_P, _P, C.c_size_t],
 }
 for _name, _args in _SIG.items():
     _f = getattr(_lib, _name)
@@ -355,6 +359,24 @@ def db_energy_noalloc(ctx):
     e = np.zeros(6)
     _check(ctx, _lib.db_energy_noalloc(ctx, _ptr(e)))
     return e
+
+
+def db_checkpoint_bytes(ctx):
+    v = C.c_size_t()
+    _check(ctx, _lib.db_checkpoint_bytes(ctx, C.byref(v)))
+    return int(v.value)
+
+
+def db_checkpoint_save(ctx):
+    """the handle's checkpoint as a uint8 array"""
+    buf = np.zeros(db_checkpoint_bytes(ctx), dtype=np.uint8)
+    _check(ctx, _lib.db_checkpoint_save(ctx, _ptr(buf), buf.size))
+    return buf
+
+
+def db_checkpoint_load(ctx, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(ctx, _lib.db_checkpoint_load(ctx, _ptr(buf), buf.size))
 
 
 def db_get_state(ctx, x, v):

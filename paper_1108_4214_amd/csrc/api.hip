@@ -1615,6 +1615,181 @@ int db_set_step(db_ctx* c, int64_t step) {
     return DB_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// checkpoints: the whole device arena (state, tables, lists, cells, sweep buffers,
+// in slot order) and the scheduler's host state, so that a run resumed from one
+// continues as the saved run would have, bit for bit
+
+namespace {
+struct CkptHead {
+    char magic[8];
+    int32_t version, n, precision, nrep;
+    uint64_t seed;
+    double L;
+    uint64_t arena_bytes;
+    double skin;
+    int32_t permute_every, tile_mode, brick_edge, cur;
+    int32_t rebuild_interval, ntile, tile_bB, pad0;
+    int64_t step, swept_step, rebuilds, rollbacks, sweeps, patches, rebuild_count;
+    int64_t stat_last[8], stat_cum[8];
+    uint8_t list_valid, tiles_valid, regions_valid, halo_force, halo_sweep, have_topology, ledger, pad1;
+    double list_disp, disp_rate, vmax_est, du_last, du_cum;
+    // the step kernel writes positions (and with DPD velocities) into a second
+    // buffer and the pointers are exchanged: which arena buffer each one names
+    uint64_t off_x[3], off_v[3];   // bank[0], bank[1], next
+};
+const char kCkptMagic[8] = {'D', 'B', 'C', 'K', 'P', 'T', '1', 0};
+const int32_t kCkptVersion = 1;
+}  // namespace
+
+int db_checkpoint_bytes(db_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_EINVAL, "checkpoints are taken of single systems");
+    *bytes = sizeof(CkptHead) + layout(c, false);
+    return DB_OK;
+}
+
+int db_checkpoint_save(db_ctx* c, void* buf, size_t bytes) {
+    if (!c || !buf) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_EINVAL, "checkpoints are taken of single systems");
+    int rc = ready(c);
+    if (rc) return rc;
+    const size_t arena = layout(c, false);
+    if (bytes < sizeof(CkptHead) + arena)
+        return fail(c, DB_EINVAL, "checkpoint needs %zu bytes", sizeof(CkptHead) + arena);
+    CkptHead h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, kCkptMagic, 8);
+    h.version = kCkptVersion;
+    h.n = c->n;
+    h.precision = c->precision;
+    h.nrep = c->nrep;
+    h.seed = c->seed;
+    h.L = c->L;
+    h.arena_bytes = arena;
+    h.skin = c->skin;
+    h.permute_every = c->permute_every;
+    h.tile_mode = c->tile_mode;
+    h.brick_edge = c->brick_edge;
+    h.cur = c->cur;
+    h.rebuild_interval = c->rebuild_interval;
+    h.ntile = c->ntile;
+    h.tile_bB = c->tile_bB;
+    h.step = c->step;
+    h.swept_step = c->swept_step;
+    h.rebuilds = c->rebuilds;
+    h.rollbacks = c->rollbacks;
+    h.sweeps = c->sweeps;
+    h.patches = c->patches;
+    h.rebuild_count = c->rebuild_count;
+    memcpy(h.stat_last, c->stat_last, sizeof h.stat_last);
+    memcpy(h.stat_cum, c->stat_cum, sizeof h.stat_cum);
+    h.list_valid = c->list_valid;
+    h.tiles_valid = c->tiles_valid;
+    h.regions_valid = c->regions_valid;
+    h.halo_force = c->halo_force;
+    h.halo_sweep = c->halo_sweep;
+    h.have_topology = c->have_topology;
+    h.ledger = c->ledger;
+    h.list_disp = c->list_disp;
+    h.disp_rate = c->disp_rate;
+    h.vmax_est = c->vmax_est;
+    h.du_last = c->du_last;
+    h.du_cum = c->du_cum;
+    const double4* xp[3] = {c->bank[0].x, c->bank[1].x, c->xnext};
+    const double* vp[3] = {c->bank[0].v, c->bank[1].v, c->vnext};
+    for (int k = 0; k < 3; ++k) {
+        h.off_x[k] = (uint64_t)((const char*)xp[k] - c->arena);
+        h.off_v[k] = (uint64_t)((const char*)vp[k] - c->arena);
+    }
+    memcpy(buf, &h, sizeof h);
+    HIPCHK(c, hipMemcpyAsync((char*)buf + sizeof h, c->arena, arena, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DB_OK;
+}
+
+int db_checkpoint_load(db_ctx* c, const void* buf, size_t bytes) {
+    if (!c || !buf) return DB_EINVAL;
+    if (c->nrep > 0) return fail(c, DB_EINVAL, "checkpoints are taken of single systems");
+    if (bytes < sizeof(CkptHead)) return fail(c, DB_EINVAL, "checkpoint too short");
+    CkptHead h;
+    memcpy(&h, buf, sizeof h);
+    if (memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion)
+        return fail(c, DB_EINVAL, "not a checkpoint of this library version");
+    if (h.n != c->n || h.precision != c->precision || h.nrep != 0 || h.seed != c->seed || h.L != c->L)
+        return fail(c, DB_EINVAL, "checkpoint of another system (beads, precision, seed or box edge differ)");
+    if (h.skin != c->skin || h.permute_every != c->permute_every || h.tile_mode != c->tile_mode ||
+        h.brick_edge != c->brick_edge)
+        return fail(c, DB_EINVAL, "checkpoint taken with another skin, reorder cadence or step-kernel shape");
+    const size_t arena = layout(c, false);
+    if (h.arena_bytes != arena || bytes < sizeof h + arena)
+        return fail(c, DB_EINVAL, "checkpoint of another memory layout");
+    db_host_ext& X = ext(c);
+    int rc = ensure_memory(c);
+    if (rc) return rc;
+    // the buffers named by the saved pointers: the same three in some order
+    {
+        const char* xb[3] = {(const char*)c->bank[0].x, (const char*)c->bank[1].x, (const char*)c->xnext};
+        const char* vb[3] = {(const char*)c->bank[0].v, (const char*)c->bank[1].v, (const char*)c->vnext};
+        auto same_set = [&](const uint64_t* off, const char* const* bufs) {
+            for (int k = 0; k < 3; ++k) {
+                int hits = 0;
+                for (int q = 0; q < 3; ++q) hits += off[q] == (uint64_t)(bufs[k] - c->arena);
+                if (hits != 1) return false;
+            }
+            return true;
+        };
+        if (!same_set(h.off_x, xb) || !same_set(h.off_v, vb))
+            return fail(c, DB_EINVAL, "checkpoint of another memory layout");
+    }
+    c->params_dirty = true;
+    rc = upload_params(c);   // the grid of this handle's parameters
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->arena, (const char*)buf + sizeof h, arena, hipMemcpyHostToDevice, c->stream));
+    // the parameter block in the arena holds the saving handle's addresses: write ours
+    c->params_dirty = true;
+    rc = upload_params(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->bank[0].x = (double4*)(c->arena + h.off_x[0]);
+    c->bank[1].x = (double4*)(c->arena + h.off_x[1]);
+    c->xnext = (double4*)(c->arena + h.off_x[2]);
+    c->bank[0].v = (double*)(c->arena + h.off_v[0]);
+    c->bank[1].v = (double*)(c->arena + h.off_v[1]);
+    c->vnext = (double*)(c->arena + h.off_v[2]);
+    c->cur = h.cur;
+    c->rebuild_interval = h.rebuild_interval;
+    c->ntile = h.ntile;
+    c->tile_bB = h.tile_bB;
+    c->step = h.step;
+    c->swept_step = h.swept_step;
+    c->rebuilds = h.rebuilds;
+    c->rollbacks = h.rollbacks;
+    c->sweeps = h.sweeps;
+    c->patches = h.patches;
+    c->rebuild_count = h.rebuild_count;
+    memcpy(c->stat_last, h.stat_last, sizeof h.stat_last);
+    memcpy(c->stat_cum, h.stat_cum, sizeof h.stat_cum);
+    c->list_valid = h.list_valid;
+    c->tiles_valid = h.tiles_valid;
+    c->regions_valid = h.regions_valid;
+    c->halo_force = h.halo_force;
+    c->halo_sweep = h.halo_sweep;
+    c->have_state = true;
+    c->have_topology = h.have_topology;
+    c->ledger = h.ledger;
+    c->list_disp = h.list_disp;
+    c->disp_rate = h.disp_rate;
+    c->vmax_est = h.vmax_est;
+    c->du_last = h.du_last;
+    c->du_cum = h.du_cum;
+    X.dev_valid = true;
+    X.host_valid = false;
+    X.dev_error = 0;
+    X.pin->err = 0;
+    return DB_OK;
+}
+
 int db_graph(db_ctx* c, int enable) {
     if (!c || (enable != 0 && enable != 1)) return DB_EINVAL;
     c->use_graph = enable == 1;

@@ -192,9 +192,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
     return (bid & 7) * per + (bid >> 3);   // XCD (bid % 8) owns tiles [x*per, (x+1)*per)
 }
 
+// cell coordinate of x in [0, nc): every input, NaN and infinities included, lands
+// in range without an out-of-range conversion (a non-finite position is reported
+// by the step kernel after its block; the cell build of the next block may read it
+// before the host stops)
 __device__ __forceinline__ int cell_coord(double x, double scale, int nc) {
-    int c = (int)(x * scale);
-    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+    const double t = x * scale;
+    return t >= 0.0 ? (t < (double)nc ? (int)t : nc - 1) : 0;
 }
 
 __device__ __forceinline__ int wrap_cell(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
