@@ -110,12 +110,12 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
     }
     int cell_no = 0;
     for (int oz = 0; oz < X.noff; ++oz) {
-        const int zz = wrap_cell(cz + X.off[oz], nc);
+        const int zz = wrap_cell(cz + box_off(X, oz), nc);
         for (int oy = 0; oy < X.noff; ++oy) {
-            const int row = (zz * nc + wrap_cell(cy + X.off[oy], nc)) * nc;
+            const int row = (zz * nc + wrap_cell(cy + box_off(X, oy), nc)) * nc;
             for (int ox = 0; ox < X.noff; ++ox) {
                 if (PARTS > 1 && cell_no++ % PARTS != part) continue;
-                const int c = row + wrap_cell(cx + X.off[ox], nc);
+                const int c = row + wrap_cell(cx + box_off(X, ox), nc);
                 const int s0 = cstart[c], s1 = cstart[c + 1];
                 for (int p = s0; p < s1; ++p) {
                     const float4 e = xs[p];
@@ -129,6 +129,77 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
                 }
             }
         }
+    }
+}
+
+// The candidates of scan_cells (grids of three or more cells per edge only), each
+// passed as f(j, hit) with hit = (j != i and float r2 < cut2), in scan_cells'
+// order.  f runs for every candidate, so a visitor without branches (one that
+// writes every candidate and advances its count by hit) keeps the lanes of a wave
+// together; the x-range of a row and its wrapped part are separate loops, so the
+// common range needs no per-candidate choice of image.
+template <class F>
+__device__ __forceinline__ void scan_cells_all(const Box& X, const int* __restrict__ cstart,
+                                               const float4* __restrict__ xs, int i, const double4& xi, float cut2,
+                                               F&& f) {
+    const int nc = X.nc;
+    const int cx = cell_coord(xi.x, X.cell_scale, nc);
+    const int cy = cell_coord(xi.y, X.cell_scale, nc);
+    const int cz = cell_coord(xi.z, X.cell_scale, nc);
+    const float Lf = (float)X.L;
+    const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
+    cstart += X.cell_off;
+    auto shift = [&](int c) { return c < 0 ? -Lf : (c >= nc ? Lf : 0.0f); };
+    int a0, a1, b0 = 0, b1 = 0;
+    float qx1 = px;
+    if (cx >= 1 && cx <= nc - 2) {
+        a0 = cx - 1;
+        a1 = cx + 2;
+    } else if (cx == 0) {
+        a0 = 0;
+        a1 = 2;
+        b0 = nc - 1;
+        b1 = nc;
+        qx1 = px + Lf;
+    } else {
+        a0 = nc - 2;
+        a1 = nc;
+        b0 = 0;
+        b1 = 1;
+        qx1 = px - Lf;
+    }
+    const bool wrapx = b1 > b0;
+    auto row_of = [&](int r) { return (wrap_cell(cz + r / 3 - 1, nc) * nc + wrap_cell(cy + r % 3 - 1, nc)) * nc; };
+    // one run [s, e) of consecutive entries seen from (qx, qy, qz)
+    auto run = [&](int s, int e, float qx, float qy, float qz) {
+        for (int p = s; p < e; p += DB_SCAN_W) {
+            float4 c[DB_SCAN_W];
+#pragma unroll
+            for (int q = 0; q < DB_SCAN_W; ++q) c[q] = xs[min(p + q, e - 1)];
+#pragma unroll
+            for (int q = 0; q < DB_SCAN_W; ++q) {
+                const int j = xs_slot(__float_as_int(c[q].w));
+                const float dx = c[q].x - qx, dy = c[q].y - qy, dz = c[q].z - qz;
+                const float r2 = (dx * dx + dy * dy) + dz * dz;
+                f(j, (p + q < e) & (j != i) & (r2 < cut2));
+            }
+        }
+    };
+    int row = row_of(0);
+    int s0 = cstart[row + a0], s1 = cstart[row + a1];
+    int t0 = wrapx ? cstart[row + b0] : 0, t1 = wrapx ? cstart[row + b1] : 0;
+    for (int r = 0; r < 9; ++r) {
+        const float qz = pz - shift(cz + r / 3 - 1), qy = py - shift(cy + r % 3 - 1);
+        const int c0 = s0, c1 = s1, d0 = t0, d1 = t1;
+        if (r + 1 < 9) {   // the next row's bounds are requested before this row is scanned
+            row = row_of(r + 1);
+            s0 = cstart[row + a0];
+            s1 = cstart[row + a1];
+            t0 = wrapx ? cstart[row + b0] : 0;
+            t1 = wrapx ? cstart[row + b1] : 0;
+        }
+        run(c0, c1, px, qy, qz);
+        run(d0, d1, qx1, qy, qz);
     }
 }
 

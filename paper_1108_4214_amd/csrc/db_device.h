@@ -201,6 +201,10 @@ __device__ __forceinline__ int cell_coord(double x, double scale, int nc) {
     return t >= 0.0 ? (t < (double)nc ? (int)t : nc - 1) : 0;
 }
 
+// neighbour offset k < 3 of box X by selects (an indexed read would place a box
+// held in registers in scratch memory)
+__device__ __forceinline__ int box_off(const Box& X, int k) { return k == 0 ? X.off[0] : (k == 1 ? X.off[1] : X.off[2]); }
+
 __device__ __forceinline__ int wrap_cell(int c, int nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
 
 // position update with the periodic wrap into [0, L)

@@ -193,9 +193,9 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
     const bool rowmerge = (X.noff == 3) && cx >= 1 && cx <= nc - 2;
     cstart += X.cell_off;
     for (int oz = 0; oz < X.noff; ++oz) {
-        int zz = wrap_cell(cz + X.off[oz], nc);
+        int zz = wrap_cell(cz + box_off(X, oz), nc);
         for (int oy = 0; oy < X.noff; ++oy) {
-            int yy = wrap_cell(cy + X.off[oy], nc);
+            int yy = wrap_cell(cy + box_off(X, oy), nc);
             int row = (zz * nc + yy) * nc;
             // the three cells of one x-row are contiguous in the list unless the row wraps
             int nseg = rowmerge ? 1 : X.noff;
@@ -205,7 +205,7 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
                     s0 = cstart[row + cx - 1];
                     s1 = cstart[row + cx + 2];
                 } else {
-                    int c = row + wrap_cell(cx + X.off[ox], nc);
+                    int c = row + wrap_cell(cx + box_off(X, ox), nc);
                     s0 = cstart[c];
                     s1 = cstart[c + 1];
                 }
@@ -257,6 +257,10 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
                                                           const int* __restrict__ list_n, double cut) {
     const Params& P = *Pp;
     const int n = P.n;
+    // list rows staged in LDS, plus (full build) one row that takes the writes of
+    // the candidates that are not kept
+    constexpr int NL_STAGE = WIDE ? 1 : 24;
+    __shared__ int stage[NL_STAGE + (WIDE ? 0 : 1)][DB_BLOCK];
     int i;
     if (WIDE) {
         const int nl = *list_n;
@@ -282,7 +286,6 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     const int p1 = nb > 1 ? pr[1] : -1;
     const int p2 = nb > 2 ? pr[2] : -1;
     const int p3 = nb > 3 ? pr[3] : -1;
-    const Box& X = box_of<BATCH>(P, meta_word(xi));
     // the beads two bonds away (partners of partners), gathered once per bead, so
     // that testing a candidate compares registers instead of re-reading the
     // partners' tables; -1 marks an empty entry
@@ -312,8 +315,6 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     // covers consecutive beads of one row; entries beyond go straight to memory.
     // (Written as they are found, the lanes of a wave store into rows that differ
     // by their counts, and each store scatters over as many rows.)
-    constexpr int NL_STAGE = WIDE ? 1 : 20;
-    __shared__ int stage[NL_STAGE][DB_BLOCK];
     const int tid = threadIdx.x;
     auto excluded = [&](int j) {
         if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return true;
@@ -328,8 +329,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         if (!WIDE && k < NL_STAGE) stage[k][tid] = j;
         else if (k < DB_NLCAP) NL.nl[k * n + i] = j;
     };
-    auto get = [&](int k) { return (!WIDE && k < NL_STAGE) ? stage[k][tid] : NL.nl[k * n + i]; };
     int cnt = 0;
+    const Box& X = box_of<BATCH>(P, meta_word(xi));
     if (WIDE) {
         auto visit = [&](int j, int) {
             if (excluded(j)) return;
@@ -338,21 +339,28 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         };
         scan_cells_wide(X, cstart, xs, i, xi, (float)((cut + X.pf_slack) * (cut + X.pf_slack) * 1.0001), visit);
     } else {
-        // Every candidate within the cutoff is kept first and the exclusions are
-        // applied afterwards, compacting in place in scan order.  (Tested inside
-        // the scan, the exclusion test runs for every candidate some lane of the
-        // wave keeps, which is nearly every candidate.)  A bead with more kept
-        // candidates than the list holds is scanned again with the test inside.
+        // Every candidate within the cutoff is kept first, in the LDS rows, and the
+        // exclusions are applied afterwards, compacting in place in scan order.
+        // The scan writes every candidate (those not kept into the extra row) and
+        // advances the count by the test, with no branch per candidate; tested
+        // inside the scan, the exclusion test and the store ran for every
+        // candidate some lane of the wave kept, which is nearly every candidate.
+        // A bead with more kept candidates than the LDS rows hold, or a grid of
+        // fewer than three cells per edge, is scanned with the test inside.
         int raw = 0;
-        scan_cells(X, cstart, xs, i, xi, X.pf_list2, [&](int j, int) {
-            put(raw, j);
-            ++raw;
-        });
-        if (raw <= DB_NLCAP) {
+        if (X.noff == 3) {
+            scan_cells_all(X, cstart, xs, i, xi, X.pf_list2, [&](int j, bool hit) {
+                stage[hit ? min(raw, NL_STAGE) : NL_STAGE][tid] = j;
+                raw += hit ? 1 : 0;
+            });
+        } else {
+            raw = NL_STAGE + 1;
+        }
+        if (raw <= NL_STAGE) {
             for (int k = 0; k < raw; ++k) {
-                const int j = get(k);
+                const int j = stage[k][tid];
                 if (excluded(j)) continue;
-                put(cnt, j);
+                stage[cnt][tid] = j;
                 ++cnt;
             }
         } else {
@@ -962,7 +970,7 @@ void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H, double4* __
     double m2 = 0.0;   // |v|^2, or the squared displacement from the reference
     if (active) {
         xi = B.x[i];
-        with_box<BATCH>(P, meta_word(xi), [&](const Box& X) {
+        with_box<BATCH>(P, meta_word(xi), [&](const Box& X) __attribute__((always_inline)) {
             const int nu = H.nu[i];
             // the list's count and first entries are requested ahead of the bonded terms
             constexpr int PQ = pair_batch<R, PAIR>();
