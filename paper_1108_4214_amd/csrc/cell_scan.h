@@ -29,14 +29,20 @@ __device__ __forceinline__ float fmin_image(float d, float L, float hL) {
 // four entries at a time.  Smaller grids visit every cell once and take the
 // per-candidate minimum image.  The visitor has a single call site per grid
 // case, which keeps it inlined once.
-// PARTS > 1 splits one bead's scan over PARTS threads: the thread with the given
-// part takes the rows (or, on small grids, the cells) whose index is part modulo
-// PARTS; together the threads visit every candidate once.
+// PARTS > 1 splits one bead's scan over PARTS threads: on grids of three or more
+// cells per edge every thread walks all nine rows and takes the entries of each
+// run whose place in the run is part modulo PARTS (neighbouring threads read
+// neighbouring entries, and the shares differ by at most one entry per row); on
+// small grids the thread takes the cells whose index is part modulo PARTS.
+// Together the threads visit every candidate once.
 template <int PARTS = 1, class F>
 __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__ cstart,
                                            const float4* __restrict__ xs, int i, const double4& xi, float cut2,
                                            F&& f, int part = 0) {
-    static_assert(PARTS >= 1 && PARTS <= 9, "at most one thread per row");
+    static_assert(PARTS >= 1 && PARTS <= 64, "a bead's threads lie within a wavefront");
+    // entries requested together per run: a thread of a split scan takes a few of
+    // each run, so fewer at a time
+    constexpr int SW = PARTS == 1 ? DB_SCAN_W : 2;
     const int nc = X.nc;
     const int cx = cell_coord(xi.x, X.cell_scale, nc);
     const int cy = cell_coord(xi.y, X.cell_scale, nc);
@@ -72,36 +78,36 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
         auto row_of = [&](int r) {
             return (wrap_cell(cz + r / 3 - 1, nc) * nc + wrap_cell(cy + r % 3 - 1, nc)) * nc;
         };
-        const int r0 = PARTS == 1 ? 0 : part;
-        int row = row_of(r0);
+        int row = row_of(0);
         int s0 = cstart[row + a0], s1 = cstart[row + a1];
         int t0 = wrapx ? cstart[row + b0] : 0, t1 = wrapx ? cstart[row + b1] : 0;
-        for (int r = r0; r < 9; r += PARTS) {
+        for (int r = 0; r < 9; ++r) {
             const float qz = pz - shift(cz + r / 3 - 1), qy = py - shift(cy + r % 3 - 1);
             const int c0 = s0, d0 = t0;
             const int len0 = s1 - s0, len = len0 + (t1 - t0);
-            if (r + PARTS < 9) {
-                row = row_of(r + PARTS);
+            if (r + 1 < 9) {
+                row = row_of(r + 1);
                 s0 = cstart[row + a0];
                 s1 = cstart[row + a1];
                 t0 = wrapx ? cstart[row + b0] : 0;
                 t1 = wrapx ? cstart[row + b1] : 0;
             }
-            for (int p = 0; p < len; p += DB_SCAN_W) {
-                float4 e[DB_SCAN_W];
+            for (int p = PARTS == 1 ? 0 : part; p < len; p += SW * PARTS) {
+                float4 e[SW];
 #pragma unroll
-                for (int q = 0; q < DB_SCAN_W; ++q) {
-                    const int k = min(p + q, len - 1);
+                for (int q = 0; q < SW; ++q) {
+                    const int k = min(p + q * PARTS, len - 1);
                     e[q] = xs[k < len0 ? c0 + k : d0 + (k - len0)];
                 }
 #pragma unroll
-                for (int q = 0; q < DB_SCAN_W; ++q) {
+                for (int q = 0; q < SW; ++q) {
                     // one branch per candidate: range, self and distance folded into one predicate
+                    const int k = p + q * PARTS;
                     const int w = __float_as_int(e[q].w);
                     const int j = xs_slot(w);
-                    const float dx = e[q].x - (p + q < len0 ? px : qx1), dy = e[q].y - qy, dz = e[q].z - qz;
+                    const float dx = e[q].x - (k < len0 ? px : qx1), dy = e[q].y - qy, dz = e[q].z - qz;
                     const float r2 = (dx * dx + dy * dy) + dz * dz;
-                    const bool hit = (p + q < len) & (j != i) & (r2 < cut2);
+                    const bool hit = (k < len) & (j != i) & (r2 < cut2);
                     if (hit) f(j, w);
                 }
             }

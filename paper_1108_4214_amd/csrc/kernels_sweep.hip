@@ -168,10 +168,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
 // list longer than the grid's share is covered too.
 constexpr int CREATE_LANES = 8;
 
+// candidates a thread queues before examining them (more are examined at once)
+constexpr int CREATE_QUEUE = 8;
+
 template <bool BATCH>
 __device__ __forceinline__ void nominate_create_one(const Params& P, const int n, const Bank& B,
                                                     const int* __restrict__ cstart, const float4* __restrict__ xs,
-                                                    const SweepBuf& S, const int i, const int lane) {
+                                                    const SweepBuf& S, const int i, const int lane,
+                                                    int (*queue)[DB_BLOCK]) {
     const double4 xi = B.x[i];
     const int mi = meta_word(xi);
     const Box& X = box_of<BATCH>(P, mi);
@@ -194,8 +198,11 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
 #pragma unroll
             for (int b = 0; b < DB_MAXB; ++b) two[a * DB_MAXB + b] = b < nq ? B.bp[b * n + q] : -1;
         }
-        auto visit = [&](int j, int w) {
-            if (!xs_reactive(w) || !((partner_types >> xs_type(w)) & 1u)) return;
+        // A candidate of a wanted type is queued and examined after the scan: taken
+        // as found, the examination ran for every candidate any lane of the wave
+        // kept, with the other lanes idle.  The nominee, the least (r^2, id), does
+        // not depend on the order of the examinations.
+        auto examine = [&](int j) {
             const double4 xj = B.x[j];
             const int mj = meta_word(xj);
             double dx, dy, dz;
@@ -254,8 +261,20 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
                 best_bt = bti;
             }
         };
+        const int tid = threadIdx.x;
+        int nq = 0;
+        auto visit = [&](int j, int w) {
+            if (!xs_reactive(w) || !((partner_types >> xs_type(w)) & 1u)) return;
+            if (nq == CREATE_QUEUE) {   // full: examine the queue
+                for (int k = 0; k < CREATE_QUEUE; ++k) examine(queue[k][tid]);
+                nq = 0;
+            }
+            queue[nq][tid] = j;
+            ++nq;
+        };
         if (X.wide_create) scan_cells_wide<CREATE_LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
         else scan_cells<CREATE_LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
+        for (int k = 0; k < nq; ++k) examine(queue[k][tid]);
     }
     // the group's least (r^2, id), exchanged within the aligned group of lanes
 #pragma unroll
@@ -289,12 +308,13 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
     const int n = P.n;
     const int nl = S.aoff[n];
     const int ntile = (int)(((long long)nl * CREATE_LANES + DB_BLOCK - 1) / DB_BLOCK);
+    __shared__ int queue[CREATE_QUEUE][DB_BLOCK];   // a column per thread
     for (int tb = blockIdx.x; tb < ntile; tb += gridDim.x) {
         const long long pos = (long long)xcd_tile(tb, ntile) * DB_BLOCK + threadIdx.x;
         const int t = (int)(pos / CREATE_LANES);
         const int lane = (int)(pos % CREATE_LANES);
         // the lanes of a group share t: they take this branch together
-        if (t < nl) nominate_create_one<BATCH>(P, n, B, cstart, xs, S, S.act[t], lane);
+        if (t < nl) nominate_create_one<BATCH>(P, n, B, cstart, xs, S, S.act[t], lane, queue);
     }
 }
 
