@@ -212,8 +212,12 @@ __device__ __forceinline__ void scan_cells_all(const Box& X, const int* __restri
 // f(j, w) for every slot j != i with float r2 < cut2 in the 5 x 5 x 5 cells
 // around xi: a reach of two cell edges, for lists redone with a cutoff beyond one
 // edge.  Needs at least five cells per edge (no cell is visited twice).  Each
-// candidate takes the minimum image; this serves only the few beads whose lists
-// are redone after a sweep.  PARTS and part split the 25 rows as in scan_cells.
+// candidate takes the minimum image; this serves only the beads whose lists are
+// redone after a sweep.  The outer layer of cells on a side is visited only when
+// the bead lies within the cutoff of it (for a cutoff just beyond one edge, most
+// beads need the inner 3 x 3 x 3 cells alone), and the x-cells of a row are read
+// as one run unless the row wraps.  PARTS and part split the rows by their index
+// modulo PARTS.
 template <int PARTS = 1, class F>
 __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, const float4* __restrict__ xs,
                                 int i, const double4& xi, float cut2, F&& f, int part = 0) {
@@ -224,14 +228,23 @@ __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, co
     const float Lf = (float)X.L, hLf = (float)X.hL;
     const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
     cstart += X.cell_off;
-    for (int oz = -2; oz <= 2; ++oz) {
+    // the outer layer on a side: needed when the bead is nearer than the reach
+    // (the prefilter's radius, widened for rounding) to that layer's inner face
+    const double edge = X.L / (double)nc;
+    const double reach = sqrt((double)cut2) * (1.0 + 1e-6) + 1e-9 * X.L;
+    auto lo_of = [&](double x, int c) { return (x * X.cell_scale - c + 1.0) * edge < reach ? -2 : -1; };
+    auto hi_of = [&](double x, int c) { return (2.0 - (x * X.cell_scale - c)) * edge < reach ? 2 : 1; };
+    const int lox = lo_of(xi.x, cx), hix = hi_of(xi.x, cx);
+    const int loy = lo_of(xi.y, cy), hiy = hi_of(xi.y, cy);
+    const int loz = lo_of(xi.z, cz), hiz = hi_of(xi.z, cz);
+    const bool xrun = cx + lox >= 0 && cx + hix < nc;   // the row's x-cells are contiguous
+    int rowno = 0;
+    for (int oz = loz; oz <= hiz; ++oz) {
         const int zz = wrap_cell(cz + oz, nc);
-        for (int oy = -2; oy <= 2; ++oy) {
-            if (PARTS > 1 && ((oz + 2) * 5 + (oy + 2)) % PARTS != part) continue;
+        for (int oy = loy; oy <= hiy; ++oy) {
+            if (PARTS > 1 && rowno++ % PARTS != part) continue;
             const int row = (zz * nc + wrap_cell(cy + oy, nc)) * nc;
-            for (int ox = -2; ox <= 2; ++ox) {
-                const int c = row + wrap_cell(cx + ox, nc);
-                const int s0 = cstart[c], s1 = cstart[c + 1];
+            auto run = [&](int s0, int s1) {
                 for (int p = s0; p < s1; ++p) {
                     const float4 e = xs[p];
                     const int w = __float_as_int(e.w);
@@ -241,6 +254,14 @@ __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, co
                     const float dz = fmin_image(e.z - pz, Lf, hLf);
                     const float r2 = (dx * dx + dy * dy) + dz * dz;
                     if ((j != i) & (r2 < cut2)) f(j, w);
+                }
+            };
+            if (xrun) {
+                run(cstart[row + cx + lox], cstart[row + cx + hix + 1]);
+            } else {
+                for (int ox = lox; ox <= hix; ++ox) {
+                    const int c = row + wrap_cell(cx + ox, nc);
+                    run(cstart[c], cstart[c + 1]);
                 }
             }
         }

@@ -333,11 +333,19 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
     double best_r2 = 0.0;
     int rm = 0;
     unsigned long long killed_here = 0;
+    // the bead's table with all rows requested at once, then its partners'
+    // positions, all in flight together
+    const Tab Ti = load_tab_all(B, n, i);
+    const bool scan_bonds = meta_reactive(mi) && (P.has_kill || P.has_break_class);
+    double4 xp[DB_MAXB];
+#pragma unroll
+    for (int k = 0; k < DB_MAXB; ++k)
+        if (scan_bonds && k < Ti.n) xp[k] = B.x[Ti.p(k)];
     {
         // creation: flag the bead for the creation scan's list; its nomination starts empty
         const int ti = meta_type(mi);
         bool can = meta_reactive(mi) && ((P.create_types >> ti) & 1u) && P.rmax2_create > 0.0;
-        if (can) can = create_admits(P, ti, load_tab(B, n, i));
+        if (can) can = create_admits(P, ti, Ti);
         S.act[i] = can ? 1 : 0;
         S.chg[i] = 0;
         S.tchg[i] = 0;
@@ -347,12 +355,13 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         S.ruleC[i] = -1;
         S.btC[i] = 0;
     }
-    if (meta_reactive(mi) && (P.has_kill || P.has_break_class)) {
-        Tab Ti = load_tab(B, n, i);
+    if (scan_bonds) {
         int ti = meta_type(mi);
-        for (int k = 0; k < Ti.n; ++k) {
+#pragma unroll
+        for (int k = 0; k < DB_MAXB; ++k) {
+            if (k >= Ti.n) continue;
             int j = Ti.p(k), t = Ti.t(k);
-            double4 xj = B.x[j];
+            const double4 xj = xp[k];
             int mj = meta_word(xj);
             if (!meta_reactive(mj)) continue;
             double dx, dy, dz;
