@@ -161,17 +161,22 @@ __global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
     if (S.aoff[i + 1] > o) S.act[o] = i;
 }
 
-// CREATE_LANES threads per listed bead, each scanning a share of the cell rows;
-// the group's nominee is the least (r^2, id) of its members' nominees, which is
-// what one thread scanning every row in any order would find.  The listed range
-// is split per XCD; the workgroups step over the tiles of the list, so that a
-// list longer than the grid's share is covered too.
-constexpr int CREATE_LANES = 8;
+// LANES threads per listed bead, each scanning a share of every cell run; the
+// group's nominee is the least (r^2, id) of its members' nominees, which is what
+// one thread scanning every run in any order would find.  The listed range is
+// split per XCD; the workgroups step over the tiles of the list, so that a list
+// longer than the grid's share is covered too.  The kernel picks LANES from the
+// list's length: a long list (every base of a melted system) fills the GPU with
+// two threads per bead and gains from their shorter per-row overhead, a short one
+// (a few melted bases among hybridized duplexes) needs sixteen to fill it at all.
+__device__ __forceinline__ int create_lanes_for(int nl) {
+    return nl >= (1 << 19) ? 2 : (nl >= (1 << 18) ? 4 : (nl >= (1 << 17) ? 8 : 16));
+}
 
 // candidates a thread queues before examining them (more are examined at once)
 constexpr int CREATE_QUEUE = 8;
 
-template <bool BATCH>
+template <bool BATCH, int LANES>
 __device__ __forceinline__ void nominate_create_one(const Params& P, const int n, const Bank& B,
                                                     const int* __restrict__ cstart, const float4* __restrict__ xs,
                                                     const SweepBuf& S, const int i, const int lane,
@@ -272,13 +277,13 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
             queue[nq][tid] = j;
             ++nq;
         };
-        if (X.wide_create) scan_cells_wide<CREATE_LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
-        else scan_cells<CREATE_LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
+        if (X.wide_create) scan_cells_wide<LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
+        else scan_cells<LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
         for (int k = 0; k < nq; ++k) examine(queue[k][tid]);
     }
     // the group's least (r^2, id), exchanged within the aligned group of lanes
 #pragma unroll
-    for (int o = 1; o < CREATE_LANES; o <<= 1) {
+    for (int o = 1; o < LANES; o <<= 1) {
         const double r2o = __shfl_xor(best_r2, o, 64);
         const int go = __shfl_xor(best_g, o, 64);
         const int jo = __shfl_xor(best, o, 64);
@@ -299,22 +304,33 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
     }
 }
 
+template <bool BATCH, int LANES>
+__device__ __forceinline__ void nominate_create_all(const Params& P, const Bank& B, const int* __restrict__ cstart,
+                                                    const float4* __restrict__ xs, const SweepBuf& S, int nl,
+                                                    int (*queue)[DB_BLOCK]) {
+    static_assert(64 % LANES == 0 && DB_BLOCK % 64 == 0, "groups lie within a wavefront");
+    const int ntile = (int)(((long long)nl * LANES + DB_BLOCK - 1) / DB_BLOCK);
+    for (int tb = blockIdx.x; tb < ntile; tb += gridDim.x) {
+        const long long pos = (long long)xcd_tile(tb, ntile) * DB_BLOCK + threadIdx.x;
+        const int t = (int)(pos / LANES);
+        const int lane = (int)(pos % LANES);
+        // the lanes of a group share t: they take this branch together
+        if (t < nl) nominate_create_one<BATCH, LANES>(P, P.n, B, cstart, xs, S, S.act[t], lane, queue);
+    }
+}
+
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __restrict__ Pp, Bank B,
                                                               const int* __restrict__ cstart,
                                                               const float4* __restrict__ xs, SweepBuf S) {
-    static_assert(64 % CREATE_LANES == 0 && DB_BLOCK % 64 == 0, "groups lie within a wavefront");
     const Params& P = *Pp;
-    const int n = P.n;
-    const int nl = S.aoff[n];
-    const int ntile = (int)(((long long)nl * CREATE_LANES + DB_BLOCK - 1) / DB_BLOCK);
+    const int nl = S.aoff[P.n];
     __shared__ int queue[CREATE_QUEUE][DB_BLOCK];   // a column per thread
-    for (int tb = blockIdx.x; tb < ntile; tb += gridDim.x) {
-        const long long pos = (long long)xcd_tile(tb, ntile) * DB_BLOCK + threadIdx.x;
-        const int t = (int)(pos / CREATE_LANES);
-        const int lane = (int)(pos % CREATE_LANES);
-        // the lanes of a group share t: they take this branch together
-        if (t < nl) nominate_create_one<BATCH>(P, n, B, cstart, xs, S, S.act[t], lane, queue);
+    switch (create_lanes_for(nl)) {   // uniform over the grid
+        case 2: nominate_create_all<BATCH, 2>(P, B, cstart, xs, S, nl, queue); break;
+        case 4: nominate_create_all<BATCH, 4>(P, B, cstart, xs, S, nl, queue); break;
+        case 8: nominate_create_all<BATCH, 8>(P, B, cstart, xs, S, nl, queue); break;
+        default: nominate_create_all<BATCH, 16>(P, B, cstart, xs, S, nl, queue); break;
     }
 }
 
