@@ -433,7 +433,10 @@ def main():
                 "c5": lambda: run_c5(args.steps, args.warmup),
                 "small": lambda: run_small(max(200, args.steps), min(args.warmup, 50)),
                 "batch": lambda: run_batch(max(100, args.steps // 4), min(args.warmup, 50))}
-        print(json.dumps({"leg": args.leg, **legs[args.leg]()}), flush=True)
+        out = legs[args.leg]()
+        if args.copy_probe:
+            copy_probe()
+        print(json.dumps({"leg": args.leg, **out}), flush=True)
         return
     w = synth.c3()
     every = w.rules.every
