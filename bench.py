@@ -42,8 +42,8 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """bytes per launch from the counters, or None if absent or taken on other sources"""
+def recorded_counters():
+    """the counter record of the step kernel (key -> text), or None if absent or taken on other sources"""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -54,7 +54,27 @@ def recorded_traffic():
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return kv
+
+
+def recorded_traffic():
+    """bytes per launch from the counters, or None if absent or taken on other sources"""
+    kv = recorded_counters()
+    return float(kv["traffic_bytes_per_launch"]) if kv else None
+
+
+# VALU issue of the chip: 256 CUs x 4 SIMDs, one wavefront instruction of 64 lanes per
+# 4 cycles on a 16-lane SIMD, at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4.0   # wavefront instructions per second
+
+
+def valu_issue_frac(launch_us):
+    """share of the chip's VALU issue the step kernel uses: its VALU instruction count
+    per launch (SQ_INSTS_VALU, recorded with the traffic) over the live launch time"""
+    kv = recorded_counters()
+    if not kv or "valu_insts_per_launch" not in kv or not launch_us > 0:
+        return None
+    return float(kv["valu_insts_per_launch"]) / (launch_us * 1e-6) / VALU_ISSUE_PEAK
 
 
 def copy_probe():
@@ -471,7 +491,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": tb,
                      "kernel": "k_step<float> (fused pair + bonded + Langevin + velocity Verlet)",
                      "bytes_per_bead_step": kernel_bytes, "beads_per_launch": n,
-                     "launch_us": mixed["step_kernel_us"], "launches_timed": mixed["step_kernel_launches"]},
+                     "launch_us": mixed["step_kernel_us"], "launches_timed": mixed["step_kernel_launches"],
+                     # the kernel is bound by VALU issue, not HBM: its share of the chip's issue rate
+                     "valu_issue_frac": valu_issue_frac(mixed["step_kernel_us"])},
         "path_roofline_frac": step_bytes * mixed["bead_steps_per_s"] / (HBM_PEAK_GBS * 1e9),
         "fp64": {"value": fp64["bead_steps_per_s"], "ms_per_step": fp64["ms_per_step"],
                  "step_kernel_us": fp64["step_kernel_us"],
