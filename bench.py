@@ -191,7 +191,7 @@ def run_batch(steps, warmup, precision=1):
         out[label] = {"value": ntot * steps / t, "ms_per_step": 1e3 * t / steps}
         bg.close()
     bt = pk.Batch(reps)
-    skin, perm = pk.db_autotune(bt.ctx, 10)
+    skin, perm = pk.db_autotune(bt.ctx, 40)
     shape = pk.db_get_shape(bt.ctx)
     t = timed(bt, steps)
     out["tuned"] = {"value": ntot * steps / t, "ms_per_step": 1e3 * t / steps, "skin": skin,

@@ -197,6 +197,23 @@ def test_sweep_dense_gas_with_bonds(seed):
     assert g.stats()["bonds_created"] > 50 and g.stats()["bonds_broken"] > 10
 
 
+@pytest.mark.parametrize("n", [200_000, 300_000])
+def test_sweep_long_creation_list(n):
+    """A dense gas whose unbonded beads all nominate: about 2e5 and 3e5 listed beads,
+    where the creation scan runs 8 and 4 threads per bead (the thread count follows
+    the list's length); nominations, acceptances and statistics bit-exact against
+    the oracle."""
+    L = 14.0 * (n / 2500.0) ** (1.0 / 3.0)
+    s = synth.random_gas(n, L, seed=n // 1000, n_types=4)
+    s.bonds = np.array([(2 * k, 2 * k + 1, 1, 1) for k in range(300)], dtype=np.int32)
+    rules = synth.RuleSet(every=1, rules=[("create", 1, 1, 2, 1.5, 0.7), ("create", 1, 3, 4, 1.5, 0.7),
+                                          ("break", 1, 1.2, 0.6), ("maxbond", 1, 0, 1)])
+    g, o = _sweep_both(s, synth.ForceField(), rules, seed=4, step=9)
+    assert same_topology(g, o), topo_diff(g, o)
+    assert _stats_equal(g, o)
+    assert g.stats()["bonds_created"] > n // 20
+
+
 def test_topology_energy_ledger():
     """The ledger is the change of the potential energy across a sweep at fixed
     positions: the oracle's energies before and after the same sweep."""
