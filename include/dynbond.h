@@ -200,13 +200,32 @@ int db_dihedral_pattern(db_ctx* ctx, int32_t dtype, const int32_t bead[4], const
 
 /* ---- run and observe ----------------------------------------------------------- */
 
-/* advance n steps (sweep at every step k with k % every == 0, before the force) */
+/* Advance n >= 0 steps.  Step k: if every > 0 and k % every == 0, the bond sweep
+ * of the appendix (steps 2-9: nominations, mutual matching with stochastic
+ * acceptance, purge, removal and conversion, creation, angle / dihedral
+ * generation, statistics) on the positions after the previous drift; then the
+ * forces of sections 2 and 3 (pairs, directional bonds, angles, dihedrals,
+ * external forces), the thermostat (Langevin or the DPD pair forces) and the
+ * velocity-Verlet update of section 3.  Runs on the handle's stream and returns
+ * when the steps are done.  Errors: DB_ESTATE before db_set_state or after a
+ * latched device error; DB_ENONFINITE when a position became non-finite or left
+ * the box (latched: the state is undefined until db_set_state or
+ * db_checkpoint_load); DB_ECAPACITY when a sweep overflowed a per-bead table or a
+ * Verlet list (latched likewise); DB_EDEVICE on a HIP error.  n = 0 runs nothing
+ * after those checks. */
 int db_step(db_ctx* ctx, int64_t n);
-/* the sweep of the current step, now (it is then not repeated by db_step) */
+/* The sweep of the current step (appendix steps 2-9), now, on the current
+ * positions; db_step then does not repeat it for this step.  Errors as db_step. */
 int db_sweep_now(db_ctx* ctx);
-/* conservative forces at the current positions, N x 3 */
+/* The conservative forces of sections 2 and 3 (pairs, bonds, angles, dihedrals,
+ * and the external forces) at the current positions, no thermostat: f is N x 3
+ * doubles in bead-id order, caller-owned, host memory (on_device = 0) or device
+ * memory (on_device = 1, written on the handle's stream, complete on return).
+ * Errors as db_step (DB_EINVAL for f == NULL). */
 int db_forces(db_ctx* ctx, double* f, int on_device);
-/* out = {kinetic (full-step velocities), U_pair, U_bond, U_angle, U_dihedral, virial} */
+/* out (host, 6 doubles) = {kinetic energy from the full-step velocities, U_pair,
+ * U_bond, U_angle, U_dihedral (section 3 potentials, FP64 sums in a fixed order),
+ * virial sum over interactions of r . F (Clausius)}.  Errors as db_step. */
 int db_energy(db_ctx* ctx, double out[6]);
 /* db_energy for callers that cannot allocate device or pinned memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid it): the same
@@ -219,12 +238,22 @@ int db_energy(db_ctx* ctx, double out[6]);
  * All handles on one device share that array, so calls that overlap on one
  * device (from several threads or streams) race; calls in sequence do not. */
 int db_energy_noalloc(db_ctx* ctx, double out[6]);
+/* Positions (in [0, box_L)) and velocities (as in db_set_state), N x 3 doubles
+ * each in bead-id order, caller-owned, host or device memory as on_device says;
+ * either may be NULL.  Errors as db_step. */
 int db_get_state(db_ctx* ctx, double* x, double* v, int on_device);
+/* Current numbers of bonds, angles and dihedrals (section 2 topology), host. */
 int db_topology_counts(db_ctx* ctx, int64_t* nb, int64_t* na, int64_t* nd);
-/* canonical, sorted lists: bonds i<j; angles a<c; dihedrals a<d (path reversed if needed) */
+/* The topology as canonical sorted lists, into caller-owned host arrays sized by
+ * db_topology_counts: bonds (i, j) with i < j, the type each end stores (t_ij by
+ * i, t_ji by j: section 2 directional bonds); angles (a, b, c) with a < c and
+ * dihedrals (a, b, c, d) with a < d (path reversed if needed), with their types. */
 int db_get_bonds(db_ctx* ctx, int32_t* ij, int32_t* t_ij, int32_t* t_ji);
 int db_get_angles(db_ctx* ctx, int32_t* abc, int32_t* type);
 int db_get_dihedrals(db_ctx* ctx, int32_t* abcd, int32_t* type);
+/* The sweep statistics (appendix step 9: bonds created / broken / killed /
+ * converted, angles and dihedrals created / removed; last sweep and cumulative)
+ * and the scheduler's counters, into a caller-owned struct. */
 int db_get_stats(db_ctx* ctx, db_stats* out);
 /* Checkpoints of a single system.  db_checkpoint_bytes gives the size of the
  * host buffer; db_checkpoint_save fills it with every device array of the handle
