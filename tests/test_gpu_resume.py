@@ -90,6 +90,44 @@ def test_checkpoint_resume_is_bitwise(precision, tiles):
     assert np.array_equal(a.energy(), b.energy())
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_resume_dpd_is_bitwise(precision):
+    """With the DPD pair thermostat the step kernels read the neighbours' input
+    velocities and write a second velocity buffer, the two exchanged after each
+    step: a checkpoint after an odd number of steps restores which buffer holds the
+    current velocities.  Sweeps every step keep and patch the lists."""
+    import paper_1108_4214_amd as pk
+    s = perturbed(synth.dpd_solution(16, 6, 4000, 3.0, 7, 17), 0.05, 7)
+    ff, rules = synth.ff_dpd(gamma_dpd=4.5), synth.rules_t2(p=0.7, every=1, r_kill=1.3)
+
+    def make():
+        return pk.System(s.n, s.L, 31, precision).configure(s, ff, rules)
+
+    a = make()
+    a.step(23)
+    buf = pk.db_checkpoint_save(a.ctx)
+    a.step(30)
+    b = make()
+    pk.db_checkpoint_load(b.ctx, buf)
+    b.step(30)
+    xa, va = a.state()
+    xb, vb = b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert np.array_equal(a.bonds(), b.bonds())
+    assert np.array_equal(a.angles(), b.angles()) and np.array_equal(a.dihedrals(), b.dihedrals())
+    assert a.stats()["steps"] == b.stats()["steps"] == 53
+
+
+def test_checkpoint_of_a_batch_is_refused():
+    import paper_1108_4214_amd as pk
+    s, make = _run_pair(0, 0)
+    g1, g2 = make(), make()
+    bt = pk.Batch([g1, g2])
+    with pytest.raises(pk.DynBondError) as e:
+        pk.db_checkpoint_bytes(bt.ctx)
+    assert e.value.code == pk.DB_EINVAL
+
+
 def test_checkpoint_rejects_another_system():
     import paper_1108_4214_amd as pk
     s, make = _run_pair(0, 0)
