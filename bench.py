@@ -17,6 +17,7 @@ the same run and reported under ``fp64``.
 """
 import argparse
 import json
+import statistics
 import os
 import sys
 import time
@@ -116,10 +117,20 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
     # microseconds, and 7 is prime to the usual block lengths
     pk.db_profile(g.ctx, PROFILE_EVERY)
     st0 = g.stats()
+    # the timed steps in five equal chunks (each a multiple of the sweep cadence for
+    # the default 1,000 steps, so the blocks are the same), each timed too: the
+    # median of the five is reported beside the whole
+    nchunk = 5 if steps >= 5 else 1
+    sizes = [steps // nchunk] * nchunk
+    sizes[-1] += steps - sum(sizes)
+    chunk_rates = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.step(steps)
-    torch.cuda.synchronize()
+    for k in sizes:
+        tc = time.perf_counter()
+        g.step(k)
+        torch.cuda.synchronize()
+        chunk_rates.append(s.n * k / (time.perf_counter() - tc))
     t1 = time.perf_counter()
     pk.db_profile(g.ctx, 0)
     kern_us, launches = pk.db_step_kernel_time(g.ctx)
@@ -129,6 +140,8 @@ def run_gpu(w, precision, steps, warmup, skin=None, permute_every=None):
     out = {
         "seconds": t1 - t0,
         "bead_steps_per_s": s.n * steps / (t1 - t0),
+        "chunk_bead_steps_per_s": chunk_rates,
+        "median_of_chunks": statistics.median(chunk_rates),
         "ms_per_step": 1e3 * (t1 - t0) / steps,
         "step_kernel_us": kern_us,
         "step_kernel_launches": launches,
@@ -479,6 +492,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": mixed["ms_per_step"],
+        # the timed steps were also timed in five equal chunks: their median rate
+        "median_of_5_chunks": mixed["median_of_chunks"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
