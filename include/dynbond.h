@@ -290,9 +290,14 @@ int db_graph(db_ctx* ctx, int enable);
  * consecutive beads, loads the positions of every bead their lists and bonded
  * terms name into LDS once (each as its image next to the tile), and reads
  * partners from there; after every list build a region pass records those beads
- * and re-codes the entries as 16-bit indices.  enable = 0 (default): one thread
- * per bead gathers partners from memory.  The two agree to rounding (the staged
- * separations are differences of images instead of images of differences).
+ * and re-codes the entries as 16-bit indices.  In a tile whose beads hold at most
+ * four angles and four dihedrals each (448 and 224 per tile at most), every angle
+ * and dihedral is evaluated once, by one thread, and each member adds its share.
+ * enable = 0 (default): one thread per bead gathers partners from memory and
+ * evaluates its own terms.  The two agree to rounding (the staged separations are
+ * differences of images instead of images of differences, and a bead's force is
+ * summed in another order).  The arrays of this shape are part of the workspace
+ * whether or not it is on.
  * Takes effect at the next block.  EINVAL for enable outside {0, 1} or
  * brick_edge outside 0..64. */
 int db_tile_shape(db_ctx* ctx, int enable, int32_t brick_edge);
