@@ -205,9 +205,10 @@ static size_t layout(db_ctx* c, bool assign) {
     put(c->cells.cnt, 4 * (nc + 1));
     put(c->cells.start, 4 * (nc + 1));
     put(c->cells.list, 4 * n);
-    put(c->cells.xs, 16 * n);
+    put(c->cells.xs, 16 * (n + DB_XS_PAD));
     put(c->cells.cellid, 4 * n);
     put(c->cells.rank, 4 * n);
+    put(c->cells.unsorted, 4 * n);
     put(c->cells.blocksum, 4 * (size_t)blocksum_ints((int)std::max(n, nc) + 1));
     put(c->slot_of_gid, 4 * n);
     if (assign) c->tile_cap = tile_cap_of(c);

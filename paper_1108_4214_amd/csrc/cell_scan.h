@@ -11,6 +11,7 @@
 #ifndef DB_SCAN_W
 #define DB_SCAN_W 4   // candidates requested together per run
 #endif
+static_assert(DB_SCAN_W <= DB_XS_PAD, "a run's last group of loads stays within the padded position copy");
 
 namespace db {
 
@@ -139,11 +140,14 @@ __device__ __forceinline__ void scan_cells(const Box& X, const int* __restrict__
 }
 
 // The candidates of scan_cells (grids of three or more cells per edge only), each
-// passed as f(j, hit) with hit = (j != i and float r2 < cut2), in scan_cells'
-// order.  f runs for every candidate, so a visitor without branches (one that
-// writes every candidate and advances its count by hit) keeps the lanes of a wave
-// together; the x-range of a row and its wrapped part are separate loops, so the
-// common range needs no per-candidate choice of image.
+// passed as f(w, hit) with w the entry's word (xs_slot(w) is its slot) and hit =
+// (slot != i and float r2 < cut2), in scan_cells' order.  f runs for every
+// candidate, so a visitor without branches (one that writes every candidate and
+// advances its count by hit) keeps the lanes of a wave together; the x-range of a
+// row and its wrapped part are separate loops, so the common range needs no
+// per-candidate choice of image.  The bead's own entry is told apart by its whole
+// word (the slot bits differ for every other bead), and r2 is formed with fused
+// multiply-adds, whose rounding is within the relative margin of cut2.
 template <class F>
 __device__ __forceinline__ void scan_cells_all(const Box& X, const int* __restrict__ cstart,
                                                const float4* __restrict__ xs, int i, const double4& xi, float cut2,
@@ -154,6 +158,7 @@ __device__ __forceinline__ void scan_cells_all(const Box& X, const int* __restri
     const int cz = cell_coord(xi.z, X.cell_scale, nc);
     const float Lf = (float)X.L;
     const float px = (float)xi.x, py = (float)xi.y, pz = (float)xi.z;
+    const int wi = __float_as_int(xs_word(i, meta_word(xi)));
     cstart += X.cell_off;
     auto shift = [&](int c) { return c < 0 ? -Lf : (c >= nc ? Lf : 0.0f); };
     int a0, a1, b0 = 0, b1 = 0;
@@ -176,18 +181,22 @@ __device__ __forceinline__ void scan_cells_all(const Box& X, const int* __restri
     }
     const bool wrapx = b1 > b0;
     auto row_of = [&](int r) { return (wrap_cell(cz + r / 3 - 1, nc) * nc + wrap_cell(cy + r % 3 - 1, nc)) * nc; };
-    // one run [s, e) of consecutive entries seen from (qx, qy, qz)
+    // one run [s, e) of consecutive entries seen from (qx, qy, qz); a group of
+    // loads may run past e (into the next cells' entries, or into the padding after
+    // the last entry), and those candidates are masked
     auto run = [&](int s, int e, float qx, float qy, float qz) {
         for (int p = s; p < e; p += DB_SCAN_W) {
             float4 c[DB_SCAN_W];
+            const float4* src = xs + p;
 #pragma unroll
-            for (int q = 0; q < DB_SCAN_W; ++q) c[q] = xs[min(p + q, e - 1)];
+            for (int q = 0; q < DB_SCAN_W; ++q) c[q] = src[q];
+            const int rem = e - p;
 #pragma unroll
             for (int q = 0; q < DB_SCAN_W; ++q) {
-                const int j = xs_slot(__float_as_int(c[q].w));
+                const int w = __float_as_int(c[q].w);
                 const float dx = c[q].x - qx, dy = c[q].y - qy, dz = c[q].z - qz;
-                const float r2 = (dx * dx + dy * dy) + dz * dz;
-                f(j, (p + q < e) & (j != i) & (r2 < cut2));
+                const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                f(w, (q < rem) & (w != wi) & (r2 < cut2));
             }
         }
     };

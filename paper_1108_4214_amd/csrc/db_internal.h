@@ -22,6 +22,7 @@
 #define DB_RCAP 768          // region entries a tile of the step kernel stages in LDS
 #define DB_CAPA 448          // angle work items of a tile
 #define DB_CAPD 224          // dihedral work items of a tile
+#define DB_XS_PAD 8          // entries after the float position copy that a run of the cell scan may read
 #define DB_SLOT_BITS 26      // the float position copy packs slot | type << 26 | reactive << 31
 #define DB_MAX_BEADS ((1 << DB_SLOT_BITS) - 1)
 
@@ -211,9 +212,10 @@ struct Cells {
     int* cnt;         // [ncell]
     int* start;       // [ncell + 1]
     int* list;        // [n] slots, cell by cell, ascending within a cell
-    float4* xs;       // [n] in list order: float x, y, z and (bits) slot | type << 26 | reactive << 31
+    float4* xs;       // [n + DB_XS_PAD] in list order: float x, y, z and (bits) slot | type << 26 | reactive << 31
     int* cellid;      // [n]
     int* rank;        // [n] place of the bead among the beads of its cell
+    int* unsorted;    // [n] the list before the ordering inside each cell
     int* blocksum;    // scan scratch
 };
 

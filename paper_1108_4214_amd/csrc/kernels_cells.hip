@@ -19,10 +19,23 @@ void launch_fill_int(int* p, int value, size_t count, hipStream_t s) {
 }
 
 // ---- binning -----------------------------------------------------------------
+// The run of equal keys around this lane within its wavefront: [start, end) lanes.
+__device__ __forceinline__ void wave_run(int key, int lane, int& start, int& end) {
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || prev != key;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    start = 63 - __clzll(heads & upto);
+    const unsigned long long after = start == 63 ? 0ull : (heads & ~((2ull << start) - 1ull));
+    end = after ? __ffsll((long long)after) - 1 : 64;
+}
+
 // Cell of every bead and its rank among the beads of that cell.  Beads in slot
 // order are mostly sorted by cell, so neighbouring lanes of a wavefront usually
 // share a cell: each run of equal cells takes one atomic for the whole run and
-// hands out consecutive ranks.
+// hands out consecutive ranks.  (Counting the beads per scan tile of cells here as
+// well costs far more than a pass of its own: thousands of waves then add into
+// each of a few words, and atomics on one word from all XCDs are serialised.)
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_bin(const Params* __restrict__ Pp, const double4* __restrict__ x,
                                                    int* __restrict__ cellid, int* __restrict__ rank,
@@ -39,13 +52,8 @@ __global__ __launch_bounds__(DB_BLOCK) void k_bin(const Params* __restrict__ Pp,
         const int cz = cell_coord(xi.z, X.cell_scale, X.nc);
         c = X.cell_off + (cz * X.nc + cy) * X.nc + cx;
     }
-    const int prev = __shfl_up(c, 1, 64);
-    const bool head = lane == 0 || prev != c;
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const int start = 63 - __clzll(heads & upto);
-    const unsigned long long after = start == 63 ? 0ull : (heads & ~((2ull << start) - 1ull));
-    const int end = after ? __ffsll((long long)after) - 1 : 64;
+    int start, end;
+    wave_run(c, lane, start, end);
     int base = 0;
     if (lane == start && c >= 0) base = atomicAdd(&cnt[c], end - start);
     base = __shfl(base, start, 64);
@@ -130,6 +138,111 @@ __global__ void k_scan_total(const int* __restrict__ last_in, int* __restrict__ 
     if (threadIdx.x == 0 && blockIdx.x == 0) out[count] = out[count - 1] + *last_in;
 }
 
+// ---- exclusive scan in two launches (up to SCAN2_MAX_TILES tiles) --------------
+// scan tiles of 4096 items: 256 threads of 16 consecutive items each
+#define SCAN2_ITEMS 16
+#define SCAN2_TILE 4096
+static_assert(SCAN2_TILE == DB_BLOCK * SCAN2_ITEMS, "a scan tile is one workgroup's items");
+// the second pass sums the totals of all earlier tiles in every tile:
+// beyond this many tiles the multi-level scan is cheaper
+#define SCAN2_MAX_TILES 2048
+
+// The 16 items of one thread; a thread reads and writes only its own items, so
+// that a scan may run in place.
+__device__ __forceinline__ void load_items(const int* in, int base, int count, int (&v)[SCAN2_ITEMS]) {
+    if (base + SCAN2_ITEMS <= count && (reinterpret_cast<uintptr_t>(in) & 15) == 0) {
+        const int4* p = reinterpret_cast<const int4*>(in + base);
+#pragma unroll
+        for (int q = 0; q < SCAN2_ITEMS / 4; ++q) {
+            const int4 a = p[q];
+            v[4 * q] = a.x;
+            v[4 * q + 1] = a.y;
+            v[4 * q + 2] = a.z;
+            v[4 * q + 3] = a.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN2_ITEMS; ++k) v[k] = base + k < count ? in[base + k] : 0;
+    }
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// tsum[b] = sum of tile b's items
+__global__ __launch_bounds__(DB_BLOCK) void k_scan_tile_sums(const int* __restrict__ in, int count,
+                                                             int* __restrict__ tsum) {
+    __shared__ int wsum[DB_BLOCK / 64];
+    int v[SCAN2_ITEMS];
+    load_items(in, blockIdx.x * SCAN2_TILE + threadIdx.x * SCAN2_ITEMS, count, v);
+    int local = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN2_ITEMS; ++k) local += v[k];
+    local = wave_sum(local);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+#pragma unroll
+        for (int w = 0; w < DB_BLOCK / 64; ++w) t += wsum[w];
+        tsum[blockIdx.x] = t;
+    }
+}
+
+// Tile b: the sum of the totals of tiles 0..b-1 (every tile adds them up itself),
+// then the tile's own exclusive scan on top.  The last tile writes the total of
+// all items to total (when not null).  in == out is allowed.
+__global__ __launch_bounds__(DB_BLOCK) void k_scan_apply(const int* in, int* out, int count,
+                                                         const int* __restrict__ tsum, int* __restrict__ total) {
+    __shared__ int wpre[DB_BLOCK / 64], wtot[DB_BLOCK / 64];
+    const int b = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    int pre = 0;
+    for (int k = tid; k < b; k += DB_BLOCK) pre += tsum[k];
+    const int base = b * SCAN2_TILE + tid * SCAN2_ITEMS;
+    int v[SCAN2_ITEMS];
+    load_items(in, base, count, v);
+    int local = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN2_ITEMS; ++k) local += v[k];
+    pre = wave_sum(pre);
+    const int incl = wave_inclusive_scan(local);
+    if (lane == 0) wpre[wid] = pre;
+    if (lane == 63) wtot[wid] = incl;
+    __syncthreads();
+    int run = incl - local;
+#pragma unroll
+    for (int w = 0; w < DB_BLOCK / 64; ++w) run += wpre[w] + (w < wid ? wtot[w] : 0);
+    int o[SCAN2_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SCAN2_ITEMS; ++k) {
+        o[k] = run;
+        run += v[k];
+    }
+    if (base + SCAN2_ITEMS <= count && (reinterpret_cast<uintptr_t>(out) & 15) == 0) {
+        int4* p = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+        for (int q = 0; q < SCAN2_ITEMS / 4; ++q) p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN2_ITEMS; ++k)
+            if (base + k < count) out[base + k] = o[k];
+    }
+    // items past count are zero, so the last thread's running sum is the total
+    if (total && b == (int)gridDim.x - 1 && tid == DB_BLOCK - 1) *total = run;
+}
+
+static int scan2_tiles(int count) { return (count + SCAN2_TILE - 1) / SCAN2_TILE; }
+
+// two-launch scan; tsum holds scan2_tiles(count) ints
+static void scan2(const int* in, int* out, int count, int* tsum, hipStream_t s, int* total) {
+    const int tiles = scan2_tiles(count);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(DB_BLOCK), 0, s, in, count, tsum);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(DB_BLOCK), 0, s, in, out, count, tsum, total);
+}
+
 // Exclusive scan of in[0..count) into out[0..count) (in == out allowed: each tile
 // reads its items before any of them is written).  blocksum must hold the tile
 // totals of every level: ceil(count/1024) + ceil(count/1024^2) + ... ints.
@@ -149,6 +262,11 @@ static void scan_into(const int* in, int* out, int count, int* blocksum, hipStre
 }
 
 void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStream_t s) {
+    const int tiles = scan2_tiles(count);
+    if (tiles > 0 && tiles <= SCAN2_MAX_TILES) {
+        scan2(in, out, count, blocksum, s, out + count);
+        return;
+    }
     scan_into(in, out, count, blocksum, s, out + count);
 }
 
@@ -156,6 +274,10 @@ void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStr
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s) {
     (void)total_out;
     if (count <= 0) return;
+    if (scan2_tiles(count) <= SCAN2_MAX_TILES) {
+        scan2(data, data, count, blocksum, s, data + count);
+        return;
+    }
     int* last = blocksum;
     hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(1), 0, s, data + count - 1, last);
     scan_into(data, data, count, blocksum + 1, s);
@@ -163,43 +285,39 @@ void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, 
 }
 
 // ---- scatter and in-cell ordering --------------------------------------------
-// the bead's place in the list from its cell start and rank; the first bead of
-// every cell clears the count for the next build (the scan has consumed it)
+// the bead's place in the unsorted list from its cell start and rank; the first
+// bead of every cell clears the count for the next build (the scan has consumed it)
 __global__ __launch_bounds__(DB_BLOCK) void k_scatter(int n, const int* __restrict__ cellid,
                                                        const int* __restrict__ rank, const int* __restrict__ start,
-                                                       int* __restrict__ cnt, int* __restrict__ list,
+                                                       int* __restrict__ cnt, int* __restrict__ unsorted,
                                                        unsigned long long* __restrict__ stats) {
     int i = blockIdx.x * DB_BLOCK + threadIdx.x;
     if (i < 8) stats[i] = 0ull;   // the counters of the sweep that follows this build
     if (i >= n) return;
     const int c = cellid[i], k = rank[i];
-    list[start[c] + k] = i;
+    unsorted[start[c] + k] = i;
     if (k == 0) cnt[c] = 0;
 }
 
-// ascending slot order inside each cell makes the list independent of the
-// arrival order of the atomics above; the float copy of the positions is then
-// written in list order, so a scan over neighbouring cells reads contiguous runs
-__global__ __launch_bounds__(DB_BLOCK) void k_cellsort(int ncell, const int* __restrict__ start,
-                                                        int* __restrict__ list, const double4* __restrict__ x,
-                                                        float4* __restrict__ xs) {
-    int c = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (c >= ncell) return;
-    int s0 = start[c], s1 = start[c + 1];
-    for (int a = s0 + 1; a < s1; ++a) {
-        int v = list[a];
-        int b = a - 1;
-        while (b >= s0 && list[b] > v) {
-            list[b + 1] = list[b];
-            --b;
-        }
-        list[b + 1] = v;
-    }
-    for (int a = s0; a < s1; ++a) {
-        int j = list[a];
-        double4 xj = x[j];
-        xs[a] = make_float4((float)xj.x, (float)xj.y, (float)xj.z, xs_word(j, meta_word(xj)));
-    }
+// Ascending slot order inside each cell makes the list independent of the
+// arrival order of the atomics above.  One thread per entry of the unsorted
+// list: the entry's place in its cell is the number of the cell's entries with a
+// smaller slot.  The float copy of the positions is written in list order, so a
+// scan over neighbouring cells reads contiguous runs.
+__global__ __launch_bounds__(DB_BLOCK) void k_cellsort(int n, const int* __restrict__ start,
+                                                        const int* __restrict__ cellid,
+                                                        const int* __restrict__ unsorted, int* __restrict__ list,
+                                                        const double4* __restrict__ x, float4* __restrict__ xs) {
+    const int t = blockIdx.x * DB_BLOCK + threadIdx.x;
+    if (t >= n) return;
+    const int j = unsorted[t];
+    const double4 xj = x[j];
+    const int c = cellid[j];
+    const int s0 = start[c], s1 = start[c + 1];
+    int r = 0;
+    for (int k = s0; k < s1; ++k) r += unsorted[k] < j ? 1 : 0;
+    list[s0 + r] = j;
+    xs[s0 + r] = make_float4((float)xj.x, (float)xj.y, (float)xj.z, xs_word(j, meta_word(xj)));
 }
 
 void launch_build_cells(db_ctx* c) {
@@ -217,13 +335,12 @@ void launch_build_cells(db_ctx* c) {
                                c->cells.rank, c->cells.cnt);
     }
     // start = exclusive scan of cnt; start[ncell] = their total, n
-    scan_into(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s, c->cells.start + ncell);
+    launch_scan_total(c->cells.cnt, c->cells.start, ncell, c->cells.blocksum, s);
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.cellid, c->cells.rank,
-                           c->cells.start, c->cells.cnt, c->cells.list, c->sw.stats);
-        unsigned cb = (unsigned)((ncell + DB_BLOCK - 1) / DB_BLOCK);
-        hipLaunchKernelGGL(k_cellsort, dim3(cb), dim3(DB_BLOCK), 0, s, ncell, c->cells.start, c->cells.list, B.x,
-                           c->cells.xs);
+                           c->cells.start, c->cells.cnt, c->cells.unsorted, c->sw.stats);
+        hipLaunchKernelGGL(k_cellsort, dim3(nb), dim3(DB_BLOCK), 0, s, n, c->cells.start, c->cells.cellid,
+                           c->cells.unsorted, c->cells.list, B.x, c->cells.xs);
     }
 }
 

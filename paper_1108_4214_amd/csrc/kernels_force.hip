@@ -341,16 +341,18 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
     } else {
         // Every candidate within the cutoff is kept first, in the LDS rows, and the
         // exclusions are applied afterwards, compacting in place in scan order.
-        // The scan writes every candidate (those not kept into the extra row) and
-        // advances the count by the test, with no branch per candidate; tested
-        // inside the scan, the exclusion test and the store ran for every
-        // candidate some lane of the wave kept, which is nearly every candidate.
+        // The scan writes every candidate into the row of the next kept entry (a
+        // candidate not kept is overwritten by the next one kept; past the LDS rows
+        // the extra row takes them all) and advances the count by the test, with no
+        // branch per candidate; tested inside the scan, the exclusion test and the
+        // store ran for every candidate some lane of the wave kept, which is nearly
+        // every candidate.
         // A bead with more kept candidates than the LDS rows hold, or a grid of
         // fewer than three cells per edge, is scanned with the test inside.
         int raw = 0;
         if (X.noff == 3) {
-            scan_cells_all(X, cstart, xs, i, xi, X.pf_list2, [&](int j, bool hit) {
-                stage[hit ? min(raw, NL_STAGE) : NL_STAGE][tid] = j;
+            scan_cells_all(X, cstart, xs, i, xi, X.pf_list2, [&](int w, bool hit) {
+                stage[min(raw, NL_STAGE)][tid] = w;   // the word; its slot is taken below
                 raw += hit ? 1 : 0;
             });
         } else {
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restri
         }
         if (raw <= NL_STAGE) {
             for (int k = 0; k < raw; ++k) {
-                const int j = stage[k][tid];
+                const int j = xs_slot(stage[k][tid]);
                 if (excluded(j)) continue;
                 stage[cnt][tid] = j;
                 ++cnt;
