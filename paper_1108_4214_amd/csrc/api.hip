@@ -1068,6 +1068,7 @@ static int add_rule(db_ctx* c, Rule r) {
     }
     if (r.kind == RK_BREAK || r.kind == RK_CONVERT) P.has_break_class = 1;
     if (r.kind == RK_KILL) P.has_kill = 1;
+    if (r.kind == RK_BREAK || r.kind == RK_CONVERT || r.kind == RK_KILL) P.break_types |= 1u << r.bt1;
     c->params_dirty = true;
     return DB_OK;
 }

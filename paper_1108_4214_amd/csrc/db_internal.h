@@ -111,6 +111,7 @@ struct Params {
     uint32_t create_types;      // bit t: bead type t occurs in some creation rule
     int has_break_class;        // any breakbond / convertbond rule
     int has_kill;
+    uint32_t break_types;       // bit t: some breakbond / killbond / convertbond rule acts on bond type t
 };
 
 // Per-bead storage in slot (cell-sorted) order.  Tables are column-major:

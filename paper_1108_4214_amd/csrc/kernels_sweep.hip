@@ -349,14 +349,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
     double best_r2 = 0.0;
     int rm = 0;
     unsigned long long killed_here = 0;
-    // the bead's table with all rows requested at once, then its partners'
-    // positions, all in flight together
+    // the bead's table with all rows requested at once, then the positions of the
+    // partners whose bond type some breaking rule acts on, all in flight together
     const Tab Ti = load_tab_all(B, n, i);
     const bool scan_bonds = meta_reactive(mi) && (P.has_kill || P.has_break_class);
     double4 xp[DB_MAXB];
 #pragma unroll
     for (int k = 0; k < DB_MAXB; ++k)
-        if (scan_bonds && k < Ti.n) xp[k] = B.x[Ti.p(k)];
+        if (scan_bonds && k < Ti.n && ((P.break_types >> Ti.t(k)) & 1u)) xp[k] = B.x[Ti.p(k)];
     {
         // creation: flag the bead for the creation scan's list; its nomination starts empty
         const int ti = meta_type(mi);
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_break(const Params* __res
         int ti = meta_type(mi);
 #pragma unroll
         for (int k = 0; k < DB_MAXB; ++k) {
-            if (k >= Ti.n) continue;
+            if (k >= Ti.n || !((P.break_types >> Ti.t(k)) & 1u)) continue;
             int j = Ti.p(k), t = Ti.t(k);
             const double4 xj = xp[k];
             int mj = meta_word(xj);
