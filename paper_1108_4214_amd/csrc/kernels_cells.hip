@@ -63,9 +63,14 @@ __global__ __launch_bounds__(DB_BLOCK) void k_bin(const Params* __restrict__ Pp,
     }
 }
 
-// ---- exclusive scan (1024 items per workgroup, multi-level) -------------------
-#define SCAN_ITEMS 4
-#define SCAN_TILE (DB_BLOCK * SCAN_ITEMS)
+// ---- exclusive scan in two launches -------------------------------------------
+// Tiles of 4096 items: 256 threads of 16 consecutive items each.  The first launch
+// sums every tile; in the second every tile adds up the sums of the tiles before
+// it (from L2: at most one int per thread up to a million items, 128 for the
+// largest cell grid) and scans its own items on top.
+#define SCAN2_ITEMS 16
+#define SCAN2_TILE 4096
+static_assert(SCAN2_TILE == DB_BLOCK * SCAN2_ITEMS, "a scan tile is one workgroup's items");
 
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
     // Hillis-Steele over the 64 lanes of a wavefront
@@ -77,75 +82,6 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
     }
     return v;
 }
-
-// in[0..count) -> out[0..count) exclusive; per-tile totals to blocksum; total (when
-// not null and a single tile covers count) receives the sum of all
-__global__ __launch_bounds__(DB_BLOCK) void k_scan_tiles(const int* __restrict__ in, int* __restrict__ out, int count,
-                                                         int* __restrict__ blocksum, int* __restrict__ total) {
-    __shared__ int wsum[DB_BLOCK / 64];
-    int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    int v[SCAN_ITEMS];
-    int local = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int idx = base + k;
-        v[k] = idx < count ? in[idx] : 0;
-        local += v[k];
-    }
-    int incl = wave_inclusive_scan(local);
-    int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int woff = 0;
-    for (int w = 0; w < wid; ++w) woff += wsum[w];
-    int run = woff + incl - local;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int idx = base + k;
-        if (idx < count) out[idx] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == DB_BLOCK - 1) {
-        blocksum[blockIdx.x] = run;
-        if (total) *total = run;
-    }
-}
-
-// adds the tile offsets; the thread holding the last item writes the total (in is
-// the unchanged input of an out-of-place scan, read only for that item)
-__global__ __launch_bounds__(DB_BLOCK) void k_scan_add(int* __restrict__ out, int count,
-                                                       const int* __restrict__ offsets, const int* __restrict__ in,
-                                                       int* __restrict__ total) {
-    int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    int off = offsets[blockIdx.x];
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int idx = base + k;
-        if (idx < count) {
-            const int o = out[idx] + off;
-            out[idx] = o;
-            if (total && idx == count - 1) *total = o + in[idx];
-        }
-    }
-}
-
-__global__ void k_copy_int(const int* __restrict__ src, int* __restrict__ dst) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
-}
-
-// out[count] = out[count - 1] + (saved last input)
-__global__ void k_scan_total(const int* __restrict__ last_in, int* __restrict__ out, int count) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[count] = out[count - 1] + *last_in;
-}
-
-// ---- exclusive scan in two launches (up to SCAN2_MAX_TILES tiles) --------------
-// scan tiles of 4096 items: 256 threads of 16 consecutive items each
-#define SCAN2_ITEMS 16
-#define SCAN2_TILE 4096
-static_assert(SCAN2_TILE == DB_BLOCK * SCAN2_ITEMS, "a scan tile is one workgroup's items");
-// the second pass sums the totals of all earlier tiles in every tile:
-// beyond this many tiles the multi-level scan is cheaper
-#define SCAN2_MAX_TILES 2048
 
 // The 16 items of one thread; a thread reads and writes only its own items, so
 // that a scan may run in place.
@@ -199,8 +135,16 @@ __global__ __launch_bounds__(DB_BLOCK) void k_scan_apply(const int* in, int* out
                                                          const int* __restrict__ tsum, int* __restrict__ total) {
     __shared__ int wpre[DB_BLOCK / 64], wtot[DB_BLOCK / 64];
     const int b = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    int pre = 0;
-    for (int k = tid; k < b; k += DB_BLOCK) pre += tsum[k];
+    int pre = 0, pre1 = 0, pre2 = 0, pre3 = 0;
+    int k = tid;
+    for (; k + 3 * DB_BLOCK < b; k += 4 * DB_BLOCK) {
+        pre += tsum[k];
+        pre1 += tsum[k + DB_BLOCK];
+        pre2 += tsum[k + 2 * DB_BLOCK];
+        pre3 += tsum[k + 3 * DB_BLOCK];
+    }
+    for (; k < b; k += DB_BLOCK) pre += tsum[k];
+    pre += (pre1 + pre2) + pre3;
     const int base = b * SCAN2_TILE + tid * SCAN2_ITEMS;
     int v[SCAN2_ITEMS];
     load_items(in, base, count, v);
@@ -243,45 +187,21 @@ static void scan2(const int* in, int* out, int count, int* tsum, hipStream_t s, 
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(DB_BLOCK), 0, s, in, out, count, tsum, total);
 }
 
-// Exclusive scan of in[0..count) into out[0..count) (in == out allowed: each tile
-// reads its items before any of them is written).  blocksum must hold the tile
-// totals of every level: ceil(count/1024) + ceil(count/1024^2) + ... ints.
-// total (optional, out-of-place scans only: in != out) receives the sum of all.
-static void scan_into(const int* in, int* out, int count, int* blocksum, hipStream_t s, int* total = nullptr) {
-    int tiles = (count + SCAN_TILE - 1) / SCAN_TILE;
-    if (tiles == 0) {
-        if (total) hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, total, 0, (size_t)1);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(DB_BLOCK), 0, s, in, out, count, blocksum,
-                       tiles == 1 ? total : nullptr);
-    if (tiles > 1) {
-        scan_into(blocksum, blocksum, tiles, blocksum + tiles, s);
-        hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(DB_BLOCK), 0, s, out, count, blocksum, in, total);
-    }
-}
-
+// out[0..count) = exclusive prefix sums of in[0..count), out[count] = their total;
+// blocksum holds at least ceil(count / 4096) ints
 void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStream_t s) {
-    const int tiles = scan2_tiles(count);
-    if (tiles > 0 && tiles <= SCAN2_MAX_TILES) {
-        scan2(in, out, count, blocksum, s, out + count);
+    if (count <= 0) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, out, 0, (size_t)1);
         return;
     }
-    scan_into(in, out, count, blocksum, s, out + count);
+    scan2(in, out, count, blocksum, s, out + count);
 }
 
 // data[0..count) -> exclusive prefix sums in place, and the total in data[count]
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s) {
     (void)total_out;
     if (count <= 0) return;
-    if (scan2_tiles(count) <= SCAN2_MAX_TILES) {
-        scan2(data, data, count, blocksum, s, data + count);
-        return;
-    }
-    int* last = blocksum;
-    hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(1), 0, s, data + count - 1, last);
-    scan_into(data, data, count, blocksum + 1, s);
-    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, last, data, count);
+    scan2(data, data, count, blocksum, s, data + count);
 }
 
 // ---- scatter and in-cell ordering --------------------------------------------
