@@ -221,13 +221,16 @@ __device__ __forceinline__ void scan_cells_all(const Box& X, const int* __restri
 // f(j, w) for every slot j != i with float r2 < cut2 in the 5 x 5 x 5 cells
 // around xi: a reach of two cell edges, for lists redone with a cutoff beyond one
 // edge.  Needs at least five cells per edge (no cell is visited twice).  Each
-// candidate takes the minimum image; this serves only the beads whose lists are
-// redone after a sweep.  The outer layer of cells on a side is visited only when
-// the bead lies within the cutoff of it (for a cutoff just beyond one edge, most
-// beads need the inner 3 x 3 x 3 cells alone), and the x-cells of a row are read
-// as one run unless the row wraps.  PARTS and part split the rows by their index
-// modulo PARTS.
-template <int PARTS = 1, class F>
+// candidate takes the minimum image; this serves the beads whose lists are redone
+// after a sweep, and creation scans with a creation distance beyond one edge.  The
+// outer layer of cells on a side is visited only when the bead lies within the
+// cutoff of it (for a cutoff just beyond one edge, most beads need the inner
+// 3 x 3 x 3 cells alone), and the x-cells of a row are read as one run unless the
+// row wraps.  PARTS and part split the rows by their index modulo PARTS.  GW
+// entries of a run are requested together (a patched list is redone for few
+// beads, one thread each, so their loads in flight set its time; the creation scan
+// takes one at a time, to keep its registers).
+template <int PARTS = 1, int GW = DB_SCAN_W, class F>
 __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, const float4* __restrict__ xs,
                                 int i, const double4& xi, float cut2, F&& f, int part = 0) {
     const int nc = X.nc;
@@ -247,31 +250,54 @@ __device__ void scan_cells_wide(const Box& X, const int* __restrict__ cstart, co
     const int loy = lo_of(xi.y, cy), hiy = hi_of(xi.y, cy);
     const int loz = lo_of(xi.z, cz), hiz = hi_of(xi.z, cz);
     const bool xrun = cx + lox >= 0 && cx + hix < nc;   // the row's x-cells are contiguous
-    int rowno = 0;
-    for (int oz = loz; oz <= hiz; ++oz) {
-        const int zz = wrap_cell(cz + oz, nc);
-        for (int oy = loy; oy <= hiy; ++oy) {
-            if (PARTS > 1 && rowno++ % PARTS != part) continue;
-            const int row = (zz * nc + wrap_cell(cy + oy, nc)) * nc;
-            auto run = [&](int s0, int s1) {
-                for (int p = s0; p < s1; ++p) {
-                    const float4 e = xs[p];
-                    const int w = __float_as_int(e.w);
-                    const int j = xs_slot(w);
-                    const float dx = fmin_image(e.x - px, Lf, hLf);
-                    const float dy = fmin_image(e.y - py, Lf, hLf);
-                    const float dz = fmin_image(e.z - pz, Lf, hLf);
-                    const float r2 = (dx * dx + dy * dy) + dz * dz;
-                    if ((j != i) & (r2 < cut2)) f(j, w);
-                }
-            };
-            if (xrun) {
-                run(cstart[row + cx + lox], cstart[row + cx + hix + 1]);
-            } else {
-                for (int ox = lox; ox <= hix; ++ox) {
-                    const int c = row + wrap_cell(cx + ox, nc);
-                    run(cstart[c], cstart[c + 1]);
-                }
+    // a run is read GW entries at a time, all in flight together; the last group
+    // may read past the run (into the next cells, or the padding after the copy),
+    // and those entries are masked
+    static_assert(GW >= 1 && GW <= DB_XS_PAD, "a group stays within the padded position copy");
+    auto run = [&](int s0, int s1) {
+        for (int p = s0; p < s1; p += GW) {
+            float4 e[GW];
+            const float4* src = xs + p;
+#pragma unroll
+            for (int q = 0; q < GW; ++q) e[q] = src[q];
+            const int rem = s1 - p;
+#pragma unroll
+            for (int q = 0; q < GW; ++q) {
+                const int w = __float_as_int(e[q].w);
+                const int j = xs_slot(w);
+                const float dx = fmin_image(e[q].x - px, Lf, hLf);
+                const float dy = fmin_image(e[q].y - py, Lf, hLf);
+                const float dz = fmin_image(e[q].z - pz, Lf, hLf);
+                const float r2 = (dx * dx + dy * dy) + dz * dz;
+                if ((q < rem) & (j != i) & (r2 < cut2)) f(j, w);
+            }
+        }
+    };
+    // rows in z-major order; with contiguous x-cells the next row's bounds are
+    // requested before the current row is scanned
+    const int ny = hiy - loy + 1, nrow = (hiz - loz + 1) * ny;
+    auto row_of = [&](int r) { return (wrap_cell(cz + loz + r / ny, nc) * nc + wrap_cell(cy + loy + r % ny, nc)) * nc; };
+    int r = PARTS > 1 ? part : 0;
+    int a0 = 0, a1 = 0;
+    if (xrun && r < nrow) {
+        const int row = row_of(r);
+        a0 = cstart[row + cx + lox];
+        a1 = cstart[row + cx + hix + 1];
+    }
+    for (; r < nrow; r += PARTS) {
+        if (xrun) {
+            const int s0 = a0, s1 = a1;
+            if (r + PARTS < nrow) {
+                const int row = row_of(r + PARTS);
+                a0 = cstart[row + cx + lox];
+                a1 = cstart[row + cx + hix + 1];
+            }
+            run(s0, s1);
+        } else {
+            const int row = row_of(r);
+            for (int ox = lox; ox <= hix; ++ox) {
+                const int c = row + wrap_cell(cx + ox, nc);
+                run(cstart[c], cstart[c + 1]);
             }
         }
     }

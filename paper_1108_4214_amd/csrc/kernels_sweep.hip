@@ -277,7 +277,7 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
             queue[nq][tid] = j;
             ++nq;
         };
-        if (X.wide_create) scan_cells_wide<LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
+        if (X.wide_create) scan_cells_wide<LANES, 1>(X, cstart, xs, i, xi, cut2, visit, lane);
         else scan_cells<LANES>(X, cstart, xs, i, xi, cut2, visit, lane);
         for (int k = 0; k < nq; ++k) examine(queue[k][tid]);
     }
