@@ -208,7 +208,10 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
         // kept, with the other lanes idle.  The nominee, the least (r^2, id), does
         // not depend on the order of the examinations.
         auto examine = [&](int j) {
+            // the candidate's table is requested with its position (nearly every
+            // examined candidate passes the distance and rule tests that need it)
             const double4 xj = B.x[j];
+            const Tab Tj = load_tab_all(B, n, j);
             const int mj = meta_word(xj);
             double dx, dy, dz;
             const double r2 = separation(X, xi, xj, dx, dy, dz);
@@ -217,8 +220,6 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
             const int gj = meta_gid(xj);
             // last creation rule that applies to the pair
             int rule = -1, bti = 0;
-            bool have_tj = false;
-            Tab Tj{0, -1, -1, -1, -1, 0, 0, 0, 0};
             for (int q = 0; q < P.nrule; ++q) {
                 const Rule& r = P.rule[q];
                 if (r.kind != RK_CREATE && r.kind != RK_CREATEDIR) continue;
@@ -230,10 +231,6 @@ __device__ __forceinline__ void nominate_create_one(const Params& P, const int n
                 const int sj = o1 ? r.bt2 : r.bt1;
                 if (!(r2 < r.r2)) continue;
                 if (!max_ok(P, ti, Ti, si)) continue;
-                if (!have_tj) {
-                    Tj = load_tab_all(B, n, j);
-                    have_tj = true;
-                }
                 if (!max_ok(P, tj, Tj, sj)) continue;
                 rule = q;
                 bti = si;
