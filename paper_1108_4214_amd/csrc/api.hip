@@ -130,15 +130,9 @@ static int ncell_cap(const db_ctx* c) { return 2 * c->n + 64 * std::max(1, c->nr
 // tiles than this runs without them
 static int tile_cap_of(const db_ctx* c) { return c->nrep > 0 ? 1 : (c->n + DB_BLOCK - 1) / DB_BLOCK + 1; }
 
-static int blocksum_ints(int count) {
-    int tot = 2;
-    int t = count;
-    while (t > 1) {
-        t = (t + 1023) / 1024;
-        tot += t + 1;
-    }
-    return tot + 64;
-}
+// scan scratch: the tile sums of the longest scanned array (one int per tile of
+// 4096 items)
+static int blocksum_ints(int count) { return (count + 4095) / 4096 + 64; }
 
 struct Layout {
     size_t off[64];
