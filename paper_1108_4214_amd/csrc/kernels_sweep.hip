@@ -166,11 +166,12 @@ __global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
 // one thread scanning every run in any order would find.  The listed range is
 // split per XCD; the workgroups step over the tiles of the list, so that a list
 // longer than the grid's share is covered too.  The kernel picks LANES from the
-// list's length: a long list (every base of a melted system) fills the GPU with
-// two threads per bead and gains from their shorter per-row overhead, a short one
-// (a few melted bases among hybridized duplexes) needs sixteen to fill it at all.
+// list's length: a list of half a million beads or more (the bases of a melted
+// system) fills the GPU with one thread per bead (on the 4M-bead stress case 239
+// against 300 us with two, 377 with four), a short one (a few melted bases among
+// hybridized duplexes) needs sixteen to fill it at all.
 __device__ __forceinline__ int create_lanes_for(int nl) {
-    return nl >= (1 << 19) ? 2 : (nl >= (1 << 18) ? 4 : (nl >= (1 << 17) ? 8 : 16));
+    return nl >= (1 << 19) ? 1 : (nl >= (1 << 18) ? 2 : (nl >= (1 << 17) ? 4 : (nl >= (1 << 16) ? 8 : 16)));
 }
 
 // candidates a thread queues before examining them (more are examined at once)
@@ -324,6 +325,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_nominate_create(const Params* __re
     const int nl = S.aoff[P.n];
     __shared__ int queue[CREATE_QUEUE][DB_BLOCK];   // a column per thread
     switch (create_lanes_for(nl)) {   // uniform over the grid
+        case 1: nominate_create_all<BATCH, 1>(P, B, cstart, xs, S, nl, queue); break;
         case 2: nominate_create_all<BATCH, 2>(P, B, cstart, xs, S, nl, queue); break;
         case 4: nominate_create_all<BATCH, 4>(P, B, cstart, xs, S, nl, queue); break;
         case 8: nominate_create_all<BATCH, 8>(P, B, cstart, xs, S, nl, queue); break;

@@ -197,12 +197,12 @@ def test_sweep_dense_gas_with_bonds(seed):
     assert g.stats()["bonds_created"] > 50 and g.stats()["bonds_broken"] > 10
 
 
-@pytest.mark.parametrize("n", [200_000, 300_000])
+@pytest.mark.parametrize("n", [100_000, 200_000, 300_000, 600_000])
 def test_sweep_long_creation_list(n):
-    """A dense gas whose unbonded beads all nominate: about 2e5 and 3e5 listed beads,
-    where the creation scan runs 8 and 4 threads per bead (the thread count follows
-    the list's length); nominations, acceptances and statistics bit-exact against
-    the oracle."""
+    """A dense gas whose unbonded beads all nominate: about 1e5, 2e5, 3e5 and 6e5
+    listed beads, where the creation scan runs 8, 4, 2 and 1 threads per bead (the
+    thread count follows the list's length); nominations, acceptances and
+    statistics bit-exact against the oracle."""
     L = 14.0 * (n / 2500.0) ** (1.0 / 3.0)
     s = synth.random_gas(n, L, seed=n // 1000, n_types=4)
     s.bonds = np.array([(2 * k, 2 * k + 1, 1, 1) for k in range(300)], dtype=np.int32)
