@@ -239,147 +239,203 @@ __device__ void pair_forces(const Params& P, const Box& X, const Bank& B, const 
     }
 }
 
-// Verlet list of bead i: every bead within the list cutoff (pair cutoff plus a
-// skin) that is not excluded, from the 27 cells of the current cell list.  The
-// float prefilter's cutoff is widened by the box's bound on float rounding
-// (Box::pf_slack), so the list is a superset of the pairs within the cutoff in
-// double.
-// The full build (list == nullptr: every bead, and with DPD its position is kept
-// in xref, from which the step kernels measure displacements) or the patch after a sweep (list: the beads whose
-// exclusions changed, count at list_n; cut then exceeds the list cutoff by the
-// displacement margin and the wide stencil reaches it).
-template <bool BATCH, bool WIDE>
-__global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restrict__ Pp, Bank B,
-                                                          const int* __restrict__ cstart,
-                                                          const float4* __restrict__ xs, NList NL,
-                                                          int* __restrict__ err, double4* __restrict__ xref,
-                                                          const int* __restrict__ list,
-                                                          const int* __restrict__ list_n, double cut) {
-    const Params& P = *Pp;
-    const int n = P.n;
-    // list rows staged in LDS, plus (full build) one row that takes the writes of
-    // the candidates that are not kept
-    constexpr int NL_STAGE = WIDE ? 1 : 24;
-    __shared__ int stage[NL_STAGE + (WIDE ? 0 : 1)][DB_BLOCK];
-    int i;
-    if (WIDE) {
-        const int nl = *list_n;
-        const int ntile = (nl + DB_BLOCK - 1) / DB_BLOCK;
-        if ((int)blockIdx.x >= ntile) return;
-        const int t = xcd_tile(blockIdx.x, ntile) * DB_BLOCK + threadIdx.x;
-        if (t >= nl) return;
-        i = list[t];
-    } else {
-        i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
-        if (i >= n) return;
+// The beads a list of bead i leaves out: its bond partners (exclusion depth 1)
+// and their partners (depth 2), -1 for an empty entry, so that testing a
+// candidate compares registers instead of re-reading the partners' tables.  The
+// bond rows exist for every bead: all are requested at once with the count and
+// the unused ones ignored, and likewise for the partners' rows, so that gathering
+// the set costs two memory latencies.
+struct ExclSet {
+    int nb, p0, p1, p2, p3;
+    bool d1, d2;
+    int two[DB_MAXB * DB_MAXB];
+    __device__ __forceinline__ bool has(int j) const {
+        if (d1 && in_list4(j, nb, p0, p1, p2, p3)) return true;
+        bool ex = false;
+        if (d2 && nb > 0) {
+#pragma unroll
+            for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) ex |= two[k] == j;
+        }
+        return ex;
     }
-    const double4 xi = B.x[i];
-    if (!WIDE && xref) xref[i] = xi;
-    // the bond rows exist for every bead: all are requested at once with the count
-    // and the unused ones ignored, and likewise for the partners' rows, so that the
-    // exclusion set costs two memory latencies before the scan
-    const int nb = B.nb[i];
+};
+
+__device__ __forceinline__ void gather_excl(const Params& P, const Bank& B, int n, int i, ExclSet& E) {
+    static_assert(DB_MAXB == 4, "the exclusion test holds four partners");
+    E.d1 = P.excl_depth >= 1;
+    E.d2 = P.excl_depth >= 2;
+    E.nb = B.nb[i];
     int pr[DB_MAXB];
 #pragma unroll
     for (int k = 0; k < DB_MAXB; ++k) pr[k] = B.bp[k * n + i];
-    const int p0 = nb > 0 ? pr[0] : -1;
-    const int p1 = nb > 1 ? pr[1] : -1;
-    const int p2 = nb > 2 ? pr[2] : -1;
-    const int p3 = nb > 3 ? pr[3] : -1;
-    // the beads two bonds away (partners of partners), gathered once per bead, so
-    // that testing a candidate compares registers instead of re-reading the
-    // partners' tables; -1 marks an empty entry
-    static_assert(DB_MAXB == 4, "the exclusion test holds four partners");
-    const bool depth2 = P.excl_depth >= 2;
-    const int pp[DB_MAXB] = {p0, p1, p2, p3};
-    int two[DB_MAXB * DB_MAXB];
+    E.p0 = E.nb > 0 ? pr[0] : -1;
+    E.p1 = E.nb > 1 ? pr[1] : -1;
+    E.p2 = E.nb > 2 ? pr[2] : -1;
+    E.p3 = E.nb > 3 ? pr[3] : -1;
+    const int pp[DB_MAXB] = {E.p0, E.p1, E.p2, E.p3};
 #pragma unroll
-    for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) two[k] = -1;
-    if (depth2) {
+    for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) E.two[k] = -1;
+    if (E.d2) {
         int nq[DB_MAXB];
 #pragma unroll
         for (int k = 0; k < DB_MAXB; ++k) {
-            const int q = k < nb ? pp[k] : i;
-            nq[k] = k < nb ? B.nb[q] : 0;
+            const int q = k < E.nb ? pp[k] : i;
+            nq[k] = k < E.nb ? B.nb[q] : 0;
 #pragma unroll
-            for (int m = 0; m < DB_MAXB; ++m) two[k * DB_MAXB + m] = B.bp[m * n + q];
+            for (int m = 0; m < DB_MAXB; ++m) E.two[k * DB_MAXB + m] = B.bp[m * n + q];
         }
 #pragma unroll
         for (int k = 0; k < DB_MAXB; ++k)
 #pragma unroll
             for (int m = 0; m < DB_MAXB; ++m)
-                if (m >= nq[k]) two[k * DB_MAXB + m] = -1;
+                if (m >= nq[k]) E.two[k * DB_MAXB + m] = -1;
     }
-    // The first NL_STAGE entries of the full build go to the thread's own LDS
-    // column and are written out afterwards one row at a time, so that a store
-    // covers consecutive beads of one row; entries beyond go straight to memory.
-    // (Written as they are found, the lanes of a wave store into rows that differ
-    // by their counts, and each store scatters over as many rows.)
+}
+
+// Verlet list of bead i: every bead within the list cutoff (pair cutoff plus a
+// skin) that is not excluded, from the 27 cells of the current cell list.  The
+// float prefilter's cutoff is widened by the box's bound on float rounding
+// (Box::pf_slack), so the list is a superset of the pairs within the cutoff in
+// double.  The full build of every bead; with DPD the bead's position is kept in
+// xref, from which the step kernels measure displacements.
+template <bool BATCH>
+__global__ __launch_bounds__(DB_BLOCK) void k_build_nlist(const Params* __restrict__ Pp, Bank B,
+                                                          const int* __restrict__ cstart,
+                                                          const float4* __restrict__ xs, NList NL,
+                                                          int* __restrict__ err, double4* __restrict__ xref) {
+    const Params& P = *Pp;
+    const int n = P.n;
+    // list rows staged in LDS, plus one row that takes the writes of the
+    // candidates that are not kept
+    constexpr int NL_STAGE = 24;
+    __shared__ int stage[NL_STAGE + 1][DB_BLOCK];
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * DB_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const double4 xi = B.x[i];
+    if (xref) xref[i] = xi;
+    ExclSet E;
+    gather_excl(P, B, n, i, E);
+    // The first NL_STAGE entries go to the thread's own LDS column and are written
+    // out afterwards one row at a time, so that a store covers consecutive beads of
+    // one row; entries beyond go straight to memory.  (Written as they are found,
+    // the lanes of a wave store into rows that differ by their counts, and each
+    // store scatters over as many rows.)
     const int tid = threadIdx.x;
-    auto excluded = [&](int j) {
-        if (P.excl_depth >= 1 && in_list4(j, nb, p0, p1, p2, p3)) return true;
-        bool ex = false;
-        if (depth2 && nb > 0) {
-#pragma unroll
-            for (int k = 0; k < DB_MAXB * DB_MAXB; ++k) ex |= two[k] == j;
-        }
-        return ex;
-    };
     auto put = [&](int k, int j) {
-        if (!WIDE && k < NL_STAGE) stage[k][tid] = j;
+        if (k < NL_STAGE) stage[k][tid] = j;
         else if (k < DB_NLCAP) NL.nl[k * n + i] = j;
     };
     int cnt = 0;
     const Box& X = box_of<BATCH>(P, meta_word(xi));
-    if (WIDE) {
-        auto visit = [&](int j, int) {
-            if (excluded(j)) return;
+    // Every candidate within the cutoff is kept first, in the LDS rows, and the
+    // exclusions are applied afterwards, compacting in place in scan order.  The
+    // scan writes every candidate into the row of the next kept entry (a candidate
+    // not kept is overwritten by the next one kept; past the LDS rows the extra row
+    // takes them all) and advances the count by the test, with no branch per
+    // candidate; tested inside the scan, the exclusion test and the store ran for
+    // every candidate some lane of the wave kept, which is nearly every candidate.
+    // A bead with more kept candidates than the LDS rows hold, or a grid of fewer
+    // than three cells per edge, is scanned with the test inside.
+    int raw = 0;
+    if (X.noff == 3) {
+        scan_cells_all(X, cstart, xs, i, xi, X.pf_list2, [&](int w, bool hit) {
+            stage[min(raw, NL_STAGE)][tid] = w;   // the word; its slot is taken below
+            raw += hit ? 1 : 0;
+        });
+    } else {
+        raw = NL_STAGE + 1;
+    }
+    if (raw <= NL_STAGE) {
+        for (int k = 0; k < raw; ++k) {
+            const int j = xs_slot(stage[k][tid]);
+            if (E.has(j)) continue;
+            stage[cnt][tid] = j;
+            ++cnt;
+        }
+    } else {
+        scan_cells(X, cstart, xs, i, xi, X.pf_list2, [&](int j, int) {
+            if (E.has(j)) return;
             put(cnt, j);
             ++cnt;
-        };
-        scan_cells_wide(X, cstart, xs, i, xi, (float)((cut + X.pf_slack) * (cut + X.pf_slack) * 1.0001), visit);
-    } else {
-        // Every candidate within the cutoff is kept first, in the LDS rows, and the
-        // exclusions are applied afterwards, compacting in place in scan order.
-        // The scan writes every candidate into the row of the next kept entry (a
-        // candidate not kept is overwritten by the next one kept; past the LDS rows
-        // the extra row takes them all) and advances the count by the test, with no
-        // branch per candidate; tested inside the scan, the exclusion test and the
-        // store ran for every candidate some lane of the wave kept, which is nearly
-        // every candidate.
-        // A bead with more kept candidates than the LDS rows hold, or a grid of
-        // fewer than three cells per edge, is scanned with the test inside.
-        int raw = 0;
-        if (X.noff == 3) {
-            scan_cells_all(X, cstart, xs, i, xi, X.pf_list2, [&](int w, bool hit) {
-                stage[min(raw, NL_STAGE)][tid] = w;   // the word; its slot is taken below
-                raw += hit ? 1 : 0;
-            });
-        } else {
-            raw = NL_STAGE + 1;
-        }
-        if (raw <= NL_STAGE) {
-            for (int k = 0; k < raw; ++k) {
-                const int j = xs_slot(stage[k][tid]);
-                if (excluded(j)) continue;
-                stage[cnt][tid] = j;
-                ++cnt;
-            }
-        } else {
-            scan_cells(X, cstart, xs, i, xi, X.pf_list2, [&](int j, int) {
-                if (excluded(j)) return;
-                put(cnt, j);
-                ++cnt;
-            });
-        }
-        const int ns = min(cnt, NL_STAGE);
-        for (int k = 0; k < ns; ++k) NL.nl[k * n + i] = stage[k][tid];
+        });
     }
+    const int ns = min(cnt, NL_STAGE);
+    for (int k = 0; k < ns; ++k) NL.nl[k * n + i] = stage[k][tid];
     if (cnt > DB_NLCAP) {
         atomicOr(err, ERR_NLIST);
         cnt = DB_NLCAP;
     }
     NL.cnt[i] = (uint8_t)cnt;
+}
+
+// The list of one bead whose exclusions a sweep changed, redone with cutoff cut
+// (beyond the list cutoff by the displacement margin; the 5 x 5 x 5 stencil
+// reaches it) by LANES threads that share its rows (row r to thread r mod LANES).
+// A first pass counts each thread's kept candidates, a shuffle within the group
+// gives each thread its offset, and a second pass writes the entries: thread by
+// thread in lane order, each in its rows' scan order.
+template <bool BATCH, int LANES>
+__device__ __forceinline__ void patch_one(const Params& P, const Bank& B, const int* __restrict__ cstart,
+                                          const float4* __restrict__ xs, const NList& NL, int* __restrict__ err,
+                                          int i, int lane, double cut) {
+    const int n = P.n;
+    const double4 xi = B.x[i];
+    ExclSet E;
+    gather_excl(P, B, n, i, E);
+    const Box& X = box_of<BATCH>(P, meta_word(xi));
+    const float cut2 = (float)((cut + X.pf_slack) * (cut + X.pf_slack) * 1.0001);
+    int c = 0;
+    scan_cells_wide<LANES>(X, cstart, xs, i, xi, cut2, [&](int j, int) { c += E.has(j) ? 0 : 1; }, lane);
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) {
+        const int t = __shfl_up(incl, o, LANES);
+        if (lane >= o) incl += t;
+    }
+    int tot = __shfl(incl, LANES - 1, LANES);
+    int k = incl - c;
+    scan_cells_wide<LANES>(X, cstart, xs, i, xi, cut2, [&](int j, int) {
+        if (E.has(j)) return;
+        if (k < DB_NLCAP) NL.nl[k * n + i] = j;
+        ++k;
+    }, lane);
+    if (lane == 0) {
+        if (tot > DB_NLCAP) {
+            atomicOr(err, ERR_NLIST);
+            tot = DB_NLCAP;
+        }
+        NL.cnt[i] = (uint8_t)tot;
+    }
+}
+
+template <bool BATCH, int LANES>
+__device__ __forceinline__ void patch_all(const Params& P, const Bank& B, const int* __restrict__ cstart,
+                                          const float4* __restrict__ xs, const NList& NL, int* __restrict__ err,
+                                          const int* __restrict__ list, int nl, double cut) {
+    static_assert(64 % LANES == 0 && DB_BLOCK % 64 == 0, "groups lie within a wavefront");
+    const int ntile = (int)(((long long)nl * LANES + DB_BLOCK - 1) / DB_BLOCK);
+    for (int tb = blockIdx.x; tb < ntile; tb += gridDim.x) {
+        const long long pos = (long long)xcd_tile(tb, ntile) * DB_BLOCK + threadIdx.x;
+        const int t = (int)(pos / LANES);
+        const int lane = (int)(pos % LANES);
+        // the lanes of a group share t: they take this branch together
+        if (t < nl) patch_one<BATCH, LANES>(P, B, cstart, xs, NL, err, list[t], lane, cut);
+    }
+}
+
+// The beads listed in list (count at list_n): after a sweep few beads are listed,
+// and one thread each ran for as long as the slowest bead's chain of memory
+// latencies, so a short list takes eight threads per bead.
+template <bool BATCH>
+__global__ __launch_bounds__(DB_BLOCK) void k_patch_nlist(const Params* __restrict__ Pp, Bank B,
+                                                          const int* __restrict__ cstart,
+                                                          const float4* __restrict__ xs, NList NL,
+                                                          int* __restrict__ err, const int* __restrict__ list,
+                                                          const int* __restrict__ list_n, double cut) {
+    const Params& P = *Pp;
+    const int nl = *list_n;
+    if (nl >= (1 << 16)) patch_all<BATCH, 1>(P, B, cstart, xs, NL, err, list, nl, cut);
+    else patch_all<BATCH, 8>(P, B, cstart, xs, NL, err, list, nl, cut);
 }
 
 // pair forces from the Verlet list (exclusions were applied when it was built).
@@ -2050,13 +2106,11 @@ void launch_build_nlist(db_ctx* c) {
     launch_halo(c);
     double4* xref = c->hp.have_pair && c->hp.pair_style == PAIR_DPD ? c->xref : nullptr;
     if (c->nrep > 0)
-        hipLaunchKernelGGL((k_build_nlist<true, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
-                           nullptr, 0.0);
+        hipLaunchKernelGGL((k_build_nlist<true>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref);
     else
-        hipLaunchKernelGGL((k_build_nlist<false, false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
-                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref, nullptr,
-                           nullptr, 0.0);
+        hipLaunchKernelGGL((k_build_nlist<false>), dim3(grid_for(c->n)), dim3(DB_BLOCK), 0, c->stream, c->dp,
+                           c->bank[c->cur], c->cells.start, c->cells.xs, c->nlist, c->err_d, xref);
     launch_regions(c);
 }
 
@@ -2091,12 +2145,14 @@ void launch_patch_nlist(db_ctx* c, double cut) {
     hipLaunchKernelGGL(k_patch_flags, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
     launch_scan_total(c->sw.act, c->sw.aoff, c->n, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_patch_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
+    // the workgroups step over the tiles of the list (its length is on the device)
+    const unsigned gp = std::min(g, 2048u);
     if (c->nrep > 0)
-        hipLaunchKernelGGL((k_build_nlist<true, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
-                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut);
+        hipLaunchKernelGGL((k_patch_nlist<true>), dim3(gp), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
+                           c->cells.xs, c->nlist, c->err_d, c->sw.act, c->sw.aoff + c->n, cut);
     else
-        hipLaunchKernelGGL((k_build_nlist<false, true>), dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
-                           c->cells.xs, c->nlist, c->err_d, c->xref, c->sw.act, c->sw.aoff + c->n, cut);
+        hipLaunchKernelGGL((k_patch_nlist<false>), dim3(gp), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
+                           c->cells.xs, c->nlist, c->err_d, c->sw.act, c->sw.aoff + c->n, cut);
     launch_regions(c);
 }
 
