@@ -1003,11 +1003,11 @@ __device__ __forceinline__ void step_amplitudes(const Params& P, const int64_t* 
 // reads the neighbours' input velocities.  Each step reports the workgroup maxima
 // of |v|^2 (WCA) or, with DPD, of the squared displacement of the new position
 // from xref, the position at the last full Verlet-list build.
-// The FP32 WCA step of a single box is held to the registers of six waves per
-// SIMD (its LDS allows six), which the compiler otherwise gives up for a few
-// registers.
+// The FP32 WCA step is held to the registers of six waves per SIMD (its LDS
+// allows six), which the compiler otherwise gives up for a few registers (the
+// batched form took 94 and ran at five).
 template <typename R, int MODE, bool BATCH, int PAIR>
-__global__ __launch_bounds__(DB_BLOCK, (sizeof(R) == 4 && PAIR == PAIR_WCA && !BATCH && MODE == MODE_STEP) ? 6 : 1)
+__global__ __launch_bounds__(DB_BLOCK, (sizeof(R) == 4 && PAIR == PAIR_WCA && MODE == MODE_STEP) ? 6 : 1)
 void k_step(const Params* __restrict__ Pp, Bank B, NList NL, Halo H, double4* __restrict__ xout, double* vout,
             int64_t step, double pref, double dsig, unsigned int* __restrict__ vmax2_slot, double* __restrict__ fout,
             int* __restrict__ err, double4* __restrict__ xsave, double* __restrict__ vsave,
