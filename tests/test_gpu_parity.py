@@ -444,6 +444,25 @@ def test_bond_capacity_overflow_is_reported():
     assert e.value.code == pk.DB_ECAPACITY
 
 
+def test_list_overflow_is_reported():
+    """A clump at density about 17: the central beads have some 300 beads within the
+    list cutoff, more than the 128 a list holds.  The list build keeps the first 128,
+    flags the overflow, and the step reports DB_ECAPACITY (WCA at zero strength, so
+    nothing else goes wrong)."""
+    import paper_1108_4214_amd as pk
+    rng = np.random.default_rng(41)
+    n, L = 300, 20.0
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    x = 10.0 + d * 1.6 * rng.uniform(size=(n, 1)) ** (1.0 / 3.0)
+    s = synth.System(L=L, x=x, v=np.zeros_like(x), type=np.ones(n, dtype=np.int32),
+                     reactive=np.zeros(n, dtype=np.uint8), bonds=np.zeros((0, 4), dtype=np.int32))
+    with pytest.raises(pk.DynBondError) as e:
+        g = pk.System(s.n, s.L, 3).configure(s, synth.ForceField(eps=0.0), synth.RuleSet(every=0))
+        g.step(1)
+    assert e.value.code == pk.DB_ECAPACITY
+
+
 def test_invalid_arguments_rejected():
     import paper_1108_4214_amd as pk
     g = pk.System(4, 10.0, 1)
