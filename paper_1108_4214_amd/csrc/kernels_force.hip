@@ -423,9 +423,11 @@ __device__ __forceinline__ void patch_all(const Params& P, const Bank& B, const 
     }
 }
 
-// The beads listed in list (count at list_n): after a sweep few beads are listed,
-// and one thread each ran for as long as the slowest bead's chain of memory
-// latencies, so a short list takes eight threads per bead.
+// The beads listed in list (count at list_n).  After a sweep few beads are
+// listed; with one thread each the pass would last as long as the slowest bead's
+// chain of memory latencies, so a short list takes eight threads per bead, and a
+// list of 2^16 beads or more, which fills the GPU, one.  Both passes of a thread
+// run the same scan on the same data, so they keep the same candidates.
 template <bool BATCH>
 __global__ __launch_bounds__(DB_BLOCK) void k_patch_nlist(const Params* __restrict__ Pp, Bank B,
                                                           const int* __restrict__ cstart,
