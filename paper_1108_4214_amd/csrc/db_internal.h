@@ -141,10 +141,10 @@ struct SweepBuf {
     uint8_t* conv;    // bead takes part in an accepted conversion
     int* newp;        // partner slot of this bead's new (created or converted) bond, or -1
     unsigned long long* stats;   // [8] counters of the sweep
-    int* aoff;        // [n + 1] exclusive prefix sums of the 0/1 flags of the beads that may
-                      // nominate a creation partner, aoff[n] = their number (after the sweep:
-                      // the same for the beads whose Verlet list must be redone)
-    int* act;         // [n] the flags, then those beads in slot order
+    int* aoff;        // [n + 1] the beads flagged in act, in slot order, aoff[n] = their number
+                      // (also exclusive prefix sums of the bonded flags while the slots are reordered)
+    int* act;         // [n] 0/1 flags: the beads that may nominate a creation partner (after
+                      // the sweep: the beads whose Verlet list must be redone)
     uint8_t* chg;     // the sweep created or removed (not converted) a bond of the bead
     uint8_t* tchg;    // the sweep changed the bead's own bond, angle or dihedral table
     uint8_t* npurge;  // the bead lies within two bonds (old tables) of a bond the sweep removes
@@ -328,6 +328,7 @@ bool tiles_enabled(const db_ctx* c);                 // the step kernel runs on 
 void launch_exclusive_scan(int* data, int count, int* total_out, int* blocksum, hipStream_t s);
 // out[0..count) = exclusive prefix sums of in (in != out), out[count] = the total
 void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStream_t s);
+void launch_compact(const int* flags, int count, int* list, int* total, int* blocksum, hipStream_t s);
 
 // kernels_force.hip
 void launch_halo(db_ctx* c);                         // bonded halo, if slots or tables changed

@@ -108,6 +108,21 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
+// this thread's share of the sum of the tile sums tsum[0..b): the threads of a
+// workgroup take every DB_BLOCK-th one, four at a time
+__device__ __forceinline__ int thread_share_before(const int* __restrict__ tsum, int b, int tid) {
+    int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    int k = tid;
+    for (; k + 3 * DB_BLOCK < b; k += 4 * DB_BLOCK) {
+        p0 += tsum[k];
+        p1 += tsum[k + DB_BLOCK];
+        p2 += tsum[k + 2 * DB_BLOCK];
+        p3 += tsum[k + 3 * DB_BLOCK];
+    }
+    for (; k < b; k += DB_BLOCK) p0 += tsum[k];
+    return p0 + ((p1 + p2) + p3);
+}
+
 // tsum[b] = sum of tile b's items
 __global__ __launch_bounds__(DB_BLOCK) void k_scan_tile_sums(const int* __restrict__ in, int count,
                                                              int* __restrict__ tsum) {
@@ -135,16 +150,7 @@ __global__ __launch_bounds__(DB_BLOCK) void k_scan_apply(const int* in, int* out
                                                          const int* __restrict__ tsum, int* __restrict__ total) {
     __shared__ int wpre[DB_BLOCK / 64], wtot[DB_BLOCK / 64];
     const int b = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    int pre = 0, pre1 = 0, pre2 = 0, pre3 = 0;
-    int k = tid;
-    for (; k + 3 * DB_BLOCK < b; k += 4 * DB_BLOCK) {
-        pre += tsum[k];
-        pre1 += tsum[k + DB_BLOCK];
-        pre2 += tsum[k + 2 * DB_BLOCK];
-        pre3 += tsum[k + 3 * DB_BLOCK];
-    }
-    for (; k < b; k += DB_BLOCK) pre += tsum[k];
-    pre += (pre1 + pre2) + pre3;
+    int pre = thread_share_before(tsum, b, tid);
     const int base = b * SCAN2_TILE + tid * SCAN2_ITEMS;
     int v[SCAN2_ITEMS];
     load_items(in, base, count, v);
@@ -178,6 +184,37 @@ __global__ __launch_bounds__(DB_BLOCK) void k_scan_apply(const int* in, int* out
     if (total && b == (int)gridDim.x - 1 && tid == DB_BLOCK - 1) *total = run;
 }
 
+// The same pass for a stream compaction: flags in[0..count) (0 or 1) give each
+// flagged item its place, and the item's index is written there; the last tile
+// writes the number of flagged items to total.  list must not overlap in.
+__global__ __launch_bounds__(DB_BLOCK) void k_compact_apply(const int* __restrict__ in, int* __restrict__ list,
+                                                            int count, const int* __restrict__ tsum,
+                                                            int* __restrict__ total) {
+    __shared__ int wpre[DB_BLOCK / 64], wtot[DB_BLOCK / 64];
+    const int b = blockIdx.x, tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    int pre = thread_share_before(tsum, b, tid);
+    const int base = b * SCAN2_TILE + tid * SCAN2_ITEMS;
+    int v[SCAN2_ITEMS];
+    load_items(in, base, count, v);
+    int local = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN2_ITEMS; ++k) local += v[k];
+    pre = wave_sum(pre);
+    const int incl = wave_inclusive_scan(local);
+    if (lane == 0) wpre[wid] = pre;
+    if (lane == 63) wtot[wid] = incl;
+    __syncthreads();
+    int run = incl - local;
+#pragma unroll
+    for (int w = 0; w < DB_BLOCK / 64; ++w) run += wpre[w] + (w < wid ? wtot[w] : 0);
+#pragma unroll
+    for (int k = 0; k < SCAN2_ITEMS; ++k) {
+        if (v[k]) list[run] = base + k;   // items past count are zero
+        run += v[k];
+    }
+    if (b == (int)gridDim.x - 1 && tid == DB_BLOCK - 1) *total = run;
+}
+
 static int scan2_tiles(int count) { return (count + SCAN2_TILE - 1) / SCAN2_TILE; }
 
 // two-launch scan; tsum holds scan2_tiles(count) ints
@@ -195,6 +232,18 @@ void launch_scan_total(const int* in, int* out, int count, int* blocksum, hipStr
         return;
     }
     scan2(in, out, count, blocksum, s, out + count);
+}
+
+// list[0..m) = the indices k < count with flags[k] = 1, ascending, and *total = m
+// (two launches; blocksum holds at least ceil(count / 4096) ints)
+void launch_compact(const int* flags, int count, int* list, int* total, int* blocksum, hipStream_t s) {
+    if (count <= 0) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, total, 0, (size_t)1);
+        return;
+    }
+    const int tiles = scan2_tiles(count);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(tiles), dim3(DB_BLOCK), 0, s, flags, count, blocksum);
+    hipLaunchKernelGGL(k_compact_apply, dim3(tiles), dim3(DB_BLOCK), 0, s, flags, list, count, blocksum, total);
 }
 
 // data[0..count) -> exclusive prefix sums in place, and the total in data[count]

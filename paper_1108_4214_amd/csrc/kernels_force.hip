@@ -2131,13 +2131,6 @@ __global__ __launch_bounds__(DB_BLOCK) void k_patch_flags(const Params* __restri
     S.act[i] = d ? 1 : 0;
 }
 
-__global__ __launch_bounds__(DB_BLOCK) void k_patch_list(int n, SweepBuf S) {
-    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const int o = S.aoff[i];
-    if (S.aoff[i + 1] > o) S.act[o] = i;
-}
-
 void launch_patch_nlist(db_ctx* c, double cut) {
     if (c->n == 0) return;
     launch_halo(c);
@@ -2145,16 +2138,15 @@ void launch_patch_nlist(db_ctx* c, double cut) {
     const unsigned g = grid_for(c->n);
     Bank& B = c->bank[c->cur];
     hipLaunchKernelGGL(k_patch_flags, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
-    launch_scan_total(c->sw.act, c->sw.aoff, c->n, c->cells.blocksum, s);
-    hipLaunchKernelGGL(k_patch_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
+    launch_compact(c->sw.act, c->n, c->sw.aoff, c->sw.aoff + c->n, c->cells.blocksum, s);
     // the workgroups step over the tiles of the list (its length is on the device)
     const unsigned gp = std::min(g, 2048u);
     if (c->nrep > 0)
         hipLaunchKernelGGL((k_patch_nlist<true>), dim3(gp), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
-                           c->cells.xs, c->nlist, c->err_d, c->sw.act, c->sw.aoff + c->n, cut);
+                           c->cells.xs, c->nlist, c->err_d, c->sw.aoff, c->sw.aoff + c->n, cut);
     else
         hipLaunchKernelGGL((k_patch_nlist<false>), dim3(gp), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
-                           c->cells.xs, c->nlist, c->err_d, c->sw.act, c->sw.aoff + c->n, cut);
+                           c->cells.xs, c->nlist, c->err_d, c->sw.aoff, c->sw.aoff + c->n, cut);
     launch_regions(c);
 }
 

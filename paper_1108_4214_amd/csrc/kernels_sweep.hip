@@ -152,14 +152,9 @@ __device__ __forceinline__ bool create_admits(const Params& P, int ti, const Tab
 // The beads that may nominate a creation partner (reactive, of a type some
 // creation rule names, with room for one of its bond types under maxbond) are
 // flagged by the breakage nomination (in S.act), which reads every bead's table
-// anyway; the flags are scanned into S.aoff and the beads listed in slot order
-// (over the flags), so that the creation scan runs on full wavefronts.
-__global__ __launch_bounds__(DB_BLOCK) void k_create_list(int n, SweepBuf S) {
-    const int i = blockIdx.x * DB_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const int o = S.aoff[i];
-    if (S.aoff[i + 1] > o) S.act[o] = i;
-}
+// anyway; the flagged beads are listed in slot order in S.aoff (their count at
+// S.aoff[n]) by a stream compaction, so that the creation scan runs on full
+// wavefronts.
 
 // LANES threads per listed bead, each scanning a share of every cell run; the
 // group's nominee is the least (r^2, id) of its members' nominees, which is what
@@ -313,7 +308,7 @@ __device__ __forceinline__ void nominate_create_all(const Params& P, const Bank&
         const int t = (int)(pos / LANES);
         const int lane = (int)(pos % LANES);
         // the lanes of a group share t: they take this branch together
-        if (t < nl) nominate_create_one<BATCH, LANES>(P, P.n, B, cstart, xs, S, S.act[t], lane, queue);
+        if (t < nl) nominate_create_one<BATCH, LANES>(P, P.n, B, cstart, xs, S, S.aoff[t], lane, queue);
     }
 }
 
@@ -844,8 +839,7 @@ template <bool BATCH>
 static void sweep_kernels(db_ctx* c, const Bank& B, unsigned g, int64_t step) {
     hipStream_t s = c->stream;
     hipLaunchKernelGGL(k_nominate_break<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw);
-    launch_scan_total(c->sw.act, c->sw.aoff, c->n, c->cells.blocksum, s);
-    hipLaunchKernelGGL(k_create_list, dim3(g), dim3(DB_BLOCK), 0, s, c->n, c->sw);
+    launch_compact(c->sw.act, c->n, c->sw.aoff, c->sw.aoff + c->n, c->cells.blocksum, s);
     hipLaunchKernelGGL(k_nominate_create<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->cells.start,
                        c->cells.xs, c->sw);
     hipLaunchKernelGGL(k_resolve<BATCH>, dim3(g), dim3(DB_BLOCK), 0, s, c->dp, B, c->sw, step);
